@@ -1,0 +1,159 @@
+/*
+ * tc.h -- C-ABI of the MI355X (gfx950) bulk update of neighborhood-sampling
+ * triangle-count estimators.
+ *
+ * Method: Tangwongsan, Pavan, Tirthapura, "Parallel Triangle Counting in
+ * Massive Streaming Graphs".  An estimator is a tuple (f1, f2, f3, chi)
+ * satisfying the neighborhood sampling invariant (Sec. 3.1, Invariant 1);
+ * one call of tc_process_batch is one bulkUpdateAll (Sec. 4, Theorem 3):
+ * Step 1 level-1 reservoir (Sec. 4.2), Step 2 rank-based level-2 resample
+ * and chi update (Sec. 4.3), Step 3 closing-edge check (Sec. 4.4).  The
+ * estimate is Lemma 1's X = chi * |E| (when closed) averaged over the bank.
+ *
+ * Conventions shared by every entry point:
+ *   - A batch is `uint32_t edges[2*w]`: edge j is {edges[2j], edges[2j+1]},
+ *     arrival order = j.  Edges must come from a simple undirected graph:
+ *     each edge once in the whole stream, no self-loops.  A self-loop is
+ *     detected on the device and reported as TC_EBADEDGE by the next
+ *     synchronising call (the bank is then unspecified).  Repeated edges
+ *     are not detected; results stay deterministic.
+ *   - An edge is reported as canon(a,b) = ((uint64)min << 32) | max; the
+ *     empty edge is TC_EMPTY_EDGE.
+ *   - Random decisions come from a counter-based generator keyed by
+ *     (seed, estimator index within its bank, batch index of that bank,
+ *     purpose, attempt): the splitmix64 finalizer chained over the key and
+ *     Lemire's multiply-shift with rejection.  Results therefore depend on
+ *     how the stream is cut into batches, and on nothing else (no launch
+ *     shape, tile size or device count changes them).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Enqueueing calls return before the GPU work finishes; device buffers
+ *     passed to them must stay valid until the stream passes that point.
+ *   - Integer returns are TC_OK (0) or a negative TC_E* code; the text of
+ *     the last error is available from tc_last_error() (per thread).
+ *   - One object must not be used from two host threads, or enqueued on two
+ *     streams, at the same time.
+ */
+#ifndef TC_H
+#define TC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TC_OK 0
+#define TC_EINVAL (-1)    /* bad argument (null pointer, size out of range) */
+#define TC_EBADEDGE (-2)  /* a self-loop was found in a batch */
+#define TC_EOVERFLOW (-3) /* an adjacency count chi reached 2^31 */
+#define TC_ENOMEM (-4)    /* device or pinned host allocation failed */
+#define TC_EHIP (-5)      /* a HIP runtime call failed */
+
+#define TC_EMPTY_EDGE UINT64_MAX
+#define TC_MAX_BATCH (1u << 28) /* largest w accepted by one call */
+
+typedef struct tc_state tc_state; /* one bank of r estimators, one stream */
+typedef struct tc_multi tc_multi; /* many independent banks */
+
+/* ---- single bank (the plain method) ------------------------------------ */
+
+/* Allocate a bank of r >= 1 estimators on the current HIP device with every
+ * estimator empty (f1 = f2 = empty, chi = 0, not closed), |E| = 0 and batch
+ * index 0.  The library owns all device memory.  Returns NULL on r == 0 or
+ * allocation failure (see tc_last_error). */
+tc_state *tc_create(uint32_t r, uint64_t seed);
+
+/* Enqueue one bulk update (Sec. 4, bulkUpdateAll) of the bank with the batch
+ * `edges` (DEVICE pointer to uint32[2w], caller-owned, read-only) on
+ * `stream`; afterwards |E| += w and the batch index += 1.  w == 0 is a
+ * no-op that does not advance the batch index.  Returns TC_EINVAL for a
+ * NULL state, NULL edges with w > 0, or w > TC_MAX_BATCH; TC_ENOMEM if
+ * scratch for a larger batch cannot be allocated; earlier sticky device
+ * errors are returned here once known. */
+int tc_process_batch(tc_state *s, const uint32_t *edges, uint32_t w,
+                     void *stream);
+
+/* Pre-size the bank's step scratch for batches of up to max_w edges so that
+ * later tc_process_batch calls with w <= max_w allocate nothing (needed
+ * before capturing them into a HIP graph).  Blocking.  TC_ENOMEM on
+ * failure. */
+int tc_reserve(tc_state *s, uint32_t max_w);
+
+/* Block until the bank's last enqueued work is done, then return
+ * tau_hat = (|E| / r) * S with S = sum_i chi_i * [closed_i] (Lemma 1, mean
+ * aggregate).  NaN on error. */
+double tc_estimate(tc_state *s);
+
+/* Blocking; writes S (exact, 64-bit), |E| and tau_hat.  Any pointer may be
+ * NULL.  Returns TC_OK or a sticky device error. */
+int tc_estimate_ex(tc_state *s, uint64_t *S, uint64_t *m, double *tau);
+
+/* Blocking; copies the bank into caller-owned HOST arrays of length r:
+ * f1, f2 (canonical codes), chi and closed (0/1).  Any pointer may be NULL. */
+int tc_read_state(tc_state *s, uint64_t *r1, uint64_t *r2, uint32_t *c,
+                  uint8_t *closed);
+
+/* Blocking; waits for the bank's enqueued work and returns any device error. */
+int tc_sync(tc_state *s);
+
+/* Number of estimators, edges seen and batches consumed so far. */
+uint32_t tc_num_estimators(const tc_state *s);
+uint64_t tc_edges_seen(const tc_state *s);
+uint64_t tc_batches_seen(const tc_state *s);
+
+/* Wait for outstanding work, then free every resource.  NULL is a no-op. */
+void tc_destroy(tc_state *s);
+
+/* Text of the calling thread's last error ("" if none). */
+const char *tc_last_error(void);
+
+/* ---- many independent banks (batched and served forms) ----------------- */
+
+/* nbanks banks; bank b has r[b] >= 1 estimators and seed seeds[b].  Each
+ * bank behaves exactly as a tc_state fed the same batches. */
+tc_multi *tc_multi_create(uint32_t nbanks, const uint32_t *r,
+                          const uint64_t *seeds);
+
+/* Enqueue one step: chunk k (k < nchunks) is a batch of w[k] edges at DEVICE
+ * address edges[k] for bank bank_ids[k].  Bank ids must be distinct within
+ * a call (one batch per bank per step); banks not named are untouched.  All
+ * chunks advance in one set of kernel launches.  The three arrays are
+ * HOST arrays read before the call returns. */
+int tc_multi_process(tc_multi *s, uint32_t nchunks, const uint32_t *bank_ids,
+                     const uint32_t *const *edges, const uint32_t *w,
+                     void *stream);
+
+/* Pre-size the step scratch as a tc_multi_process call with these chunks
+ * would (edge pointers are not needed).  Blocking. */
+int tc_multi_reserve(tc_multi *s, uint32_t nchunks, const uint32_t *bank_ids,
+                     const uint32_t *w);
+
+/* Blocking; per-bank S, |E| and tau_hat into HOST arrays of length nbanks
+ * (any may be NULL). */
+int tc_multi_estimate(tc_multi *s, uint64_t *S, uint64_t *m, double *tau);
+
+/* Blocking; like tc_read_state for bank `bank`. */
+int tc_multi_read_state(tc_multi *s, uint32_t bank, uint64_t *r1, uint64_t *r2,
+                        uint32_t *c, uint8_t *closed);
+
+int tc_multi_sync(tc_multi *s);
+uint32_t tc_multi_num_banks(const tc_multi *s);
+void tc_multi_destroy(tc_multi *s);
+
+/* ---- diagnostics: per-kernel device time --------------------------------
+ * While enabled, every step records HIP events between its kernels on the
+ * step's own stream (a few microseconds of overhead per step).  Enabling or
+ * disabling resets the totals.  tc_kernel_times blocks, then writes the
+ * accumulated milliseconds of each of the tc_num_kernels() launches of a
+ * step (launch order; names from tc_kernel_name) into the HOST array `ms`
+ * and the number of timed steps into *steps. */
+int tc_set_kernel_timing(tc_state *s, int enable);
+int tc_kernel_times(tc_state *s, double *ms, uint64_t *steps);
+int tc_multi_set_kernel_timing(tc_multi *s, int enable);
+int tc_multi_kernel_times(tc_multi *s, double *ms, uint64_t *steps);
+int tc_num_kernels(void);
+const char *tc_kernel_name(int k);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,602 @@
+// Host side of libtc: bank storage, per-step scratch, the C-ABI.
+//
+// A tc_multi owns the estimator state of all its banks (structure of arrays
+// in HBM) and the scratch of one step; a tc_state is a tc_multi with one
+// bank.  Scratch grows to the largest step seen and is then reused, so a
+// steady stream of equal-sized batches allocates nothing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tc.h"
+#include "tc_internal.h"
+
+namespace tc {
+hipError_t launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev);
+hipError_t launch_sum(const uint32_t* cc, const uint64_t* bank_off,
+                      uint32_t nbanks, uint64_t total,
+                      unsigned long long* sums, hipStream_t st);
+hipError_t launch_fill64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
+hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+}  // namespace tc
+
+namespace {
+
+using namespace tc;
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+uint64_t host_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint32_t log2_ceil(uint64_t x) {
+  uint32_t b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+
+// directory slots for a chunk of w edges: at most 2w distinct vertices,
+// load <= 1/2 when hashed
+uint32_t dir_log2_for(uint32_t w) {
+  return std::max<uint32_t>(10, log2_ceil(4ull * w));
+}
+// query-table slots for a bank of r estimators: at most r queries
+uint32_t qt_log2_for(uint32_t r) {
+  return std::max<uint32_t>(10, log2_ceil(2ull * r));
+}
+
+template <class T>
+hipError_t dalloc(T** p, uint64_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+struct Engine {
+  int device = 0;
+  uint32_t nbanks = 0;
+  std::vector<uint32_t> r;
+  std::vector<uint64_t> seed, key0, m, batch, est_off;  // est_off: nbanks+1
+  uint64_t total = 0;
+
+  // bank state (all banks, contiguous)
+  uint64_t* R1 = nullptr;
+  uint64_t* R2 = nullptr;
+  uint32_t* CC = nullptr;
+  uint64_t* LINK = nullptr;
+  uint64_t* bank_off = nullptr;  // device copy of est_off
+  unsigned long long* sums = nullptr;
+  uint32_t* err = nullptr;
+  unsigned long long* h_sums = nullptr;  // pinned
+  uint32_t* h_err = nullptr;             // pinned
+
+  // step scratch
+  uint64_t cap_arcs = 0, cap_tiles = 0, cap_dir = 0, cap_qt = 0;
+  uint32_t cap_segs = 0;
+  uint64_t* arcs[2] = {nullptr, nullptr};
+  uint32_t* status[2] = {nullptr, nullptr};
+  uint32_t* tile_ctr = nullptr;
+  SegWork* work = nullptr;
+  DirSlot* dir = nullptr;
+  QSlot* qt = nullptr;
+  SegDesc* segs_dev = nullptr;
+
+  // pinned staging ring for multi-segment descriptors
+  static constexpr int kRing = 4;
+  SegDesc* stage[kRing] = {};
+  hipEvent_t stage_ev[kRing] = {};
+  bool stage_used[kRing] = {};
+  uint32_t stage_cap = 0;
+  int ring = 0;
+
+  uint32_t tag = 0;
+  hipStream_t last = nullptr;
+  int sticky = TC_OK;
+
+  // optional per-kernel timing: one set of kNumKernels+1 events per step
+  bool timing = false;
+  std::vector<hipEvent_t*> ev_pending, ev_free;
+  double kernel_ms[kNumKernels] = {};
+  uint64_t timed_steps = 0;
+
+  ~Engine() { release(); }
+
+  void release() {
+    if (last) (void)hipStreamSynchronize(last);
+    (void)hipDeviceSynchronize();
+    for (auto* v : {&ev_pending, &ev_free})
+      for (hipEvent_t* e : *v) {
+        for (int k = 0; k <= kNumKernels; ++k) (void)hipEventDestroy(e[k]);
+        delete[] e;
+      }
+    ev_pending.clear();
+    ev_free.clear();
+    dfree(R1), dfree(R2), dfree(CC), dfree(LINK), dfree(bank_off);
+    dfree(sums), dfree(err);
+    if (h_sums) (void)hipHostFree(h_sums);
+    if (h_err) (void)hipHostFree(h_err);
+    h_sums = nullptr, h_err = nullptr;
+    free_scratch();
+    for (int i = 0; i < kRing; ++i) {
+      if (stage[i]) (void)hipHostFree(stage[i]);
+      if (stage_ev[i]) (void)hipEventDestroy(stage_ev[i]);
+      stage[i] = nullptr, stage_ev[i] = nullptr;
+    }
+  }
+
+  void free_scratch() {
+    dfree(arcs[0]), dfree(arcs[1]), dfree(status[0]), dfree(status[1]);
+    dfree(tile_ctr), dfree(work), dfree(dir), dfree(qt), dfree(segs_dev);
+    cap_arcs = cap_tiles = cap_dir = cap_qt = 0;
+    cap_segs = 0;
+  }
+
+  int init(uint32_t n, const uint32_t* rr, const uint64_t* seeds) {
+    if (hipGetDevice(&device) != hipSuccess) return fail(TC_EHIP, "hipGetDevice failed");
+    nbanks = n;
+    r.assign(rr, rr + n);
+    seed.assign(seeds, seeds + n);
+    key0.resize(n);
+    m.assign(n, 0);
+    batch.assign(n, 0);
+    est_off.resize(n + 1);
+    est_off[0] = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+      if (r[b] == 0) return fail(TC_EINVAL, "every bank needs r >= 1");
+      key0[b] = host_mix64(seed[b] ^ kGolden);
+      est_off[b + 1] = est_off[b] + r[b];
+    }
+    total = est_off[n];
+    if (total >= 0x7FFFFFFFull)
+      return fail(TC_EINVAL, "too many estimators in one object (max 2^31-2)");
+    if (dalloc(&R1, total) || dalloc(&R2, total) || dalloc(&CC, total) ||
+        dalloc(&LINK, total) || dalloc(&bank_off, n + 1) ||
+        dalloc(&sums, n) || dalloc(&err, 1))
+      return fail(TC_ENOMEM, "device allocation of the estimator banks failed");
+    if (hipHostMalloc(reinterpret_cast<void**>(&h_sums), sizeof(uint64_t) * n) ||
+        hipHostMalloc(reinterpret_cast<void**>(&h_err), sizeof(uint32_t)))
+      return fail(TC_ENOMEM, "pinned host allocation failed");
+    if (launch_fill64(R1, total, kEmpty, nullptr) ||
+        launch_fill64(R2, total, kEmpty, nullptr) ||
+        launch_fill32(CC, total, 0, nullptr) ||
+        launch_fill32(err, 1, 0, nullptr) ||
+        hipMemcpy(bank_off, est_off.data(), sizeof(uint64_t) * (n + 1),
+                  hipMemcpyHostToDevice) ||
+        hipDeviceSynchronize())
+      return fail(TC_EHIP, "initialising the estimator banks failed");
+    return TC_OK;
+  }
+
+  int ensure_scratch(uint64_t arcs_n, uint64_t tiles, uint64_t dir_n,
+                     uint64_t qt_n, uint32_t nseg, hipStream_t st) {
+    if (arcs_n <= cap_arcs && tiles <= cap_tiles && dir_n <= cap_dir &&
+        qt_n <= cap_qt && nseg <= cap_segs)
+      return TC_OK;
+    if (last) (void)hipStreamSynchronize(last);
+    (void)hipStreamSynchronize(st);
+    free_scratch();
+    cap_arcs = std::max(arcs_n, cap_arcs);
+    cap_tiles = std::max(tiles, cap_tiles);
+    cap_dir = std::max(dir_n, cap_dir);
+    cap_qt = std::max(qt_n, cap_qt);
+    cap_segs = std::max(nseg, cap_segs);
+    if (dalloc(&arcs[0], cap_arcs) || dalloc(&arcs[1], cap_arcs) ||
+        dalloc(&status[0], cap_tiles * kDigits) ||
+        dalloc(&status[1], cap_tiles * kDigits) ||
+        dalloc(&tile_ctr, kPasses) || dalloc(&work, cap_segs) ||
+        dalloc(&dir, cap_dir) || dalloc(&qt, cap_qt) ||
+        dalloc(&segs_dev, cap_segs)) {
+      free_scratch();
+      return fail(TC_ENOMEM, "device allocation of step scratch failed");
+    }
+    // zero = "no tag" for the tables, cleared look-back and work areas
+    if (hipMemsetAsync(status[0], 0, cap_tiles * kDigits * 4, st) ||
+        hipMemsetAsync(status[1], 0, cap_tiles * kDigits * 4, st) ||
+        hipMemsetAsync(tile_ctr, 0, kPasses * 4, st) ||
+        hipMemsetAsync(work, 0, sizeof(SegWork) * cap_segs, st) ||
+        hipMemsetAsync(dir, 0, sizeof(DirSlot) * cap_dir, st) ||
+        hipMemsetAsync(qt, 0, sizeof(QSlot) * cap_qt, st) ||
+        hipStreamSynchronize(st))
+      return fail(TC_EHIP, "clearing step scratch failed");
+    return TC_OK;
+  }
+
+  int stage_descs(const std::vector<SegDesc>& segs, hipStream_t st) {
+    const uint32_t n = (uint32_t)segs.size();
+    if (n > stage_cap) {
+      for (int i = 0; i < kRing; ++i) {
+        if (stage_used[i]) (void)hipEventSynchronize(stage_ev[i]);
+        if (stage[i]) (void)hipHostFree(stage[i]);
+        stage[i] = nullptr;
+        stage_used[i] = false;
+        if (hipHostMalloc(reinterpret_cast<void**>(&stage[i]), sizeof(SegDesc) * n))
+          return fail(TC_ENOMEM, "pinned descriptor staging failed");
+        if (!stage_ev[i] && hipEventCreateWithFlags(&stage_ev[i], hipEventDisableTiming))
+          return fail(TC_EHIP, "hipEventCreate failed");
+      }
+      stage_cap = n;
+    }
+    const int k = ring;
+    ring = (ring + 1) % kRing;
+    if (stage_used[k]) (void)hipEventSynchronize(stage_ev[k]);
+    std::memcpy(stage[k], segs.data(), sizeof(SegDesc) * n);
+    if (hipMemcpyAsync(segs_dev, stage[k], sizeof(SegDesc) * n,
+                       hipMemcpyHostToDevice, st) ||
+        hipEventRecord(stage_ev[k], st))
+      return fail(TC_EHIP, "descriptor upload failed");
+    stage_used[k] = true;
+    return TC_OK;
+  }
+
+  // reserve == true: size the scratch for this step without launching it
+  int step(uint32_t nchunks, const uint32_t* ids, const uint32_t* const* edges,
+           const uint32_t* w, hipStream_t st, bool reserve = false) {
+    if (sticky != TC_OK) return fail(sticky, "an earlier batch failed on the device");
+    std::vector<SegDesc> segs;
+    segs.reserve(nchunks);
+    std::vector<char> seen(nbanks, 0);
+    uint64_t arcs_n = 0, tiles = 0, dir_n = 0, qt_n = 0, nest = 0;
+    for (uint32_t k = 0; k < nchunks; ++k) {
+      const uint32_t b = ids[k];
+      if (b >= nbanks) return fail(TC_EINVAL, "bank id out of range");
+      if (seen[b]) return fail(TC_EINVAL, "a bank appears twice in one step");
+      seen[b] = 1;
+      if (w[k] > TC_MAX_BATCH) return fail(TC_EINVAL, "batch larger than TC_MAX_BATCH");
+      if (w[k] == 0) continue;
+      if (!reserve && !edges[k]) return fail(TC_EINVAL, "null edge pointer with w > 0");
+      SegDesc d{};
+      d.edges = reserve ? nullptr : edges[k];
+      d.m = m[b];
+      d.batch = batch[b];
+      d.key0 = key0[b];
+      d.est_off = est_off[b];
+      d.gest_off = nest;
+      d.arc_off = arcs_n;
+      d.dir_off = dir_n;
+      d.qt_off = qt_n;
+      d.w = w[k];
+      d.r = r[b];
+      d.tile_off = (uint32_t)tiles;
+      d.ntiles = (uint32_t)((2ull * w[k] + kTile - 1) / kTile);
+      d.dir_log2 = dir_log2_for(w[k]);
+      d.qt_log2 = qt_log2_for(r[b]);
+      arcs_n += 2ull * w[k];
+      tiles += d.ntiles;
+      dir_n += 1ull << d.dir_log2;
+      qt_n += 1ull << d.qt_log2;
+      nest += r[b];
+      segs.push_back(d);
+    }
+    if (segs.empty()) return TC_OK;
+    if (tiles >= 0x7FFFFFFFull) return fail(TC_EINVAL, "step too large");
+    int rc = ensure_scratch(arcs_n, tiles, dir_n, qt_n, (uint32_t)segs.size(), st);
+    if (rc || reserve) return rc;
+    if (tag >= kTagMax) {
+      // tags wrapped: forget every table entry
+      if (hipMemsetAsync(dir, 0, sizeof(DirSlot) * cap_dir, st))
+        return fail(TC_EHIP, "table reset failed");
+      tag = 0;
+    }
+    ++tag;
+    StepArgs a{};
+    a.nseg = (uint32_t)segs.size();
+    a.segs = segs_dev;
+    a.seg0 = segs[0];
+    a.ntiles = (uint32_t)tiles;
+    a.nest = nest;
+    a.tag = tag;
+    a.r1 = R1, a.r2 = R2, a.cc = CC, a.link = LINK;
+    a.work = work;
+    a.arcs[0] = arcs[0], a.arcs[1] = arcs[1];
+    a.status[0] = status[0], a.status[1] = status[1];
+    a.tile_ctr = tile_ctr;
+    a.dir = dir;
+    a.qt = qt;
+    a.qt_slots = qt_n;
+    a.err = err;
+    if (a.nseg > 1) {
+      rc = stage_descs(segs, st);
+      if (rc) return rc;
+    }
+    hipEvent_t* ev = nullptr;
+    if (timing) {
+      if (!ev_free.empty()) {
+        ev = ev_free.back();
+        ev_free.pop_back();
+      } else {
+        ev = new hipEvent_t[kNumKernels + 1];
+        for (int k = 0; k <= kNumKernels; ++k)
+          if (hipEventCreate(&ev[k])) return fail(TC_EHIP, "hipEventCreate failed");
+      }
+      ev_pending.push_back(ev);
+    }
+    if (launch_step(a, st, ev) != hipSuccess) return fail(TC_EHIP, "kernel launch failed");
+    for (uint32_t k = 0; k < nchunks; ++k) {
+      if (w[k] == 0) continue;
+      m[ids[k]] += w[k];
+      batch[ids[k]] += 1;
+    }
+    last = st;
+    return TC_OK;
+  }
+
+  int sync() {
+    if (last && hipStreamSynchronize(last) != hipSuccess)
+      return fail(TC_EHIP, "hipStreamSynchronize failed");
+    if (hipMemcpy(h_err, err, 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(TC_EHIP, "reading the device error word failed");
+    const uint32_t e = *h_err;
+    if (e & kErrSelfLoop) sticky = TC_EBADEDGE;
+    else if (e & kErrOverflow) sticky = TC_EOVERFLOW;
+    else if (e & (kErrProbe | kErrStall)) sticky = TC_EHIP;
+    if (sticky == TC_EBADEDGE) return fail(sticky, "a batch contained a self-loop");
+    if (sticky == TC_EOVERFLOW) return fail(sticky, "an adjacency count reached 2^31");
+    if (sticky != TC_OK) return fail(sticky, "a device table or wait ran past its bound");
+    return TC_OK;
+  }
+
+  // accumulate the elapsed time of every pending timed step
+  int collect_times() {
+    for (hipEvent_t* e : ev_pending) {
+      if (hipEventSynchronize(e[kNumKernels])) return fail(TC_EHIP, "event sync failed");
+      for (int k = 0; k < kNumKernels; ++k) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, e[k], e[k + 1])) return fail(TC_EHIP, "event timing failed");
+        kernel_ms[k] += ms;
+      }
+      ++timed_steps;
+      ev_free.push_back(e);
+    }
+    ev_pending.clear();
+    return TC_OK;
+  }
+
+  int sums_all(uint64_t* S) {
+    int rc = sync();
+    if (rc) return rc;
+    hipStream_t st = last;
+    if (launch_sum(CC, bank_off, nbanks, total, sums, st) != hipSuccess ||
+        hipMemcpyAsync(h_sums, sums, sizeof(uint64_t) * nbanks,
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(TC_EHIP, "estimate reduction failed");
+    for (uint32_t b = 0; b < nbanks; ++b) S[b] = h_sums[b];
+    return TC_OK;
+  }
+
+  int read_bank(uint32_t b, uint64_t* r1, uint64_t* r2, uint32_t* c,
+                uint8_t* closed) {
+    int rc = sync();
+    if (rc) return rc;
+    const uint64_t off = est_off[b], n = r[b];
+    if (r1 && hipMemcpy(r1, R1 + off, n * 8, hipMemcpyDeviceToHost))
+      return fail(TC_EHIP, "state copy failed");
+    if (r2 && hipMemcpy(r2, R2 + off, n * 8, hipMemcpyDeviceToHost))
+      return fail(TC_EHIP, "state copy failed");
+    if (c || closed) {
+      std::vector<uint32_t> cc(n);
+      if (hipMemcpy(cc.data(), CC + off, n * 4, hipMemcpyDeviceToHost))
+        return fail(TC_EHIP, "state copy failed");
+      for (uint64_t i = 0; i < n; ++i) {
+        if (c) c[i] = cc[i] & kChiMax;
+        if (closed) closed[i] = (cc[i] & kClosed) ? 1 : 0;
+      }
+    }
+    return TC_OK;
+  }
+};
+
+}  // namespace
+
+struct tc_multi {
+  Engine e;
+};
+struct tc_state {
+  Engine e;
+};
+
+extern "C" {
+
+const char* tc_last_error(void) { return g_err.c_str(); }
+
+// ---- single bank ----------------------------------------------------------
+tc_state* tc_create(uint32_t r, uint64_t seed) {
+  if (r == 0) {
+    fail(TC_EINVAL, "r must be >= 1");
+    return nullptr;
+  }
+  tc_state* s = new (std::nothrow) tc_state;
+  if (!s) {
+    fail(TC_ENOMEM, "host allocation failed");
+    return nullptr;
+  }
+  if (s->e.init(1, &r, &seed) != TC_OK) {
+    delete s;
+    return nullptr;
+  }
+  return s;
+}
+
+int tc_process_batch(tc_state* s, const uint32_t* edges, uint32_t w,
+                     void* stream) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  const uint32_t id = 0;
+  return s->e.step(1, &id, &edges, &w, static_cast<hipStream_t>(stream));
+}
+
+int tc_reserve(tc_state* s, uint32_t max_w) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  const uint32_t id = 0;
+  const uint32_t* none = nullptr;
+  return s->e.step(1, &id, &none, &max_w, nullptr, true);
+}
+
+int tc_estimate_ex(tc_state* s, uint64_t* S, uint64_t* m, double* tau) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  uint64_t sum = 0;
+  int rc = s->e.sums_all(&sum);
+  if (rc) return rc;
+  if (S) *S = sum;
+  if (m) *m = s->e.m[0];
+  if (tau) *tau = (double)sum * (double)s->e.m[0] / (double)s->e.r[0];
+  return TC_OK;
+}
+
+double tc_estimate(tc_state* s) {
+  double tau = NAN;
+  if (tc_estimate_ex(s, nullptr, nullptr, &tau) != TC_OK) return NAN;
+  return tau;
+}
+
+int tc_read_state(tc_state* s, uint64_t* r1, uint64_t* r2, uint32_t* c,
+                  uint8_t* closed) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  return s->e.read_bank(0, r1, r2, c, closed);
+}
+
+int tc_sync(tc_state* s) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  return s->e.sync();
+}
+
+static const char* const kKernelNames[kNumKernels] = {
+    "k_hist", "k_pass<0>", "k_pass<1>", "k_pass<2>",
+    "k_pass<3>", "k_dir", "k_est", "k_probe"};
+
+static int set_timing(Engine& e, int enable) {
+  int rc = e.collect_times();
+  if (rc) return rc;
+  e.timing = enable != 0;
+  for (double& v : e.kernel_ms) v = 0;
+  e.timed_steps = 0;
+  return TC_OK;
+}
+
+static int read_times(Engine& e, double* ms, uint64_t* steps) {
+  int rc = e.collect_times();
+  if (rc) return rc;
+  for (int k = 0; k < kNumKernels; ++k)
+    if (ms) ms[k] = e.kernel_ms[k];
+  if (steps) *steps = e.timed_steps;
+  return TC_OK;
+}
+
+int tc_set_kernel_timing(tc_state* s, int enable) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  return set_timing(s->e, enable);
+}
+
+int tc_kernel_times(tc_state* s, double* ms, uint64_t* steps) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  return read_times(s->e, ms, steps);
+}
+
+int tc_multi_set_kernel_timing(tc_multi* s, int enable) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  return set_timing(s->e, enable);
+}
+
+int tc_multi_kernel_times(tc_multi* s, double* ms, uint64_t* steps) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  return read_times(s->e, ms, steps);
+}
+
+int tc_num_kernels(void) { return kNumKernels; }
+
+const char* tc_kernel_name(int k) {
+  return (k >= 0 && k < kNumKernels) ? kKernelNames[k] : "";
+}
+
+uint32_t tc_num_estimators(const tc_state* s) { return s ? s->e.r[0] : 0; }
+uint64_t tc_edges_seen(const tc_state* s) { return s ? s->e.m[0] : 0; }
+uint64_t tc_batches_seen(const tc_state* s) { return s ? s->e.batch[0] : 0; }
+
+void tc_destroy(tc_state* s) { delete s; }
+
+// ---- many banks -----------------------------------------------------------
+tc_multi* tc_multi_create(uint32_t nbanks, const uint32_t* r,
+                          const uint64_t* seeds) {
+  if (nbanks == 0 || !r || !seeds) {
+    fail(TC_EINVAL, "need nbanks >= 1 and non-null r, seeds");
+    return nullptr;
+  }
+  tc_multi* s = new (std::nothrow) tc_multi;
+  if (!s) {
+    fail(TC_ENOMEM, "host allocation failed");
+    return nullptr;
+  }
+  if (s->e.init(nbanks, r, seeds) != TC_OK) {
+    delete s;
+    return nullptr;
+  }
+  return s;
+}
+
+int tc_multi_process(tc_multi* s, uint32_t nchunks, const uint32_t* bank_ids,
+                     const uint32_t* const* edges, const uint32_t* w,
+                     void* stream) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  if (nchunks == 0) return TC_OK;
+  if (!bank_ids || !edges || !w) return fail(TC_EINVAL, "null chunk arrays");
+  return s->e.step(nchunks, bank_ids, edges, w, static_cast<hipStream_t>(stream));
+}
+
+int tc_multi_reserve(tc_multi* s, uint32_t nchunks, const uint32_t* bank_ids,
+                     const uint32_t* w) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  if (nchunks == 0) return TC_OK;
+  if (!bank_ids || !w) return fail(TC_EINVAL, "null chunk arrays");
+  std::vector<const uint32_t*> none(nchunks, nullptr);
+  return s->e.step(nchunks, bank_ids, none.data(), w, nullptr, true);
+}
+
+int tc_multi_estimate(tc_multi* s, uint64_t* S, uint64_t* m, double* tau) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  std::vector<uint64_t> sums(s->e.nbanks);
+  int rc = s->e.sums_all(sums.data());
+  if (rc) return rc;
+  for (uint32_t b = 0; b < s->e.nbanks; ++b) {
+    if (S) S[b] = sums[b];
+    if (m) m[b] = s->e.m[b];
+    if (tau) tau[b] = (double)sums[b] * (double)s->e.m[b] / (double)s->e.r[b];
+  }
+  return TC_OK;
+}
+
+int tc_multi_read_state(tc_multi* s, uint32_t bank, uint64_t* r1, uint64_t* r2,
+                        uint32_t* c, uint8_t* closed) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  if (bank >= s->e.nbanks) return fail(TC_EINVAL, "bank id out of range");
+  return s->e.read_bank(bank, r1, r2, c, closed);
+}
+
+int tc_multi_sync(tc_multi* s) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  return s->e.sync();
+}
+
+uint32_t tc_multi_num_banks(const tc_multi* s) { return s ? s->e.nbanks : 0; }
+
+void tc_multi_destroy(tc_multi* s) { delete s; }
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal layout shared by the kernels and the host side of libtc.
+//
+// One "step" advances one or more banks by one batch each.  Every chunk of a
+// step is a segment; all per-step scratch is carved into per-segment regions
+// so one set of launches serves the plain (one segment) and the batched
+// (many segments) forms.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tc {
+
+constexpr uint64_t kEmpty = ~0ull;      // empty edge code
+constexpr uint32_t kNone = 0xFFFFFFFFu;  // no index
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+// radix sort of the 2w arcs: 8-bit digits of the 32-bit vertex id
+constexpr int kBlock = 256;              // threads per block
+constexpr int kWaves = kBlock / 64;      // wave64
+constexpr int kItems = 16;               // arcs per thread per tile
+constexpr int kTile = kBlock * kItems;   // 4096 arcs per tile
+constexpr int kDigits = 256;
+constexpr int kPasses = 4;
+constexpr int kNumKernels = 8;  // launches per step (k_hist .. k_probe)
+
+// packed estimator word: chi in bits 0..30, closed flag in bit 31
+constexpr uint32_t kClosed = 0x80000000u;
+constexpr uint32_t kChiMax = 0x7FFFFFFFu;
+
+// tagged directory: a slot is live only if its tag equals the step's tag
+constexpr uint32_t kTagMax = 0x7FFFFFFFu;
+
+// sticky device error bits
+constexpr uint32_t kErrSelfLoop = 1u;
+constexpr uint32_t kErrOverflow = 2u;
+constexpr uint32_t kErrProbe = 4u;  // a table probe ran past its bound
+constexpr uint32_t kErrStall = 8u;  // a bounded wait gave up
+// errors after which the rest of a step must not trust its scratch
+constexpr uint32_t kErrFatal = kErrSelfLoop | kErrStall;
+// bounded waits: a look-back or a busy table slot is given this many polls
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+// one chunk of a step (device view)
+struct SegDesc {
+  const uint32_t* edges;  // W: uint32[2w], device
+  uint64_t m;             // bank's |E| before this batch
+  uint64_t batch;         // bank's batch index (random key)
+  uint64_t key0;          // mix64(seed ^ golden), precomputed on the host
+  uint64_t est_off;       // bank's first estimator in the state arrays
+  uint64_t gest_off;      // first flat estimator thread of this segment
+  uint64_t arc_off;       // first arc slot in the arc buffers (2 * sum w)
+  uint64_t dir_off;       // first directory slot
+  uint64_t qt_off;        // first query-table slot
+  uint32_t w;             // edges in the chunk
+  uint32_t r;             // estimators in the bank
+  uint32_t tile_off;      // first global tile of the segment
+  uint32_t ntiles;        // ceil(2w / kTile)
+  uint32_t dir_log2;      // log2 of the directory region (slots)
+  uint32_t qt_log2;       // log2 of the query-table region (slots)
+};
+
+// per-segment values produced during a step (device)
+struct SegWork {
+  uint32_t hist[kPasses][kDigits];  // digit histograms of the 2w arcs
+  uint32_t maxid;                   // largest vertex id in the chunk
+  uint32_t final_buf;               // arc buffer holding the sorted arcs
+  uint32_t dense;                   // directory indexed by vertex id
+  uint32_t pad;
+};
+
+// vertex directory entry: segment [start, end) of vertex `key` in the
+// sorted arcs, live iff tag == step tag
+struct DirSlot {
+  uint32_t key;
+  uint32_t tag;
+  uint32_t start;
+  uint32_t end;
+};
+
+// Step-3 query table entry: a closing edge some estimators wait for, with
+// the head of the list of those estimators (linked through `link`).  The
+// table is reset to all-ones bytes (key = kEmpty, head = kNone) at the start
+// of every step, so the key itself is the claim word.
+struct QSlot {
+  uint64_t key;
+  uint32_t head;
+  uint32_t pad;
+};
+
+struct StepArgs {
+  const SegDesc* segs;    // device copy of all segment descriptors
+  SegDesc seg0;           // inline copy when nseg == 1
+  uint32_t nseg;
+  uint32_t ntiles;        // total tiles over segments
+  uint64_t nest;          // total estimator threads over segments
+  uint32_t tag;           // this step's table tag (1 .. kTagMax)
+  // estimator state (all banks)
+  uint64_t* r1;
+  uint64_t* r2;
+  uint32_t* cc;
+  uint64_t* link;         // per estimator: (next << 32) | threshold
+  // scratch
+  SegWork* work;          // [nseg]
+  uint64_t* arcs[2];      // ping-pong arc buffers
+  uint32_t* status[2];    // look-back status, [ntiles][kDigits] each
+  uint32_t* tile_ctr;     // [kPasses]
+  DirSlot* dir;
+  QSlot* qt;
+  uint64_t qt_slots;      // query-table slots over all segments
+  uint32_t* err;          // sticky error bits
+};
+
+}  // namespace tc

@@ -1,0 +1,688 @@
+// Device kernels of the bulk estimator update (Tangwongsan, Pavan,
+// Tirthapura, Sec. 4: bulkUpdateAll) for gfx950.
+//
+// One step = k_hist -> k_pass<0..3> -> k_dir -> k_est -> k_probe.
+//
+//  k_hist   digit histograms of the 2w arcs (+ max id, self-loop check)
+//  k_pass   stable LSD radix pass over 8 bits of the vertex id (onesweep:
+//           wave64 ballot ranking, decoupled look-back, LDS-staged coalesced
+//           scatter).  Arcs are (vertex << 32 | pos); stability keeps every
+//           vertex's arcs in arrival order, which is the rankAll grouping
+//           of the Lemma on rankAll read in increasing pos (rank = arcs
+//           after it in the segment).  Digits constant over a chunk are
+//           skipped on the device.
+//  k_dir    vertex -> [start, end) of its arcs (tag-versioned directory)
+//  k_est    Steps 1 and 2 for every estimator; posts the Step-3 query
+//  k_probe  Step 3: one pass over W closes the estimators waiting for it
+#include <algorithm>
+
+#include "tc_internal.h"
+
+namespace tc {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  // splitmix64 output finalizer (Steele, Lea, Flood 2014)
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  // a 32-bit bijective avalanche mixer (xorshift-multiply rounds)
+  x ^= x >> 16;
+  x *= 0x7FEB352Du;
+  x ^= x >> 15;
+  x *= 0x846CA68Bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ __forceinline__ uint64_t canon(uint32_t a, uint32_t b) {
+  return a < b ? ((uint64_t)a << 32) | b : ((uint64_t)b << 32) | a;
+}
+
+// Uniform integer in [0, n), n >= 1: Lemire's multiply-shift with rejection
+// over the keyed stream mix64(kb ^ (purpose * golden + attempt)).
+__device__ __forceinline__ uint64_t bounded(uint64_t kb, uint64_t purpose,
+                                            uint64_t n) {
+  for (uint64_t att = 0;; ++att) {
+    const uint64_t x = mix64(kb ^ (purpose * kGolden + att));
+    const uint64_t lo = x * n;
+    const uint64_t hi = __umul64hi(x, n);
+    if (lo >= n) return hi;  // outside the zone that needs the threshold
+    const uint64_t t = (0ull - n) % n;
+    if (lo >= t) return hi;
+  }
+}
+
+// the edge closing the wedge f1, f2 (the endpoints they do not share)
+__device__ __forceinline__ uint64_t closing(uint64_t f1, uint64_t f2) {
+  if (f1 == f2) return kEmpty;
+  const uint32_t a = (uint32_t)(f1 >> 32), b = (uint32_t)f1;
+  const uint32_t x = (uint32_t)(f2 >> 32), y = (uint32_t)f2;
+  if (a == x || a == y) return canon(b, a == x ? y : x);
+  if (b == x || b == y) return canon(a, b == x ? y : x);
+  return kEmpty;
+}
+
+__device__ __forceinline__ uint32_t ld_relaxed(uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// segment of a global tile: the last segment whose tile_off <= gtile
+__device__ __forceinline__ uint32_t seg_of_tile(const StepArgs& a,
+                                                uint32_t gtile) {
+  if (a.nseg == 1) return 0;
+  uint32_t lo = 0, hi = a.nseg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (a.segs[mid].tile_off <= gtile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// segment of a flat estimator thread
+__device__ __forceinline__ uint32_t seg_of_est(const StepArgs& a,
+                                               uint64_t gid) {
+  if (a.nseg == 1) return 0;
+  uint32_t lo = 0, hi = a.nseg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (a.segs[mid].gest_off <= gid) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ const SegDesc& seg_desc(const StepArgs& a,
+                                                   uint32_t s) {
+  return a.nseg == 1 ? a.seg0 : a.segs[s];
+}
+
+// exclusive scan of one value per thread over the block (kBlock threads)
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v,
+                                                    uint32_t* s_tmp,
+                                                    uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_tmp[wave] = x;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const uint32_t t = s_tmp[w];
+    off += (w < wave) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+// ---------------------------------------------------------------------------
+// k_hist: per-segment histograms of all four digits of the arc keys
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
+  __shared__ uint32_t h[kPasses][kDigits];
+  __shared__ uint32_t s_max;
+  __shared__ uint32_t s_seg;
+  const int tid = threadIdx.x;
+  const uint32_t gtile = blockIdx.x;
+  if (tid == 0) {
+    s_seg = seg_of_tile(a, gtile);
+    s_max = 0;
+  }
+  // the radix passes of this step take their tiles from these counters
+  if (gtile == 0 && tid < kPasses) a.tile_ctr[tid] = 0;
+  // empty the Step-3 query tables (first used by k_est of this step)
+  {
+    uint4* q4 = reinterpret_cast<uint4*>(a.qt);
+    const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (uint64_t t = (uint64_t)gtile * kBlock + tid; t < a.qt_slots;
+         t += (uint64_t)a.ntiles * kBlock)
+      q4[t] = ones;
+  }
+#pragma unroll
+  for (int d = 0; d < kPasses; ++d) h[d][tid] = 0;
+  __syncthreads();
+  const uint32_t sidx = s_seg;
+  const SegDesc& S = seg_desc(a, sidx);
+  const uint32_t ebase = (gtile - S.tile_off) * (kTile / 2);
+  const uint32_t eend = min(ebase + (uint32_t)(kTile / 2), S.w);
+  const uint2* E = reinterpret_cast<const uint2*>(S.edges);
+  uint32_t vmax = 0;
+  bool loop = false;
+  for (uint32_t j = ebase + tid; j < eend; j += kBlock) {
+    const uint2 e = E[j];
+    loop |= (e.x == e.y);
+    vmax = max(vmax, max(e.x, e.y));
+#pragma unroll
+    for (int d = 0; d < kPasses; ++d) {
+      atomicAdd(&h[d][(e.x >> (8 * d)) & 255u], 1u);
+      atomicAdd(&h[d][(e.y >> (8 * d)) & 255u], 1u);
+    }
+  }
+  if (loop) atomicOr(a.err, kErrSelfLoop);
+  atomicMax(&s_max, vmax);
+  __syncthreads();
+  SegWork* wk = a.work + sidx;
+  if (tid == 0) atomicMax(&wk->maxid, s_max);
+#pragma unroll
+  for (int d = 0; d < kPasses; ++d)
+    if (h[d][tid]) atomicAdd(&wk->hist[d][tid], h[d][tid]);
+}
+
+// ---------------------------------------------------------------------------
+// k_pass<P>: one stable counting pass on digit P of the vertex id
+// ---------------------------------------------------------------------------
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kValMask = (1u << 30) - 1;
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
+  __shared__ uint64_t s_el[kTile];
+  __shared__ uint32_t s_wh[kWaves][kDigits];
+  __shared__ uint32_t s_loc[kDigits];
+  __shared__ uint32_t s_dst[kDigits];
+  __shared__ uint32_t s_tmp[kWaves];
+  __shared__ uint32_t s_tile, s_seg;
+  __shared__ int s_triv[kPasses];
+  __shared__ int s_stall;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    s_tile = atomicAdd(&a.tile_ctr[P], 1u);
+    s_stall = 0;
+  }
+  if (tid < kPasses) s_triv[tid] = 0;
+  __syncthreads();
+  const uint32_t gtile = s_tile;
+  if (gtile >= a.ntiles) {  // counters not reset: refuse to touch memory
+    if (tid == 0) atomicOr(a.err, kErrStall);
+    return;
+  }
+  // the other look-back region is used by the next pass: clear our tile
+  a.status[(P + 1) & 1][(size_t)gtile * kDigits + tid] = 0;
+  if (tid == 0) s_seg = seg_of_tile(a, gtile);
+  __syncthreads();
+  const uint32_t sidx = s_seg;
+  const SegDesc& S = seg_desc(a, sidx);
+  SegWork* wk = a.work + sidx;
+  const uint32_t n = 2u * S.w;
+  const uint32_t ltile = gtile - S.tile_off;
+
+  // digits that are constant over the chunk need no pass
+#pragma unroll
+  for (int d = 0; d <= P; ++d)
+    if (wk->hist[d][tid] == n) s_triv[d] = 1;
+  __syncthreads();
+  int k = 0;  // non-trivial passes before this one
+#pragma unroll
+  for (int d = 0; d < P; ++d) k += s_triv[d] ? 0 : 1;
+  if (P == kPasses - 1 && ltile == 0 && tid == 0) {
+    const int K = k + (s_triv[P] ? 0 : 1);
+    wk->final_buf = (uint32_t)((K + 1) & 1);  // (K - 1) & 1, K >= 1
+    const uint64_t span = (uint64_t)wk->maxid + 1;
+    wk->dense = span <= (1ull << S.dir_log2) ? 1u : 0u;
+  }
+  if (s_triv[P]) return;
+
+  const uint64_t* src = a.arcs[(k + 1) & 1] + S.arc_off;  // (k-1)&1
+  uint64_t* dst = a.arcs[k & 1] + S.arc_off;
+  const uint32_t base = ltile * kTile;
+  const uint32_t nv = min((uint32_t)kTile, n - base);
+
+  // load: wave w owns arcs [w*64*kItems, (w+1)*64*kItems) of the tile,
+  // iteration i covers 64 consecutive arcs (original order = (i, lane))
+  uint64_t el[kItems];
+  uint32_t rk[kItems];
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const uint32_t li = wave * 64 * kItems + i * 64 + lane;
+    const uint32_t gi = base + li;
+    if (li < nv) {
+      el[i] = (k == 0) ? (((uint64_t)S.edges[gi] << 32) | (gi >> 1)) : src[gi];
+    } else {
+      el[i] = 0;
+    }
+  }
+  s_wh[wave][lane] = 0;
+  s_wh[wave][lane + 64] = 0;
+  s_wh[wave][lane + 128] = 0;
+  s_wh[wave][lane + 192] = 0;
+  __syncthreads();
+
+  // stable rank of each arc among equal digits of its wave (ballot match)
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const uint32_t li = wave * 64 * kItems + i * 64 + lane;
+    const bool valid = li < nv;
+    const uint32_t dg = (uint32_t)(el[i] >> (32 + 8 * P)) & 255u;
+    uint64_t mm = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (dg >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      mm &= bit ? bb : ~bb;
+    }
+    const uint32_t below = __popcll(mm & lt_mask);
+    uint32_t prev = 0;
+    if (valid) prev = s_wh[wave][dg];
+    if (valid && below == 0) s_wh[wave][dg] = prev + __popcll(mm);
+    rk[i] = prev + below;
+  }
+  __syncthreads();
+
+  // per digit (thread = digit): wave offsets, tile count, tile offsets
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const uint32_t c = s_wh[w][tid];
+    s_wh[w][tid] = cnt;
+    cnt += c;
+  }
+  uint32_t tot;
+  s_loc[tid] = block_excl_scan(cnt, s_tmp, &tot);
+  const uint32_t bin = block_excl_scan(wk->hist[P][tid], s_tmp, &tot);
+
+  // decoupled look-back over earlier tiles of this segment, per digit
+  uint32_t* st = a.status[P & 1] + (size_t)S.tile_off * kDigits;
+  uint32_t excl = 0;
+  if (ltile == 0) {
+    st_relaxed(&st[tid], kFlagInc | cnt);
+  } else {
+    st_relaxed(&st[(size_t)ltile * kDigits + tid], kFlagAgg | cnt);
+    uint32_t j = ltile - 1;
+    uint32_t polls = 0;
+    for (;;) {
+      const uint32_t v = ld_relaxed(&st[(size_t)j * kDigits + tid]);
+      const uint32_t f = v & ~kValMask;
+      if (f == 0) {
+        if (++polls > kSpinLimit) {  // a predecessor never published
+          s_stall = 1;
+          atomicOr(a.err, kErrStall);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      excl += v & kValMask;
+      if (f == kFlagInc) break;
+      if (j == 0) break;  // tile 0 always publishes an inclusive value
+      --j;
+    }
+    st_relaxed(&st[(size_t)ltile * kDigits + tid], kFlagInc | (excl + cnt));
+  }
+  s_dst[tid] = bin + excl - s_loc[tid];
+  __syncthreads();
+  if (s_stall) return;
+
+  // scatter into LDS in digit order, then write runs out coalesced
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const uint32_t li = wave * 64 * kItems + i * 64 + lane;
+    if (li < nv) {
+      const uint32_t dg = (uint32_t)(el[i] >> (32 + 8 * P)) & 255u;
+      s_el[s_loc[dg] + s_wh[wave][dg] + rk[i]] = el[i];
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < nv; i += kBlock) {
+    const uint64_t e = s_el[i];
+    const uint32_t dg = (uint32_t)(e >> (32 + 8 * P)) & 255u;
+    dst[s_dst[dg] + i] = e;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// vertex directory
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t dir_claim(DirSlot* dir, uint32_t mask,
+                                              uint32_t x, uint32_t tag,
+                                              uint32_t* err) {
+  const uint64_t want = ((uint64_t)tag << 32) | x;
+  uint32_t h = mix32(x) & mask;
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    unsigned long long* kt = reinterpret_cast<unsigned long long*>(&dir[h]);
+    const uint64_t cur = __hip_atomic_load(kt, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == want) return h;
+    if ((uint32_t)(cur >> 32) != tag) {
+      const uint64_t old = atomicCAS(kt, (unsigned long long)cur,
+                                     (unsigned long long)want);
+      if (old == cur || old == want) return h;
+      // otherwise another key took the slot this step: move on
+    }
+    h = (h + 1) & mask;
+  }
+  atomicOr(err, kErrProbe);
+  return kNone;
+}
+
+// [start, end) of x's arcs, or an empty range
+__device__ __forceinline__ uint2 dir_find(const DirSlot* dir, uint32_t log2,
+                                          bool dense, uint32_t x,
+                                          uint32_t tag) {
+  const uint32_t mask = (1u << log2) - 1u;
+  if (dense) {
+    if (x > mask) return make_uint2(0, 0);
+    const uint4 e = *reinterpret_cast<const uint4*>(&dir[x]);
+    if (e.y == tag && e.x == x) return make_uint2(e.z, e.w);
+    return make_uint2(0, 0);
+  }
+  uint32_t h = mix32(x) & mask;
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    const uint4 e = *reinterpret_cast<const uint4*>(&dir[h]);
+    if (e.y != tag) break;
+    if (e.x == x) return make_uint2(e.z, e.w);
+    h = (h + 1) & mask;
+  }
+  return make_uint2(0, 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
+  __shared__ uint32_t s_seg;
+  const int tid = threadIdx.x;
+  const uint32_t gtile = blockIdx.x;
+  if (tid == 0) s_seg = seg_of_tile(a, gtile);
+  __syncthreads();
+  if (*a.err & kErrFatal) return;
+  const uint32_t sidx = s_seg;
+  const SegDesc& S = seg_desc(a, sidx);
+  const SegWork* wk = a.work + sidx;
+  const uint64_t* arc = a.arcs[wk->final_buf] + S.arc_off;
+  const uint32_t n = 2u * S.w;
+  const uint32_t base = (gtile - S.tile_off) * kTile;
+  const uint32_t end = min(base + (uint32_t)kTile, n);
+  DirSlot* dir = a.dir + S.dir_off;
+  const bool dense = wk->dense != 0;
+  const uint32_t mask = (1u << S.dir_log2) - 1u;
+  for (uint32_t i = base + tid; i < end; i += kBlock) {
+    const uint32_t x = (uint32_t)(arc[i] >> 32);
+    const bool head = i == 0 || (uint32_t)(arc[i - 1] >> 32) != x;
+    const bool tail = i + 1 == n || (uint32_t)(arc[i + 1] >> 32) != x;
+    if (!head && !tail) continue;
+    uint32_t slot;
+    if (dense) {
+      if (x > mask) continue;  // cannot happen: x <= max id < 2^dir_log2
+      slot = x;
+      *reinterpret_cast<uint2*>(&dir[x]) = make_uint2(x, a.tag);
+    } else {
+      slot = dir_claim(dir, mask, x, a.tag, a.err);
+      if (slot == kNone) continue;
+    }
+    if (head) dir[slot].start = i;
+    if (tail) dir[slot].end = i + 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_est: Steps 1 and 2 per estimator, Step-3 query posted
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lower_bound(const uint64_t* v, uint32_t lo,
+                                                uint32_t hi, uint64_t key) {
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (v[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// join (or open) the list of estimators waiting for closing edge q;
+// returns the previous list head (kNone when first).  Only relaxed atomics:
+// the key is the claim word and the head is swapped atomically, so no
+// cross-CU fence (an L2 writeback/invalidate on this chip) is needed.
+__device__ __forceinline__ uint32_t qt_post(QSlot* qt, uint32_t mask,
+                                            uint64_t q, uint32_t est,
+                                            uint32_t* err) {
+  uint32_t h = (uint32_t)mix64(q) & mask;
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    unsigned long long* k = reinterpret_cast<unsigned long long*>(&qt[h].key);
+    uint64_t cur = __hip_atomic_load(k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == kEmpty)
+      cur = atomicCAS(k, (unsigned long long)kEmpty, (unsigned long long)q);
+    if (cur == kEmpty || cur == q) return atomicExch(&qt[h].head, est);
+    h = (h + 1) & mask;
+  }
+  atomicOr(err, kErrProbe);
+  return kNone;
+}
+
+__global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
+  const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= a.nest) return;
+  if (*a.err & kErrFatal) return;
+  const uint32_t sidx = seg_of_est(a, gid);
+  const SegDesc& S = seg_desc(a, sidx);
+  const SegWork* wk = a.work + sidx;
+  const uint32_t i = (uint32_t)(gid - S.gest_off);  // index within the bank
+  const uint64_t e = S.est_off + i;
+  const uint2* W = reinterpret_cast<const uint2*>(S.edges);
+
+  uint64_t r1 = a.r1[e], r2 = a.r2[e];
+  const uint32_t ccw = a.cc[e];
+  uint64_t c = ccw & kChiMax;
+  bool closed = (ccw & kClosed) != 0;
+  const uint64_t kb = mix64(mix64(S.key0 ^ (uint64_t)i) ^ S.batch);
+
+  // Step 1 (Sec. 4.2): replace f1 with probability w / (m + w)
+  uint32_t j1 = kNone;
+  const uint64_t x = bounded(kb, 1, S.m + S.w);
+  if (x >= S.m) {
+    j1 = (uint32_t)(x - S.m);
+    const uint2 ed = W[j1];
+    r1 = canon(ed.x, ed.y);
+    c = 0;
+    r2 = kEmpty;
+    closed = false;
+  }
+
+  // Step 2 (Sec. 4.3): chi+ = rank(u->v) + rank(v->u) with u < v
+  const uint32_t u = (uint32_t)(r1 >> 32), v = (uint32_t)r1;
+  const bool dense = wk->dense != 0;
+  const uint2 su = dir_find(a.dir + S.dir_off, S.dir_log2, dense, u, a.tag);
+  const uint2 sv = dir_find(a.dir + S.dir_off, S.dir_log2, dense, v, a.tag);
+  const uint64_t* arc = a.arcs[wk->final_buf] + S.arc_off;
+  uint32_t ld, rd;
+  if (j1 != kNone) {
+    // f1 is W[j1]: count the arcs after it on each endpoint (the arc of
+    // W[j1] itself is always present; the guard only keeps every later
+    // index inside the segment)
+    const uint32_t iu = lower_bound(arc, su.x, su.y, ((uint64_t)u << 32) | j1);
+    const uint32_t iv = lower_bound(arc, sv.x, sv.y, ((uint64_t)v << 32) | j1);
+    ld = iu < su.y ? su.y - 1 - iu : 0u;
+    rd = iv < sv.y ? sv.y - 1 - iv : 0u;
+  } else {
+    ld = su.y - su.x;
+    rd = sv.y - sv.x;
+  }
+  const uint64_t cplus = (uint64_t)ld + rd;
+  uint32_t p2 = kNone;
+  if (cplus != 0) {
+    const uint64_t tot = c + cplus;
+    const uint64_t y = bounded(kb, 2, tot);
+    if (y >= c) {
+      // phi names the (phi)-th candidate: rank phi on u, else phi-ld on v;
+      // rank k on a vertex is the arc with k later arcs of that vertex
+      const uint64_t phi = y - c;
+      const uint32_t idx = phi < ld ? su.y - 1 - (uint32_t)phi
+                                    : sv.y - 1 - (uint32_t)(phi - ld);
+      p2 = (uint32_t)arc[idx];
+      if (p2 >= S.w) {  // cannot happen: arcs carry positions < w
+        atomicOr(a.err, kErrStall);
+        p2 = 0;
+      }
+      const uint2 ed = W[p2];
+      r2 = canon(ed.x, ed.y);
+      closed = false;
+    }
+    if (tot > kChiMax) {
+      atomicOr(a.err, kErrOverflow);
+      c = kChiMax;
+    } else {
+      c = tot;
+    }
+  }
+
+  // Step 3 (Sec. 4.4) query: wait for the closing edge in this batch
+  if (r2 != kEmpty && !closed) {
+    const uint64_t q = closing(r1, r2);
+    if (q != kEmpty) {
+      const uint32_t thr = (p2 == kNone) ? 0u : p2 + 1;  // need pos >= thr
+      const uint32_t nxt = qt_post(a.qt + S.qt_off, (1u << S.qt_log2) - 1u, q,
+                                   (uint32_t)e, a.err);
+      a.link[e] = ((uint64_t)nxt << 32) | thr;
+    }
+  }
+  a.r1[e] = r1;
+  a.r2[e] = r2;
+  a.cc[e] = (uint32_t)c | (closed ? kClosed : 0u);
+}
+
+// ---------------------------------------------------------------------------
+// k_probe: Step 3, stream W once; every batch edge that some estimators
+// wait for closes those whose level-2 edge came earlier
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
+  __shared__ uint32_t s_seg;
+  const int tid = threadIdx.x;
+  const uint32_t gtile = blockIdx.x;
+  if (tid == 0) s_seg = seg_of_tile(a, gtile);
+  __syncthreads();
+  const uint32_t sidx = s_seg;
+  const SegDesc& S = seg_desc(a, sidx);
+  const bool ok = (*a.err & kErrFatal) == 0;
+  const uint32_t ebase = (gtile - S.tile_off) * (kTile / 2);
+  const uint32_t eend = min(ebase + (uint32_t)(kTile / 2), S.w);
+  const uint2* W = reinterpret_cast<const uint2*>(S.edges);
+  const QSlot* qt = a.qt + S.qt_off;
+  const uint32_t mask = (1u << S.qt_log2) - 1u;
+  for (uint32_t j = ebase + tid; ok && j < eend; j += kBlock) {
+    const uint2 ed = W[j];
+    const uint64_t q = canon(ed.x, ed.y);
+    uint32_t h = (uint32_t)mix64(q) & mask;
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+      const QSlot s = qt[h];
+      if (s.key == kEmpty) break;
+      if (s.key == q) {
+        uint64_t hops = 0;
+        for (uint32_t est = s.head; est != kNone && hops <= a.nest; ++hops) {
+          const uint64_t l = a.link[est];
+          if (j >= (uint32_t)l) atomicOr(&a.cc[est], kClosed);
+          est = (uint32_t)(l >> 32);
+        }
+        break;
+      }
+      h = (h + 1) & mask;
+    }
+  }
+  // this step no longer needs the per-segment work area: reset it
+  const uint32_t words = a.nseg * (uint32_t)(sizeof(SegWork) / 4);
+  uint32_t* wz = reinterpret_cast<uint32_t*>(a.work);
+  for (uint32_t t = gtile * kBlock + tid; t < words; t += a.ntiles * kBlock)
+    wz[t] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// estimate and small utilities
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_sum(const uint32_t* cc,
+                                                const uint64_t* bank_off,
+                                                uint32_t nbanks, uint64_t total,
+                                                unsigned long long* sums) {
+  const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= total) return;
+  const uint32_t w = cc[gid];
+  if (!(w & kClosed)) return;
+  uint32_t lo = 0, hi = nbanks - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (bank_off[mid] <= gid) lo = mid; else hi = mid - 1;
+  }
+  atomicAdd(&sums[lo], (unsigned long long)(w & kChiMax));
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill64(uint64_t* p, uint64_t n,
+                                                   uint64_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kBlock)
+    p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill32(uint32_t* p, uint64_t n,
+                                                   uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kBlock)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+// ev: optional kNumKernels + 1 events recorded around the kernels
+hipError_t launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
+  const dim3 blk(kBlock);
+  const dim3 tiles(a.ntiles);
+  const dim3 ests((uint32_t)((a.nest + kBlock - 1) / kBlock));
+  int k = 0;
+  auto mark = [&]() {
+    if (ev) (void)hipEventRecord(ev[k++], st);
+  };
+  mark();
+  hipLaunchKernelGGL(k_hist, tiles, blk, 0, st, a);
+  mark();
+  hipLaunchKernelGGL(k_pass<0>, tiles, blk, 0, st, a);
+  mark();
+  hipLaunchKernelGGL(k_pass<1>, tiles, blk, 0, st, a);
+  mark();
+  hipLaunchKernelGGL(k_pass<2>, tiles, blk, 0, st, a);
+  mark();
+  hipLaunchKernelGGL(k_pass<3>, tiles, blk, 0, st, a);
+  mark();
+  hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a);
+  mark();
+  hipLaunchKernelGGL(k_est, ests, blk, 0, st, a);
+  mark();
+  hipLaunchKernelGGL(k_probe, tiles, blk, 0, st, a);
+  mark();
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(const uint32_t* cc, const uint64_t* bank_off,
+                      uint32_t nbanks, uint64_t total,
+                      unsigned long long* sums, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill64, dim3(1), dim3(kBlock), 0, st,
+                     reinterpret_cast<uint64_t*>(sums), (uint64_t)nbanks, 0ull);
+  const uint64_t nb = (total + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_sum, dim3((uint32_t)nb), dim3(kBlock), 0, st, cc,
+                     bank_off, nbanks, total, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint64_t nb = std::min<uint64_t>((n + kBlock - 1) / kBlock, 65536);
+  hipLaunchKernelGGL(k_fill64, dim3((uint32_t)nb), dim3(kBlock), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint64_t nb = std::min<uint64_t>((n + kBlock - 1) / kBlock, 65536);
+  hipLaunchKernelGGL(k_fill32, dim3((uint32_t)nb), dim3(kBlock), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace tc

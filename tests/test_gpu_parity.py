@@ -1,0 +1,274 @@
+"""GPU path == CPU oracle, through the C-ABI (needs an MI355X).
+
+Estimator state (f1, f2, chi, closed) must match the oracle bit for bit
+after every batch; S = sum chi*closed exactly; tau_hat within 1e-12
+relative.  Inputs are the seeded synthetic streams of
+``paper_1308_2166_amd.inputs``; expected values come only from ``oracle``.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1308_2166_amd import inputs
+
+pytestmark = pytest.mark.gpu
+REL_TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1308_2166_amd as tcm
+    tcm.lib()
+    return tcm
+
+
+def to_dev(E: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(E, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def assert_same(gpu_state, ora_state, where=""):
+    names = ("r1", "r2", "c", "closed")
+    for name, g, o in zip(names, gpu_state, ora_state):
+        if not np.array_equal(g, o):
+            bad = np.nonzero(g != o)[0]
+            raise AssertionError(f"{where}: {name} differs at {bad.size} estimators, "
+                                 f"first {bad[:5].tolist()}: gpu {g[bad[:5]].tolist()} "
+                                 f"oracle {o[bad[:5]].tolist()}")
+
+
+def run_both(tc, E, r, seed, w, variant="bulk", every=True):
+    """Feed E in batches of w to a GPU bank and an oracle bank, comparing."""
+    say(f"  run r={r} seed={seed} w={w} m={len(E)}")
+    dev = to_dev(E)
+    g = tc.Bank(r, seed)
+    o = O.Bank(r, seed)
+    for k, j in enumerate(range(0, len(E), w)):
+        g.process(dev[j:j + w])
+        assert o.process(E[j:j + w], variant) == O.OK
+        if every or j + w >= len(E):
+            assert_same(g.state(), o.state(), f"batch {k}")
+    S, m, tau = tc.tc_estimate_ex(g.h)
+    assert S == o.sum() and m == o.m == len(E)
+    want = o.estimate()
+    assert abs(tau - want) <= REL_TOL * max(1.0, abs(want))
+    assert g.batch == o.batch
+    return g, o
+
+
+def np_edges(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+# -- the small workload: G(2000, 20000), r = 4096, w = 2048 (ragged tail) ---------
+
+def test_gnm2k_every_batch(tc):
+    G, r, w, seed = inputs.workload("gnm-2k")
+    E = np_edges(G)
+    g, o = run_both(tc, E, r, seed, w)
+    d = O.run_stream(E, r, seed, w, variant="def")
+    assert_same(g.state(), d.state(), "def variant")
+
+
+@pytest.mark.parametrize("n,m,r,w", [
+    (30, 120, 1, 1), (30, 120, 7, 2), (40, 300, 64, 3), (60, 500, 100, 7),
+    (200, 3000, 1000, 4096), (500, 5000, 3000, 1000), (1000, 9000, 257, 2049),
+    (80, 2000, 5000, 333),
+])
+def test_small_graphs(tc, n, m, r, w):
+    E = np_edges(inputs.gnm(n, m, seed=n + m))
+    run_both(tc, E, r, seed=r + w, w=w, variant="def")
+
+
+def test_multi_tile_ragged(tc):
+    # 2w spans several 4096-arc tiles with a ragged last one
+    E = np_edges(inputs.rmat(14, 60000, seed=3))
+    run_both(tc, E, r=20000, seed=9, w=9001)
+
+
+def test_star_giant_segment(tc):
+    hub = 7
+    leaves = np.arange(8, 20008, dtype=np.uint32)
+    E = np.stack([np.full_like(leaves, hub), leaves], 1)
+    chords = np.stack([leaves[:-1:5], leaves[1::5]], 1)
+    E = np.concatenate([E, chords])
+    E = E[np.random.default_rng(1).permutation(len(E))]
+    run_both(tc, E, r=30000, seed=2, w=6000)
+
+
+def test_wide_ids_use_the_hashed_directory(tc):
+    # ids spread over [0, 2^32): max id far above the dense directory range
+    E = np_edges(inputs.gnm(3000, 20000, seed=5)).astype(np.uint64)
+    spread = (E * 1431655761 + 977) % (2**32 - 5)
+    E = spread.astype(np.uint32)
+    assert E.max() > 2**31
+    run_both(tc, E, r=4096, seed=4, w=3000)
+
+
+def test_ids_at_the_top_of_uint32(tc):
+    E = np_edges(inputs.gnm(500, 4000, seed=6)).astype(np.uint64)
+    E = (np.uint64(2**32 - 1) - E).astype(np.uint32)
+    run_both(tc, E, r=2000, seed=8, w=777)
+
+
+def test_repeated_edges_are_deterministic(tc):
+    E = np_edges(inputs.gnm(300, 2000, seed=7))
+    E = np.concatenate([E, E[:500], E[100:300]])
+    run_both(tc, E, r=3000, seed=5, w=401)
+
+
+def test_batch_of_one_then_large(tc):
+    E = np_edges(inputs.gnm(400, 6000, seed=8))
+    dev = to_dev(E)
+    g, o = tc.Bank(1500, 3), O.Bank(1500, 3)
+    for a, b in [(0, 1), (1, 2), (2, 5000), (5000, 5001), (5001, 6000)]:
+        g.process(dev[a:b])
+        o.process(E[a:b])
+        assert_same(g.state(), o.state(), f"[{a},{b})")
+
+
+# -- boundary behaviour ------------------------------------------------------------
+
+def test_empty_batch_is_a_noop(tc):
+    g = tc.Bank(10, 1)
+    g.process(torch.zeros((0, 2), dtype=torch.int32, device="cuda"))
+    assert g.batch == 0 and g.m == 0
+    r1, r2, c, closed = g.state()
+    assert np.all(r1 == tc.TC_EMPTY_EDGE) and np.all(r2 == tc.TC_EMPTY_EDGE)
+    assert not c.any() and not closed.any()
+    assert g.estimate() == 0.0
+
+
+def test_invalid_arguments(tc):
+    with pytest.raises(tc.TcError):
+        tc.tc_create(0, 1)
+    g = tc.Bank(4, 1)
+    with pytest.raises(tc.TcError) as ei:
+        tc.tc_process_batch(g.h, None, w=5)
+    assert ei.value.code == tc.TC_EINVAL
+    assert tc.lib().tc_process_batch(g.h, 1, tc.TC_MAX_BATCH + 1, None) == tc.TC_EINVAL
+    assert g.batch == 0
+
+
+def test_self_loop_is_reported(tc):
+    E = np.array([[1, 2], [3, 3], [4, 5]], dtype=np.uint32)
+    g = tc.Bank(8, 1)
+    g.process(to_dev(E))
+    with pytest.raises(tc.TcError) as ei:
+        g.sync()
+    assert ei.value.code == tc.TC_EBADEDGE
+    with pytest.raises(tc.TcError):  # sticky
+        g.process(to_dev(E[:1]))
+
+
+def test_repeat_runs_are_identical(tc):
+    E = np_edges(inputs.rmat(16, 200000, seed=11))
+    dev = to_dev(E)
+    states = []
+    for _ in range(2):
+        g = tc.Bank(50000, 17)
+        for j in range(0, len(E), 65536):
+            g.process(dev[j:j + 65536])
+        states.append(g.state())
+    for a, b in zip(*states):
+        assert np.array_equal(a, b)
+
+
+def test_kernel_timing(tc):
+    E = np_edges(inputs.gnm(300, 3000, seed=2))
+    g = tc.Bank(1000, 1)
+    tc.tc_set_kernel_timing(g.h, True)
+    g.process(to_dev(E[:1500]))
+    g.process(to_dev(E[1500:]))
+    times, steps = tc.tc_kernel_times(g.h)
+    assert steps == 2 and len(times) == tc.tc_num_kernels()
+    assert all(v >= 0 for v in times.values()) and sum(times.values()) > 0
+    tc.tc_set_kernel_timing(g.h, False)
+    o = O.run_stream(E, 1000, 1, 1500)
+    assert_same(g.state(), o.state(), "timed")
+
+
+# -- many banks in one launch set ------------------------------------------------------
+
+def test_multi_banks_equal_their_own_streams(tc):
+    rs = [1, 100, 4096, 3000, 777, 20000]
+    seeds = [11, 12, 13, 14, 15, 16]
+    streams = [np_edges(inputs.gnm(200 + 50 * b, 2000 + 1500 * b, seed=30 + b))
+               for b in range(len(rs))]
+    ws = [97, 1000, 2048, 1, 5000, 3333]
+    mb = tc.MultiBank(rs, seeds)
+    devs = [to_dev(E) for E in streams]
+    pos = [0] * len(rs)
+    step = 0
+    oracles = [O.Bank(r, s) for r, s in zip(rs, seeds)]
+    while any(p < len(E) for p, E in zip(pos, streams)):
+        ids, chunks = [], []
+        for b in range(len(rs)):
+            if pos[b] >= len(streams[b]) or (b + step) % 3 == 0:
+                continue  # this bank sits the step out
+            w = ws[b] if b != 3 else 1 + (step * 37) % 700
+            ids.append(b)
+            chunks.append(devs[b][pos[b]:pos[b] + w])
+            oracles[b].process(streams[b][pos[b]:pos[b] + w])
+            pos[b] += w
+        if not ids:
+            step += 1
+            continue
+        mb.process(ids, chunks)
+        step += 1
+    S, m, tau = mb.estimate()
+    for b in range(len(rs)):
+        assert_same(mb.state(b), oracles[b].state(), f"bank {b}")
+        assert S[b] == oracles[b].sum() and m[b] == len(streams[b])
+    say(f"  {step} steps")
+
+
+def test_bank_alone_equals_bank_in_a_mix(tc):
+    E0 = np_edges(inputs.rmat(12, 30000, seed=1))
+    E1 = np_edges(inputs.gnm(900, 30000, seed=2))
+    d0, d1 = to_dev(E0), to_dev(E1)
+    alone = tc.MultiBank([5000], [3])
+    mix = tc.MultiBank([5000, 7000], [3, 4])
+    for j in range(0, 30000, 4000):
+        alone.process([0], [d0[j:j + 4000]])
+        mix.process([0, 1], [d0[j:j + 4000], d1[j:j + 2500]])
+    for a, b in zip(alone.state(0), mix.state(0)):
+        assert np.array_equal(a, b)
+
+
+def test_generators_identical_on_cpu_and_gpu(tc):
+    for make in (lambda d: inputs.rmat(12, 30000, seed=4, device=d),
+                 lambda d: inputs.gnm(1000, 20000, seed=5, device=d),
+                 lambda d: inputs.chung_lu(5000, 30000, seed=6, device=d)):
+        assert torch.equal(make("cpu"), make("cuda").cpu())
+
+
+# -- the benchmark workloads at full size --------------------------------------------
+
+def test_rmat20_full_stream(tc):
+    # R-MAT scale 20, m = 16*2^20, r = 2^20, w = 2^22: every batch, full state
+    say("  generating rmat20 on the GPU")
+    G, r, w, seed = inputs.workload("rmat20", device="cuda")
+    E = np_edges(G)
+    run_both(tc, E, r, seed, w)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_rmat24_first_batches(tc):
+    # R-MAT scale 24 shape: r = 2^22, w = 2^24, first two batches, full state
+    say("  generating rmat24 on the GPU")
+    G, r, w, seed = inputs.workload("rmat24", device="cuda")
+    E = np_edges(G[:2 * w])
+    del G
+    torch.cuda.empty_cache()
+    run_both(tc, E, r, seed, w)
