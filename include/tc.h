@@ -11,8 +11,8 @@
  * estimate is Lemma 1's X = chi * |E| (when closed) averaged over the bank.
  *
  * Conventions shared by every entry point:
- *   - A batch is `uint32_t edges[2*w]`: edge j is {edges[2j], edges[2j+1]},
- *     arrival order = j.  Edges must come from a simple undirected graph:
+ *   - A batch is `uint32_t edges[2*w]`, 8-byte aligned: edge j is
+ *     {edges[2j], edges[2j+1]}, arrival order = j.  Edges must come from a simple undirected graph:
  *     each edge once in the whole stream, no self-loops.  A self-loop is
  *     detected on the device and reported as TC_EBADEDGE by the next
  *     synchronising call (the bank is then unspecified).  Repeated edges
@@ -66,9 +66,9 @@ tc_state *tc_create(uint32_t r, uint64_t seed);
  * `edges` (DEVICE pointer to uint32[2w], caller-owned, read-only) on
  * `stream`; afterwards |E| += w and the batch index += 1.  w == 0 is a
  * no-op that does not advance the batch index.  Returns TC_EINVAL for a
- * NULL state, NULL edges with w > 0, or w > TC_MAX_BATCH; TC_ENOMEM if
- * scratch for a larger batch cannot be allocated; earlier sticky device
- * errors are returned here once known. */
+ * NULL state, NULL or misaligned edges with w > 0, or w > TC_MAX_BATCH;
+ * TC_ENOMEM if scratch for a larger batch cannot be allocated; earlier
+ * sticky device errors are returned here once known. */
 int tc_process_batch(tc_state *s, const uint32_t *edges, uint32_t w,
                      void *stream);
 

@@ -83,7 +83,6 @@ struct Engine {
   uint64_t* R1 = nullptr;
   uint64_t* R2 = nullptr;
   uint32_t* CC = nullptr;
-  uint64_t* LINK = nullptr;
   uint64_t* bank_off = nullptr;  // device copy of est_off
   unsigned long long* sums = nullptr;
   uint32_t* err = nullptr;
@@ -95,7 +94,6 @@ struct Engine {
   uint32_t cap_segs = 0;
   uint64_t* arcs[2] = {nullptr, nullptr};
   uint32_t* status[2] = {nullptr, nullptr};
-  uint32_t* tile_ctr = nullptr;
   SegWork* work = nullptr;
   DirSlot* dir = nullptr;
   QSlot* qt = nullptr;
@@ -131,7 +129,7 @@ struct Engine {
       }
     ev_pending.clear();
     ev_free.clear();
-    dfree(R1), dfree(R2), dfree(CC), dfree(LINK), dfree(bank_off);
+    dfree(R1), dfree(R2), dfree(CC), dfree(bank_off);
     dfree(sums), dfree(err);
     if (h_sums) (void)hipHostFree(h_sums);
     if (h_err) (void)hipHostFree(h_err);
@@ -146,7 +144,7 @@ struct Engine {
 
   void free_scratch() {
     dfree(arcs[0]), dfree(arcs[1]), dfree(status[0]), dfree(status[1]);
-    dfree(tile_ctr), dfree(work), dfree(dir), dfree(qt), dfree(segs_dev);
+    dfree(work), dfree(dir), dfree(qt), dfree(segs_dev);
     cap_arcs = cap_tiles = cap_dir = cap_qt = 0;
     cap_segs = 0;
   }
@@ -170,7 +168,7 @@ struct Engine {
     if (total >= 0x7FFFFFFFull)
       return fail(TC_EINVAL, "too many estimators in one object (max 2^31-2)");
     if (dalloc(&R1, total) || dalloc(&R2, total) || dalloc(&CC, total) ||
-        dalloc(&LINK, total) || dalloc(&bank_off, n + 1) ||
+        dalloc(&bank_off, n + 1) ||
         dalloc(&sums, n) || dalloc(&err, 1))
       return fail(TC_ENOMEM, "device allocation of the estimator banks failed");
     if (hipHostMalloc(reinterpret_cast<void**>(&h_sums), sizeof(uint64_t) * n) ||
@@ -203,7 +201,7 @@ struct Engine {
     if (dalloc(&arcs[0], cap_arcs) || dalloc(&arcs[1], cap_arcs) ||
         dalloc(&status[0], cap_tiles * kDigits) ||
         dalloc(&status[1], cap_tiles * kDigits) ||
-        dalloc(&tile_ctr, kPasses) || dalloc(&work, cap_segs) ||
+        dalloc(&work, cap_segs) ||
         dalloc(&dir, cap_dir) || dalloc(&qt, cap_qt) ||
         dalloc(&segs_dev, cap_segs)) {
       free_scratch();
@@ -212,7 +210,6 @@ struct Engine {
     // zero = "no tag" for the tables, cleared look-back and work areas
     if (hipMemsetAsync(status[0], 0, cap_tiles * kDigits * 4, st) ||
         hipMemsetAsync(status[1], 0, cap_tiles * kDigits * 4, st) ||
-        hipMemsetAsync(tile_ctr, 0, kPasses * 4, st) ||
         hipMemsetAsync(work, 0, sizeof(SegWork) * cap_segs, st) ||
         hipMemsetAsync(dir, 0, sizeof(DirSlot) * cap_dir, st) ||
         hipMemsetAsync(qt, 0, sizeof(QSlot) * cap_qt, st) ||
@@ -255,7 +252,7 @@ struct Engine {
     std::vector<SegDesc> segs;
     segs.reserve(nchunks);
     std::vector<char> seen(nbanks, 0);
-    uint64_t arcs_n = 0, tiles = 0, dir_n = 0, qt_n = 0, nest = 0;
+    uint64_t arcs_n = 0, tiles = 0, dir_n = 0, qt_n = 0, nest = 0, hblks = 0;
     for (uint32_t k = 0; k < nchunks; ++k) {
       const uint32_t b = ids[k];
       if (b >= nbanks) return fail(TC_EINVAL, "bank id out of range");
@@ -264,6 +261,8 @@ struct Engine {
       if (w[k] > TC_MAX_BATCH) return fail(TC_EINVAL, "batch larger than TC_MAX_BATCH");
       if (w[k] == 0) continue;
       if (!reserve && !edges[k]) return fail(TC_EINVAL, "null edge pointer with w > 0");
+      if (!reserve && (reinterpret_cast<uintptr_t>(edges[k]) & 7u))
+        return fail(TC_EINVAL, "edge buffer must be 8-byte aligned");
       SegDesc d{};
       d.edges = reserve ? nullptr : edges[k];
       d.m = m[b];
@@ -278,6 +277,9 @@ struct Engine {
       d.r = r[b];
       d.tile_off = (uint32_t)tiles;
       d.ntiles = (uint32_t)((2ull * w[k] + kTile - 1) / kTile);
+      d.hblk_off = (uint32_t)hblks;
+      d.nhblk = (d.ntiles + kHistTiles - 1) / kHistTiles;
+      hblks += d.nhblk;
       d.dir_log2 = dir_log2_for(w[k]);
       d.qt_log2 = qt_log2_for(r[b]);
       arcs_n += 2ull * w[k];
@@ -303,13 +305,13 @@ struct Engine {
     a.segs = segs_dev;
     a.seg0 = segs[0];
     a.ntiles = (uint32_t)tiles;
+    a.nhblk = (uint32_t)hblks;
     a.nest = nest;
     a.tag = tag;
-    a.r1 = R1, a.r2 = R2, a.cc = CC, a.link = LINK;
+    a.r1 = R1, a.r2 = R2, a.cc = CC;
     a.work = work;
     a.arcs[0] = arcs[0], a.arcs[1] = arcs[1];
     a.status[0] = status[0], a.status[1] = status[1];
-    a.tile_ctr = tile_ctr;
     a.dir = dir;
     a.qt = qt;
     a.qt_slots = qt_n;

@@ -22,6 +22,8 @@ constexpr int kTile = kBlock * kItems;   // 4096 arcs per tile
 constexpr int kDigits = 256;
 constexpr int kPasses = 4;
 constexpr int kNumKernels = 8;  // launches per step (k_hist .. k_probe)
+constexpr int kHistTiles = 8;   // tiles per k_hist block
+constexpr int kLookback = 16;   // predecessor statuses read per look-back round
 
 // packed estimator word: chi in bits 0..30, closed flag in bit 31
 constexpr uint32_t kClosed = 0x80000000u;
@@ -55,6 +57,8 @@ struct SegDesc {
   uint32_t r;             // estimators in the bank
   uint32_t tile_off;      // first global tile of the segment
   uint32_t ntiles;        // ceil(2w / kTile)
+  uint32_t hblk_off;      // first k_hist block of the segment
+  uint32_t nhblk;         // ceil(ntiles / kHistTiles)
   uint32_t dir_log2;      // log2 of the directory region (slots)
   uint32_t qt_log2;       // log2 of the query-table region (slots)
 };
@@ -62,6 +66,7 @@ struct SegDesc {
 // per-segment values produced during a step (device)
 struct SegWork {
   uint32_t hist[kPasses][kDigits];  // digit histograms of the 2w arcs
+  uint32_t tile_ctr[kPasses];       // next tile of each radix pass
   uint32_t maxid;                   // largest vertex id in the chunk
   uint32_t final_buf;               // arc buffer holding the sorted arcs
   uint32_t dense;                   // directory indexed by vertex id
@@ -77,14 +82,14 @@ struct DirSlot {
   uint32_t end;
 };
 
-// Step-3 query table entry: a closing edge some estimators wait for, with
-// the head of the list of those estimators (linked through `link`).  The
-// table is reset to all-ones bytes (key = kEmpty, head = kNone) at the start
-// of every step, so the key itself is the claim word.
+// Step-3 query table entry: estimator `est` waits for closing edge `key` at
+// a batch position >= `thr`.  Every waiting estimator owns one slot (equal
+// keys share a probe cluster).  The table is reset to key = kEmpty at the
+// start of every step, so the key itself is the claim word.
 struct QSlot {
   uint64_t key;
-  uint32_t head;
-  uint32_t pad;
+  uint32_t est;
+  uint32_t thr;
 };
 
 struct StepArgs {
@@ -92,18 +97,17 @@ struct StepArgs {
   SegDesc seg0;           // inline copy when nseg == 1
   uint32_t nseg;
   uint32_t ntiles;        // total tiles over segments
+  uint32_t nhblk;         // total k_hist blocks over segments
   uint64_t nest;          // total estimator threads over segments
   uint32_t tag;           // this step's table tag (1 .. kTagMax)
   // estimator state (all banks)
   uint64_t* r1;
   uint64_t* r2;
   uint32_t* cc;
-  uint64_t* link;         // per estimator: (next << 32) | threshold
   // scratch
   SegWork* work;          // [nseg]
   uint64_t* arcs[2];      // ping-pong arc buffers
   uint32_t* status[2];    // look-back status, [ntiles][kDigits] each
-  uint32_t* tile_ctr;     // [kPasses]
   DirSlot* dir;
   QSlot* qt;
   uint64_t qt_slots;      // query-table slots over all segments

@@ -87,6 +87,18 @@ __device__ __forceinline__ uint32_t seg_of_tile(const StepArgs& a,
   return lo;
 }
 
+// segment of a k_hist block
+__device__ __forceinline__ uint32_t seg_of_hblk(const StepArgs& a,
+                                                uint32_t b) {
+  if (a.nseg == 1) return 0;
+  uint32_t lo = 0, hi = a.nseg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (a.segs[mid].hblk_off <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // segment of a flat estimator thread
 __device__ __forceinline__ uint32_t seg_of_est(const StepArgs& a,
                                                uint64_t gid) {
@@ -99,9 +111,14 @@ __device__ __forceinline__ uint32_t seg_of_est(const StepArgs& a,
   return lo;
 }
 
-__device__ __forceinline__ const SegDesc& seg_desc(const StepArgs& a,
-                                                   uint32_t s) {
+// descriptor by value: kept in registers (scalar ones when s is uniform),
+// never re-read through a pointer inside the loops
+__device__ __forceinline__ SegDesc seg_desc(const StepArgs& a, uint32_t s) {
   return a.nseg == 1 ? a.seg0 : a.segs[s];
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+  return __builtin_amdgcn_readfirstlane(v);
 }
 
 // exclusive scan of one value per thread over the block (kBlock threads)
@@ -132,44 +149,78 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v,
 // ---------------------------------------------------------------------------
 // k_hist: per-segment histograms of all four digits of the arc keys
 // ---------------------------------------------------------------------------
+// add one to bin `dg`; a digit shared by the whole wave costs one atomic
+__device__ __forceinline__ void hist_add(uint32_t* h, uint32_t dg, bool valid) {
+  const uint32_t d0 = __shfl(dg, 0);
+  const uint64_t act = __ballot(valid);
+  if (__all(!valid || dg == d0) && act) {
+    if ((threadIdx.x & 63) == (uint32_t)(__ffsll((long long)act) - 1))
+      atomicAdd(&h[d0], (uint32_t)__popcll(act));
+  } else if (valid) {
+    atomicAdd(&h[dg], 1u);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
   __shared__ uint32_t h[kPasses][kDigits];
   __shared__ uint32_t s_max;
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
-  const uint32_t gtile = blockIdx.x;
+  const uint32_t hb = blockIdx.x;
   if (tid == 0) {
-    s_seg = seg_of_tile(a, gtile);
+    s_seg = seg_of_hblk(a, hb);
     s_max = 0;
   }
-  // the radix passes of this step take their tiles from these counters
-  if (gtile == 0 && tid < kPasses) a.tile_ctr[tid] = 0;
+#pragma unroll
+  for (int d = 0; d < kPasses; ++d) h[d][tid] = 0;
   // empty the Step-3 query tables (first used by k_est of this step)
   {
     uint4* q4 = reinterpret_cast<uint4*>(a.qt);
     const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
-    for (uint64_t t = (uint64_t)gtile * kBlock + tid; t < a.qt_slots;
-         t += (uint64_t)a.ntiles * kBlock)
+    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.qt_slots;
+         t += (uint64_t)a.nhblk * kBlock)
       q4[t] = ones;
   }
-#pragma unroll
-  for (int d = 0; d < kPasses; ++d) h[d][tid] = 0;
   __syncthreads();
-  const uint32_t sidx = s_seg;
-  const SegDesc& S = seg_desc(a, sidx);
-  const uint32_t ebase = (gtile - S.tile_off) * (kTile / 2);
-  const uint32_t eend = min(ebase + (uint32_t)(kTile / 2), S.w);
-  const uint2* E = reinterpret_cast<const uint2*>(S.edges);
+  const uint32_t sidx = uniform(s_seg);
+  const SegDesc S = seg_desc(a, sidx);
+  const uint32_t n = 2u * S.w;
+  const uint32_t abase = (hb - S.hblk_off) * (uint32_t)(kHistTiles * kTile);
+  const uint32_t aend = min(abase + (uint32_t)(kHistTiles * kTile), n);
   uint32_t vmax = 0;
   bool loop = false;
-  for (uint32_t j = ebase + tid; j < eend; j += kBlock) {
-    const uint2 e = E[j];
-    loop |= (e.x == e.y);
-    vmax = max(vmax, max(e.x, e.y));
+  const bool vec = (reinterpret_cast<uintptr_t>(S.edges) & 15u) == 0;
+  // four arcs (two edges) per thread and iteration; the block covers
+  // kHistTiles tiles so each global bin sees few atomic adds
+  for (uint32_t i = abase + 4 * tid; i < aend; i += 4 * kBlock) {
+    uint4 x = make_uint4(0, 0, 0, 0);
+    const bool full = i + 4 <= aend;
+    if (full && vec) {
+      x = *reinterpret_cast<const uint4*>(S.edges + i);
+    } else if (full) {
+      const uint2 e0 = *reinterpret_cast<const uint2*>(S.edges + i);
+      const uint2 e1 = *reinterpret_cast<const uint2*>(S.edges + i + 2);
+      x = make_uint4(e0.x, e0.y, e1.x, e1.y);
+    } else if (i < aend) {  // ragged tail: i is even, so i + 1 < aend
+      const uint2 e0 = *reinterpret_cast<const uint2*>(S.edges + i);
+      x.x = e0.x;
+      x.y = e0.y;
+    }
+    const bool v01 = i < aend, v23 = full;
+    if (v01) {
+      loop |= x.x == x.y;
+      vmax = max(vmax, max(x.x, x.y));
+    }
+    if (v23) {
+      loop |= x.z == x.w;
+      vmax = max(vmax, max(x.z, x.w));
+    }
 #pragma unroll
     for (int d = 0; d < kPasses; ++d) {
-      atomicAdd(&h[d][(e.x >> (8 * d)) & 255u], 1u);
-      atomicAdd(&h[d][(e.y >> (8 * d)) & 255u], 1u);
+      hist_add(h[d], (x.x >> (8 * d)) & 255u, v01);
+      hist_add(h[d], (x.y >> (8 * d)) & 255u, v01);
+      hist_add(h[d], (x.z >> (8 * d)) & 255u, v23);
+      hist_add(h[d], (x.w >> (8 * d)) & 255u, v23);
     }
   }
   if (loop) atomicOr(a.err, kErrSelfLoop);
@@ -201,42 +252,49 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
   __shared__ int s_stall;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // blocks [tile_off, tile_off + ntiles) serve one segment; within it the
+  // tiles are handed out in arrival order, so every tile's predecessors
+  // belong to blocks that are already running (look-back cannot deadlock)
   if (tid == 0) {
-    s_tile = atomicAdd(&a.tile_ctr[P], 1u);
+    s_seg = seg_of_tile(a, blockIdx.x);
     s_stall = 0;
   }
   if (tid < kPasses) s_triv[tid] = 0;
+  // the other look-back region is used by the next pass: clear one tile
+  a.status[(P + 1) & 1][(size_t)blockIdx.x * kDigits + tid] = 0;
   __syncthreads();
-  const uint32_t gtile = s_tile;
-  if (gtile >= a.ntiles) {  // counters not reset: refuse to touch memory
-    if (tid == 0) atomicOr(a.err, kErrStall);
-    return;
-  }
-  // the other look-back region is used by the next pass: clear our tile
-  a.status[(P + 1) & 1][(size_t)gtile * kDigits + tid] = 0;
-  if (tid == 0) s_seg = seg_of_tile(a, gtile);
-  __syncthreads();
-  const uint32_t sidx = s_seg;
-  const SegDesc& S = seg_desc(a, sidx);
+  const uint32_t sidx = uniform(s_seg);
+  const SegDesc S = seg_desc(a, sidx);
   SegWork* wk = a.work + sidx;
   const uint32_t n = 2u * S.w;
-  const uint32_t ltile = gtile - S.tile_off;
 
   // digits that are constant over the chunk need no pass
+  uint32_t hist_p = 0;
 #pragma unroll
-  for (int d = 0; d <= P; ++d)
-    if (wk->hist[d][tid] == n) s_triv[d] = 1;
+  for (int d = 0; d <= P; ++d) {
+    const uint32_t hv = wk->hist[d][tid];
+    if (hv == n) s_triv[d] = 1;
+    if (d == P) hist_p = hv;
+  }
   __syncthreads();
-  int k = 0;  // non-trivial passes before this one
+  int kk = 0;
 #pragma unroll
-  for (int d = 0; d < P; ++d) k += s_triv[d] ? 0 : 1;
-  if (P == kPasses - 1 && ltile == 0 && tid == 0) {
+  for (int d = 0; d < P; ++d) kk += s_triv[d] ? 0 : 1;
+  const int k = (int)uniform((uint32_t)kk);  // non-trivial passes before this one
+  if (P == kPasses - 1 && blockIdx.x == S.tile_off && tid == 0) {
     const int K = k + (s_triv[P] ? 0 : 1);
     wk->final_buf = (uint32_t)((K + 1) & 1);  // (K - 1) & 1, K >= 1
     const uint64_t span = (uint64_t)wk->maxid + 1;
     wk->dense = span <= (1ull << S.dir_log2) ? 1u : 0u;
   }
-  if (s_triv[P]) return;
+  if (uniform((uint32_t)s_triv[P])) return;
+  if (tid == 0) s_tile = atomicAdd(&wk->tile_ctr[P], 1u);
+  __syncthreads();
+  const uint32_t ltile = uniform(s_tile);
+  if (ltile >= S.ntiles) {  // counters not reset: refuse to touch memory
+    if (tid == 0) atomicOr(a.err, kErrStall);
+    return;
+  }
 
   const uint64_t* src = a.arcs[(k + 1) & 1] + S.arc_off;  // (k-1)&1
   uint64_t* dst = a.arcs[k & 1] + S.arc_off;
@@ -245,16 +303,22 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
 
   // load: wave w owns arcs [w*64*kItems, (w+1)*64*kItems) of the tile,
   // iteration i covers 64 consecutive arcs (original order = (i, lane))
+  // branch-free loads (a clamped index past the ragged end) so that all
+  // kItems loads are in flight together
   uint64_t el[kItems];
   uint32_t rk[kItems];
+  if (k == 0) {
+    const uint32_t* E = S.edges;
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    const uint32_t li = wave * 64 * kItems + i * 64 + lane;
-    const uint32_t gi = base + li;
-    if (li < nv) {
-      el[i] = (k == 0) ? (((uint64_t)S.edges[gi] << 32) | (gi >> 1)) : src[gi];
-    } else {
-      el[i] = 0;
+    for (int i = 0; i < kItems; ++i) {
+      const uint32_t gi = min(base + wave * 64 * kItems + i * 64 + lane, n - 1);
+      el[i] = ((uint64_t)E[gi] << 32) | (gi >> 1);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const uint32_t gi = min(base + wave * 64 * kItems + i * 64 + lane, n - 1);
+      el[i] = src[gi];
     }
   }
   s_wh[wave][lane] = 0;
@@ -263,8 +327,14 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
   s_wh[wave][lane + 192] = 0;
   __syncthreads();
 
-  // stable rank of each arc among equal digits of its wave (ballot match)
+  // stable rank of each arc among equal digits of its wave: a ballot match
+  // finds the lanes sharing the digit; the lowest of them adds the group
+  // size to the wave's bin with a returning LDS atomic (the atomics of the
+  // kItems rounds are issued back to back and land in program order, so
+  // each returns the count of earlier equal digits); the group then reads
+  // the returned base from its leader lane
   const uint64_t lt_mask = (1ull << lane) - 1ull;
+  uint32_t lead[kItems];
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
     const uint32_t li = wave * 64 * kItems + i * 64 + lane;
@@ -278,10 +348,15 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
       mm &= bit ? bb : ~bb;
     }
     const uint32_t below = __popcll(mm & lt_mask);
-    uint32_t prev = 0;
-    if (valid) prev = s_wh[wave][dg];
-    if (valid && below == 0) s_wh[wave][dg] = prev + __popcll(mm);
-    rk[i] = prev + below;
+    lead[i] = (uint32_t)__ffsll((long long)mm) - 1u;  // lowest lane of the group
+    uint32_t base = 0;
+    if (valid && below == 0) base = atomicAdd(&s_wh[wave][dg], (uint32_t)__popcll(mm));
+    rk[i] = base | (below << 16);
+  }
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const uint32_t base = __shfl(rk[i] & 0xFFFFu, (int)lead[i]);
+    rk[i] = base + (rk[i] >> 16);
   }
   __syncthreads();
 
@@ -293,35 +368,51 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
     s_wh[w][tid] = cnt;
     cnt += c;
   }
+  // publish this tile's counts first: successors can fold them meanwhile
+  uint32_t* st = a.status[P & 1] + (size_t)S.tile_off * kDigits;
+  st_relaxed(&st[(size_t)ltile * kDigits + tid],
+             (ltile == 0 ? kFlagInc : kFlagAgg) | cnt);
   uint32_t tot;
   s_loc[tid] = block_excl_scan(cnt, s_tmp, &tot);
-  const uint32_t bin = block_excl_scan(wk->hist[P][tid], s_tmp, &tot);
+  const uint32_t bin = block_excl_scan(hist_p, s_tmp, &tot);
 
   // decoupled look-back over earlier tiles of this segment, per digit
-  uint32_t* st = a.status[P & 1] + (size_t)S.tile_off * kDigits;
   uint32_t excl = 0;
-  if (ltile == 0) {
-    st_relaxed(&st[tid], kFlagInc | cnt);
-  } else {
-    st_relaxed(&st[(size_t)ltile * kDigits + tid], kFlagAgg | cnt);
-    uint32_t j = ltile - 1;
+  if (ltile != 0) {
+    // read kLookback predecessors at once (independent loads), then fold
+    // the published ones nearest-first until an inclusive value
+    uint32_t j = ltile;  // tiles below j are still to be folded
     uint32_t polls = 0;
-    for (;;) {
-      const uint32_t v = ld_relaxed(&st[(size_t)j * kDigits + tid]);
-      const uint32_t f = v & ~kValMask;
-      if (f == 0) {
+    bool done = false;
+    while (!done) {
+      uint32_t v[kLookback];
+#pragma unroll
+      for (int t = 0; t < kLookback; ++t)
+        v[t] = (j > (uint32_t)t) ? ld_relaxed(&st[(size_t)(j - 1 - t) * kDigits + tid])
+                                 : (kFlagInc | 0u);
+      uint32_t used = 0;
+      bool wait = false;
+#pragma unroll
+      for (int t = 0; t < kLookback; ++t) {
+        if (done || wait) continue;
+        const uint32_t f = v[t] & ~kValMask;
+        if (f == 0) {
+          wait = true;
+          continue;
+        }
+        excl += v[t] & kValMask;
+        ++used;
+        if (f == kFlagInc) done = true;
+      }
+      j -= min(used, j);
+      if (!done && used == 0) {
         if (++polls > kSpinLimit) {  // a predecessor never published
           s_stall = 1;
           atomicOr(a.err, kErrStall);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        continue;
       }
-      excl += v & kValMask;
-      if (f == kFlagInc) break;
-      if (j == 0) break;  // tile 0 always publishes an inclusive value
-      --j;
     }
     st_relaxed(&st[(size_t)ltile * kDigits + tid], kFlagInc | (excl + cnt));
   }
@@ -399,8 +490,8 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
   if (tid == 0) s_seg = seg_of_tile(a, gtile);
   __syncthreads();
   if (*a.err & kErrFatal) return;
-  const uint32_t sidx = s_seg;
-  const SegDesc& S = seg_desc(a, sidx);
+  const uint32_t sidx = uniform(s_seg);
+  const SegDesc S = seg_desc(a, sidx);
   const SegWork* wk = a.work + sidx;
   const uint64_t* arc = a.arcs[wk->final_buf] + S.arc_off;
   const uint32_t n = 2u * S.w;
@@ -431,33 +522,62 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
 // ---------------------------------------------------------------------------
 // k_est: Steps 1 and 2 per estimator, Step-3 query posted
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t lower_bound(const uint64_t* v, uint32_t lo,
-                                                uint32_t hi, uint64_t key) {
-  while (lo < hi) {
-    const uint32_t mid = lo + ((hi - lo) >> 1);
-    if (v[mid] < key) lo = mid + 1; else hi = mid;
+// Index of arc (x, p) inside x's segment [lo, hi) of the sorted arcs, whose
+// positions (low 32 bits) ascend.  Positions of a vertex are spread over the
+// batch, so the search interpolates on them; a step that fails to halve the
+// interval is followed by a bisection, which bounds the probes by
+// 2 log2(hi - lo).  Returns hi if p is larger than every position.
+__device__ __forceinline__ uint32_t seg_search(const uint64_t* v, uint32_t lo,
+                                               uint32_t hi, uint32_t p) {
+  if (lo >= hi) return hi;
+  uint32_t plo = (uint32_t)v[lo];
+  uint32_t b = hi - 1;
+  uint32_t pb = (uint32_t)v[b];
+  if (p <= plo) return lo;
+  if (p > pb) return hi;
+  // invariant: pos[lo] < p <= pos[b]
+  bool bisect = false;
+  while (b - lo > 1) {
+    uint32_t g;
+    if (bisect) {
+      g = lo + ((b - lo) >> 1);
+    } else {
+      const float f = (float)(p - plo) / (float)(pb - plo);
+      g = lo + (uint32_t)(f * (float)(b - lo));
+      g = min(max(g, lo + 1), b - 1);
+    }
+    const uint32_t pg = (uint32_t)v[g];
+    const uint32_t before = b - lo;
+    if (pg < p) {
+      lo = g;
+      plo = pg;
+    } else {
+      b = g;
+      pb = pg;
+    }
+    bisect = !bisect && 2 * (b - lo) > before;
   }
-  return lo;
+  return b;
 }
 
-// join (or open) the list of estimators waiting for closing edge q;
-// returns the previous list head (kNone when first).  Only relaxed atomics:
-// the key is the claim word and the head is swapped atomically, so no
-// cross-CU fence (an L2 writeback/invalidate on this chip) is needed.
-__device__ __forceinline__ uint32_t qt_post(QSlot* qt, uint32_t mask,
-                                            uint64_t q, uint32_t est,
-                                            uint32_t* err) {
+// register estimator `est` as waiting for closing edge q at a position
+// >= thr: claim an empty slot of q's probe sequence with one CAS (relaxed:
+// the slot's other fields are read only by the next kernel)
+__device__ __forceinline__ void qt_post(QSlot* qt, uint32_t mask, uint64_t q,
+                                        uint32_t est, uint32_t thr,
+                                        uint32_t* err) {
   uint32_t h = (uint32_t)mix64(q) & mask;
   for (uint32_t probe = 0; probe <= mask; ++probe) {
     unsigned long long* k = reinterpret_cast<unsigned long long*>(&qt[h].key);
-    uint64_t cur = __hip_atomic_load(k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (cur == kEmpty)
-      cur = atomicCAS(k, (unsigned long long)kEmpty, (unsigned long long)q);
-    if (cur == kEmpty || cur == q) return atomicExch(&qt[h].head, est);
+    if (atomicCAS(k, (unsigned long long)kEmpty, (unsigned long long)q) ==
+        kEmpty) {
+      qt[h].est = est;
+      qt[h].thr = thr;
+      return;
+    }
     h = (h + 1) & mask;
   }
   atomicOr(err, kErrProbe);
-  return kNone;
 }
 
 __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
@@ -465,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   if (gid >= a.nest) return;
   if (*a.err & kErrFatal) return;
   const uint32_t sidx = seg_of_est(a, gid);
-  const SegDesc& S = seg_desc(a, sidx);
+  const SegDesc S = seg_desc(a, sidx);
   const SegWork* wk = a.work + sidx;
   const uint32_t i = (uint32_t)(gid - S.gest_off);  // index within the bank
   const uint64_t e = S.est_off + i;
@@ -500,8 +620,8 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
     // f1 is W[j1]: count the arcs after it on each endpoint (the arc of
     // W[j1] itself is always present; the guard only keeps every later
     // index inside the segment)
-    const uint32_t iu = lower_bound(arc, su.x, su.y, ((uint64_t)u << 32) | j1);
-    const uint32_t iv = lower_bound(arc, sv.x, sv.y, ((uint64_t)v << 32) | j1);
+    const uint32_t iu = seg_search(arc, su.x, su.y, j1);
+    const uint32_t iv = seg_search(arc, sv.x, sv.y, j1);
     ld = iu < su.y ? su.y - 1 - iu : 0u;
     rd = iv < sv.y ? sv.y - 1 - iv : 0u;
   } else {
@@ -541,9 +661,8 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
     const uint64_t q = closing(r1, r2);
     if (q != kEmpty) {
       const uint32_t thr = (p2 == kNone) ? 0u : p2 + 1;  // need pos >= thr
-      const uint32_t nxt = qt_post(a.qt + S.qt_off, (1u << S.qt_log2) - 1u, q,
-                                   (uint32_t)e, a.err);
-      a.link[e] = ((uint64_t)nxt << 32) | thr;
+      qt_post(a.qt + S.qt_off, (1u << S.qt_log2) - 1u, q, (uint32_t)e, thr,
+              a.err);
     }
   }
   a.r1[e] = r1;
@@ -555,37 +674,49 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
 // k_probe: Step 3, stream W once; every batch edge that some estimators
 // wait for closes those whose level-2 edge came earlier
 // ---------------------------------------------------------------------------
+constexpr int kProbeEdges = kTile / 2 / kBlock;  // edges per thread
+
 __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
   const uint32_t gtile = blockIdx.x;
   if (tid == 0) s_seg = seg_of_tile(a, gtile);
   __syncthreads();
-  const uint32_t sidx = s_seg;
-  const SegDesc& S = seg_desc(a, sidx);
-  const bool ok = (*a.err & kErrFatal) == 0;
-  const uint32_t ebase = (gtile - S.tile_off) * (kTile / 2);
-  const uint32_t eend = min(ebase + (uint32_t)(kTile / 2), S.w);
-  const uint2* W = reinterpret_cast<const uint2*>(S.edges);
-  const QSlot* qt = a.qt + S.qt_off;
-  const uint32_t mask = (1u << S.qt_log2) - 1u;
-  for (uint32_t j = ebase + tid; ok && j < eend; j += kBlock) {
-    const uint2 ed = W[j];
-    const uint64_t q = canon(ed.x, ed.y);
-    uint32_t h = (uint32_t)mix64(q) & mask;
-    for (uint32_t probe = 0; probe <= mask; ++probe) {
-      const QSlot s = qt[h];
-      if (s.key == kEmpty) break;
-      if (s.key == q) {
-        uint64_t hops = 0;
-        for (uint32_t est = s.head; est != kNone && hops <= a.nest; ++hops) {
-          const uint64_t l = a.link[est];
-          if (j >= (uint32_t)l) atomicOr(&a.cc[est], kClosed);
-          est = (uint32_t)(l >> 32);
-        }
-        break;
+  const uint32_t sidx = uniform(s_seg);
+  const SegDesc S = seg_desc(a, sidx);
+  if ((*a.err & kErrFatal) == 0) {
+    const uint32_t ebase = (gtile - S.tile_off) * (kTile / 2);
+    const uint2* W = reinterpret_cast<const uint2*>(S.edges);
+    const QSlot* qt = a.qt + S.qt_off;
+    const uint32_t mask = (1u << S.qt_log2) - 1u;
+    // issue every load before walking any probe sequence
+    uint64_t q[kProbeEdges];
+    uint32_t h[kProbeEdges];
+#pragma unroll
+    for (int k = 0; k < kProbeEdges; ++k) {
+      const uint32_t j = ebase + k * kBlock + tid;
+      q[k] = kEmpty;
+      if (j < S.w) {
+        const uint2 ed = W[j];
+        q[k] = canon(ed.x, ed.y);
       }
-      h = (h + 1) & mask;
+      h[k] = (uint32_t)mix64(q[k]) & mask;
+    }
+    uint64_t first[kProbeEdges];
+#pragma unroll
+    for (int k = 0; k < kProbeEdges; ++k)
+      first[k] = q[k] == kEmpty ? kEmpty : qt[h[k]].key;
+#pragma unroll
+    for (int k = 0; k < kProbeEdges; ++k) {
+      if (first[k] == kEmpty) continue;  // the usual case: nobody waits
+      const uint32_t j = ebase + k * kBlock + tid;
+      uint32_t hh = h[k];
+      for (uint32_t probe = 0; probe <= mask; ++probe) {
+        const QSlot sl = qt[hh];
+        if (sl.key == kEmpty) break;
+        if (sl.key == q[k] && j >= sl.thr) atomicOr(&a.cc[sl.est], kClosed);
+        hh = (hh + 1) & mask;
+      }
     }
   }
   // this step no longer needs the per-segment work area: reset it
@@ -641,7 +772,7 @@ hipError_t launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
     if (ev) (void)hipEventRecord(ev[k++], st);
   };
   mark();
-  hipLaunchKernelGGL(k_hist, tiles, blk, 0, st, a);
+  hipLaunchKernelGGL(k_hist, dim3(a.nhblk), blk, 0, st, a);
   mark();
   hipLaunchKernelGGL(k_pass<0>, tiles, blk, 0, st, a);
   mark();
