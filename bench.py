@@ -53,7 +53,7 @@ def alg_bytes(kernel: str, w: int, r: int, nontrivial: list) -> float:
     if kernel == "k_dir":
         return arcs * 8.0
     if kernel == "k_est":
-        return r * (20.0 + 20.0 + 8.0)
+        return r * (20.0 + 20.0)
     if kernel == "k_probe":
         return 8.0 * w
     return 0.0
@@ -77,6 +77,125 @@ def cpu_baseline(E_host, r, seed, w, budget_s=12.0):
     return b, nb, dt
 
 
+def batched_comparison(tc, inputs, nstreams=256, ks=(4, 8, 16), replays=3):
+    """Plain (one bank per stream, one launch set per chunk) against batched
+    (every stream's chunk in one launch set per step) and graph replay of the
+    batched steps, on independent streams of uneven length.  Each stream is
+    cut into K batches (w_s = ceil(m_s / K)); K is tuned over `ks` on the
+    batched form.  Returns a dict for the JSON line."""
+    import numpy as np
+    import torch
+    log(f"[bench] generating {nstreams} independent streams on the GPU")
+    streams = inputs.many_streams(nstreams, device="cuda")
+    rs = [s["r"] for s in streams]
+    seeds = [s["seed"] for s in streams]
+    ms = [s["edges"].shape[0] for s in streams]
+    rm_total = float(sum(r * m for r, m in zip(rs, ms)))
+    stream = torch.cuda.current_stream()
+
+    def plan(K):
+        steps = []
+        for k in range(K):
+            ids, chunks = [], []
+            for b, st in enumerate(streams):
+                w = (ms[b] + K - 1) // K
+                c = st["edges"][k * w:(k + 1) * w]
+                if c.shape[0]:
+                    ids.append(b)
+                    chunks.append(c)
+            steps.append((ids, chunks))
+        return steps
+
+    mb = tc.MultiBank(rs, seeds)
+
+    def run_batched(steps):
+        tc.tc_multi_reset(mb.h, stream)
+        for ids, chunks in steps:
+            mb.process(ids, chunks, stream)
+
+    tune = {}
+    for K in ks:
+        steps = plan(K)
+        tc.tc_multi_reserve(mb.h, steps[0][0], [c.shape[0] for c in steps[0][1]])
+        run_batched(steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_batched(steps)
+        torch.cuda.synchronize()
+        tune[K] = rm_total / (time.perf_counter() - t0)
+        log(f"[bench]   K={K}: batched {tune[K]:.3e} r*m/s")
+    K = max(tune, key=tune.get)
+    steps = plan(K)
+    tc.tc_multi_reserve(mb.h, steps[0][0], [c.shape[0] for c in steps[0][1]])
+
+    # batched (eager launches)
+    run_batched(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        run_batched(steps)
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / replays
+    st_batched = [mb.state(b) for b in range(nstreams)]
+
+    # the same steps captured once into a HIP graph, replayed
+    tc.tc_multi_graph_reserve(mb.h, K)
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(stream)
+    with torch.cuda.graph(g, stream=cs):
+        tc.tc_multi_reset(mb.h, cs)
+        for ids, chunks in steps:
+            mb.process(ids, chunks, cs)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / replays
+    graph_same = all(all(np.array_equal(x, y) for x, y in zip(mb.state(b), st_batched[b]))
+                     for b in range(nstreams))
+
+    # plain: one bank per stream, one launch set per chunk
+    banks = []
+    for b in range(nstreams):
+        bk = tc.Bank(rs[b], seeds[b])
+        tc.tc_reserve(bk.h, (ms[b] + K - 1) // K)
+        banks.append(bk)
+
+    def run_plain():
+        for bk in banks:
+            tc.tc_reset(bk.h, stream)
+        for ids, chunks in steps:
+            for b, c in zip(ids, chunks):
+                banks[b].process(c, stream)
+
+    run_plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        run_plain()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / replays
+    plain_same = all(all(np.array_equal(x, y) for x, y in zip(banks[b].state(), st_batched[b]))
+                     for b in range(nstreams))
+    for bk in banks:
+        bk.close()
+    mb.close()
+    return {
+        "workload": f"{nstreams} independent streams, lognormal m in [1e4, 1e7] "
+                    "(median 3e5), even R-MAT scale 16-22, odd Chung-Lu n=m/8 "
+                    "gamma=2.1, r=2^14..2^18 per stream",
+        "total_edges": int(sum(ms)), "total_estimators": int(sum(rs)),
+        "batches_per_stream": K, "tuned": {str(k): v for k, v in tune.items()},
+        "plain_value": rm_total / t_plain, "batched_value": rm_total / t_batched,
+        "graph_value": rm_total / t_graph, "unit": "estimator-edge updates/s",
+        "batched_vs_plain": t_plain / t_batched, "graph_vs_plain": t_plain / t_graph,
+        "identical_results": bool(plain_same and graph_same),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +205,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the steps without events between kernels")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the plain vs batched comparison on many streams")
+    ap.add_argument("--streams", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
@@ -183,6 +305,9 @@ def main():
         "kernel_ms_per_step": {k_: round(v / timed, 4) for k_, v in per_kernel.items()}
         if timed else None,
     }
+
+    if not args.no_batched:
+        out["batched"] = batched_comparison(tc, inputs, nstreams=args.streams)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")

@@ -78,6 +78,11 @@ int tc_process_batch(tc_state *s, const uint32_t *edges, uint32_t w,
  * failure. */
 int tc_reserve(tc_state *s, uint32_t max_w);
 
+/* Enqueue on `stream` a return of every estimator to empty, with |E| = 0
+ * and batch index 0 (as after tc_create).  Uses kernels only, so it may be
+ * captured into a HIP graph ahead of captured steps. */
+int tc_reset(tc_state *s, void *stream);
+
 /* Block until the bank's last enqueued work is done, then return
  * tau_hat = (|E| / r) * S with S = sum_i chi_i * [closed_i] (Lemma 1, mean
  * aggregate).  NaN on error. */
@@ -126,6 +131,19 @@ int tc_multi_process(tc_multi *s, uint32_t nchunks, const uint32_t *bank_ids,
  * would (edge pointers are not needed).  Blocking. */
 int tc_multi_reserve(tc_multi *s, uint32_t nchunks, const uint32_t *bank_ids,
                      const uint32_t *w);
+
+/* Enqueue a reset of every bank (see tc_reset). */
+int tc_multi_reset(tc_multi *s, void *stream);
+
+/* Prepare to capture up to nsteps tc_multi_process calls into a HIP graph:
+ * each captured step gets its own pinned descriptor buffer, left unchanged
+ * so that every replay of the graph reads the step it captured.  Call after
+ * tc_multi_reserve and before capturing; calling it again discards the
+ * buffers of earlier captures (their graphs must not be replayed after).
+ * A captured graph that starts with tc_multi_reset replays the same
+ * computation every time; without the reset each replay continues the
+ * banks with the captured batch indices. */
+int tc_multi_graph_reserve(tc_multi *s, uint32_t nsteps);
 
 /* Blocking; per-bank S, |E| and tau_hat into HOST arrays of length nbanks
  * (any may be NULL). */

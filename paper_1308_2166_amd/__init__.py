@@ -74,6 +74,9 @@ def lib():
         "tc_multi_num_banks": ([vp], u32),
         "tc_multi_destroy": ([vp], None),
         "tc_reserve": ([vp, u32], i32),
+        "tc_reset": ([vp, vp], i32),
+        "tc_multi_reset": ([vp, vp], i32),
+        "tc_multi_graph_reserve": ([vp, u32], i32),
         "tc_multi_reserve": ([vp, u32, vp, vp], i32),
         "tc_set_kernel_timing": ([vp, i32], i32),
         "tc_kernel_times": ([vp, vp, P64], i32),
@@ -96,7 +99,8 @@ EXPORTS = ("tc_create", "tc_process_batch", "tc_estimate", "tc_estimate_ex",
            "tc_multi_sync", "tc_multi_num_banks", "tc_multi_destroy",
            "tc_set_kernel_timing", "tc_kernel_times", "tc_multi_set_kernel_timing",
            "tc_multi_kernel_times", "tc_num_kernels", "tc_kernel_name",
-           "tc_reserve", "tc_multi_reserve")
+           "tc_reserve", "tc_multi_reserve", "tc_reset", "tc_multi_reset",
+           "tc_multi_graph_reserve")
 
 
 def _check(rc: int):
@@ -141,6 +145,10 @@ def tc_process_batch(state: int, edges, w: int | None = None, stream=None) -> No
 
 def tc_reserve(state: int, max_w: int) -> None:
     _check(lib().tc_reserve(state, max_w))
+
+
+def tc_reset(state: int, stream=None) -> None:
+    _check(lib().tc_reset(state, _stream_handle(stream)))
 
 
 def tc_estimate(state: int) -> float:
@@ -248,6 +256,14 @@ def tc_multi_reserve(multi: int, bank_ids, ws) -> None:
     ids = np.ascontiguousarray(bank_ids, dtype=np.uint32)
     w = np.ascontiguousarray(ws, dtype=np.uint32)
     _check(lib().tc_multi_reserve(multi, len(ids), ids.ctypes.data, w.ctypes.data))
+
+
+def tc_multi_reset(multi: int, stream=None) -> None:
+    _check(lib().tc_multi_reset(multi, _stream_handle(stream)))
+
+
+def tc_multi_graph_reserve(multi: int, nsteps: int) -> None:
+    _check(lib().tc_multi_graph_reserve(multi, nsteps))
 
 
 def tc_multi_estimate(multi: int):

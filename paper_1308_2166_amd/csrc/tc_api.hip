@@ -86,6 +86,7 @@ struct Engine {
   uint64_t* bank_off = nullptr;  // device copy of est_off
   unsigned long long* sums = nullptr;
   uint32_t* err = nullptr;
+  uint32_t* tagp = nullptr;  // directory tag of the next step (device)
   unsigned long long* h_sums = nullptr;  // pinned
   uint32_t* h_err = nullptr;             // pinned
 
@@ -107,8 +108,12 @@ struct Engine {
   uint32_t stage_cap = 0;
   int ring = 0;
 
-  uint32_t tag = 0;
+  uint64_t steps = 0;  // steps enqueued (tag wrap guard)
   hipStream_t last = nullptr;
+  // descriptor staging for steps captured into a HIP graph: one pinned
+  // buffer per captured step, kept unchanged so every replay reads it
+  std::vector<SegDesc*> graph_stage;
+  size_t graph_next = 0;
   int sticky = TC_OK;
 
   // optional per-kernel timing: one set of kNumKernels+1 events per step
@@ -130,7 +135,9 @@ struct Engine {
     ev_pending.clear();
     ev_free.clear();
     dfree(R1), dfree(R2), dfree(CC), dfree(bank_off);
-    dfree(sums), dfree(err);
+    dfree(sums), dfree(err), dfree(tagp);
+    for (SegDesc* g : graph_stage) (void)hipHostFree(g);
+    graph_stage.clear();
     if (h_sums) (void)hipHostFree(h_sums);
     if (h_err) (void)hipHostFree(h_err);
     h_sums = nullptr, h_err = nullptr;
@@ -169,7 +176,7 @@ struct Engine {
       return fail(TC_EINVAL, "too many estimators in one object (max 2^31-2)");
     if (dalloc(&R1, total) || dalloc(&R2, total) || dalloc(&CC, total) ||
         dalloc(&bank_off, n + 1) ||
-        dalloc(&sums, n) || dalloc(&err, 1))
+        dalloc(&sums, n) || dalloc(&err, 1) || dalloc(&tagp, 1))
       return fail(TC_ENOMEM, "device allocation of the estimator banks failed");
     if (hipHostMalloc(reinterpret_cast<void**>(&h_sums), sizeof(uint64_t) * n) ||
         hipHostMalloc(reinterpret_cast<void**>(&h_err), sizeof(uint32_t)))
@@ -178,6 +185,7 @@ struct Engine {
         launch_fill64(R2, total, kEmpty, nullptr) ||
         launch_fill32(CC, total, 0, nullptr) ||
         launch_fill32(err, 1, 0, nullptr) ||
+        launch_fill32(tagp, 1, 1, nullptr) ||
         hipMemcpy(bank_off, est_off.data(), sizeof(uint64_t) * (n + 1),
                   hipMemcpyHostToDevice) ||
         hipDeviceSynchronize())
@@ -218,8 +226,20 @@ struct Engine {
     return TC_OK;
   }
 
-  int stage_descs(const std::vector<SegDesc>& segs, hipStream_t st) {
+  int stage_descs(const std::vector<SegDesc>& segs, hipStream_t st,
+                  bool capturing) {
     const uint32_t n = (uint32_t)segs.size();
+    if (capturing) {
+      if (graph_next >= graph_stage.size())
+        return fail(TC_EINVAL, "more captured steps than tc_multi_graph_reserve allowed");
+      if (n > nbanks) return fail(TC_EINVAL, "too many chunks");
+      SegDesc* buf = graph_stage[graph_next++];
+      std::memcpy(buf, segs.data(), sizeof(SegDesc) * n);
+      if (hipMemcpyAsync(segs_dev, buf, sizeof(SegDesc) * n,
+                         hipMemcpyHostToDevice, st))
+        return fail(TC_EHIP, "descriptor upload failed");
+      return TC_OK;
+    }
     if (n > stage_cap) {
       for (int i = 0; i < kRing; ++i) {
         if (stage_used[i]) (void)hipEventSynchronize(stage_ev[i]);
@@ -293,13 +313,16 @@ struct Engine {
     if (tiles >= 0x7FFFFFFFull) return fail(TC_EINVAL, "step too large");
     int rc = ensure_scratch(arcs_n, tiles, dir_n, qt_n, (uint32_t)segs.size(), st);
     if (rc || reserve) return rc;
-    if (tag >= kTagMax) {
-      // tags wrapped: forget every table entry
-      if (hipMemsetAsync(dir, 0, sizeof(DirSlot) * cap_dir, st))
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess)
+      return fail(TC_EHIP, "hipStreamIsCapturing failed");
+    const bool capturing = cap == hipStreamCaptureStatusActive;
+    if (capturing && timing) return fail(TC_EINVAL, "kernel timing is on while capturing");
+    if (++steps % 0xFFFF0000ull == 0 && !capturing) {
+      // directory tags are about to wrap: forget every entry (fill, not memset)
+      if (launch_fill32(reinterpret_cast<uint32_t*>(dir), cap_dir * 4, 0, st))
         return fail(TC_EHIP, "table reset failed");
-      tag = 0;
     }
-    ++tag;
     StepArgs a{};
     a.nseg = (uint32_t)segs.size();
     a.segs = segs_dev;
@@ -307,7 +330,7 @@ struct Engine {
     a.ntiles = (uint32_t)tiles;
     a.nhblk = (uint32_t)hblks;
     a.nest = nest;
-    a.tag = tag;
+    a.tagp = tagp;
     a.r1 = R1, a.r2 = R2, a.cc = CC;
     a.work = work;
     a.arcs[0] = arcs[0], a.arcs[1] = arcs[1];
@@ -317,7 +340,7 @@ struct Engine {
     a.qt_slots = qt_n;
     a.err = err;
     if (a.nseg > 1) {
-      rc = stage_descs(segs, st);
+      rc = stage_descs(segs, st, capturing);
       if (rc) return rc;
     }
     hipEvent_t* ev = nullptr;
@@ -339,6 +362,30 @@ struct Engine {
       batch[ids[k]] += 1;
     }
     last = st;
+    return TC_OK;
+  }
+
+  // every bank back to empty, |E| = 0, batch 0 (fill kernels only, so a
+  // reset can be captured into a graph ahead of captured steps)
+  int reset(hipStream_t st) {
+    if (launch_fill64(R1, total, kEmpty, st) || launch_fill64(R2, total, kEmpty, st) ||
+        launch_fill32(CC, total, 0, st))
+      return fail(TC_EHIP, "bank reset failed");
+    std::fill(m.begin(), m.end(), 0);
+    std::fill(batch.begin(), batch.end(), 0);
+    last = st;
+    return TC_OK;
+  }
+
+  int graph_reserve(uint32_t nsteps) {
+    if (last) (void)hipStreamSynchronize(last);
+    for (SegDesc* g : graph_stage) (void)hipHostFree(g);
+    graph_stage.assign(nsteps, nullptr);
+    graph_next = 0;
+    for (uint32_t i = 0; i < nsteps; ++i)
+      if (hipHostMalloc(reinterpret_cast<void**>(&graph_stage[i]),
+                        sizeof(SegDesc) * nbanks))
+        return fail(TC_ENOMEM, "pinned descriptor staging failed");
     return TC_OK;
   }
 
@@ -451,6 +498,11 @@ int tc_reserve(tc_state* s, uint32_t max_w) {
   const uint32_t id = 0;
   const uint32_t* none = nullptr;
   return s->e.step(1, &id, &none, &max_w, nullptr, true);
+}
+
+int tc_reset(tc_state* s, void* stream) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  return s->e.reset(static_cast<hipStream_t>(stream));
 }
 
 int tc_estimate_ex(tc_state* s, uint64_t* S, uint64_t* m, double* tau) {
@@ -570,6 +622,16 @@ int tc_multi_reserve(tc_multi* s, uint32_t nchunks, const uint32_t* bank_ids,
   if (!bank_ids || !w) return fail(TC_EINVAL, "null chunk arrays");
   std::vector<const uint32_t*> none(nchunks, nullptr);
   return s->e.step(nchunks, bank_ids, none.data(), w, nullptr, true);
+}
+
+int tc_multi_reset(tc_multi* s, void* stream) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  return s->e.reset(static_cast<hipStream_t>(stream));
+}
+
+int tc_multi_graph_reserve(tc_multi* s, uint32_t nsteps) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  return s->e.graph_reserve(nsteps);
 }
 
 int tc_multi_estimate(tc_multi* s, uint64_t* S, uint64_t* m, double* tau) {

@@ -30,7 +30,6 @@ constexpr uint32_t kClosed = 0x80000000u;
 constexpr uint32_t kChiMax = 0x7FFFFFFFu;
 
 // tagged directory: a slot is live only if its tag equals the step's tag
-constexpr uint32_t kTagMax = 0x7FFFFFFFu;
 
 // sticky device error bits
 constexpr uint32_t kErrSelfLoop = 1u;
@@ -99,7 +98,8 @@ struct StepArgs {
   uint32_t ntiles;        // total tiles over segments
   uint32_t nhblk;         // total k_hist blocks over segments
   uint64_t nest;          // total estimator threads over segments
-  uint32_t tag;           // this step's table tag (1 .. kTagMax)
+  uint32_t* tagp;         // device word: this step's directory tag (never 0);
+                          // advanced by the step's last kernel
   // estimator state (all banks)
   uint64_t* r1;
   uint64_t* r2;

@@ -500,6 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
   DirSlot* dir = a.dir + S.dir_off;
   const bool dense = wk->dense != 0;
   const uint32_t mask = (1u << S.dir_log2) - 1u;
+  const uint32_t tag = uniform(*a.tagp);
   for (uint32_t i = base + tid; i < end; i += kBlock) {
     const uint32_t x = (uint32_t)(arc[i] >> 32);
     const bool head = i == 0 || (uint32_t)(arc[i - 1] >> 32) != x;
@@ -509,9 +510,9 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
     if (dense) {
       if (x > mask) continue;  // cannot happen: x <= max id < 2^dir_log2
       slot = x;
-      *reinterpret_cast<uint2*>(&dir[x]) = make_uint2(x, a.tag);
+      *reinterpret_cast<uint2*>(&dir[x]) = make_uint2(x, tag);
     } else {
-      slot = dir_claim(dir, mask, x, a.tag, a.err);
+      slot = dir_claim(dir, mask, x, tag, a.err);
       if (slot == kNone) continue;
     }
     if (head) dir[slot].start = i;
@@ -612,8 +613,9 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   // Step 2 (Sec. 4.3): chi+ = rank(u->v) + rank(v->u) with u < v
   const uint32_t u = (uint32_t)(r1 >> 32), v = (uint32_t)r1;
   const bool dense = wk->dense != 0;
-  const uint2 su = dir_find(a.dir + S.dir_off, S.dir_log2, dense, u, a.tag);
-  const uint2 sv = dir_find(a.dir + S.dir_off, S.dir_log2, dense, v, a.tag);
+  const uint32_t tag = *a.tagp;
+  const uint2 su = dir_find(a.dir + S.dir_off, S.dir_log2, dense, u, tag);
+  const uint2 sv = dir_find(a.dir + S.dir_off, S.dir_log2, dense, v, tag);
   const uint64_t* arc = a.arcs[wk->final_buf] + S.arc_off;
   uint32_t ld, rd;
   if (j1 != kNone) {
@@ -718,6 +720,11 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
         hh = (hh + 1) & mask;
       }
     }
+  }
+  // the next step's directory entries get a fresh tag (0 means empty)
+  if (gtile == 0 && tid == 0) {
+    const uint32_t t = *a.tagp + 1u;
+    *a.tagp = t ? t : 1u;
   }
   // this step no longer needs the per-segment work area: reset it
   const uint32_t words = a.nseg * (uint32_t)(sizeof(SegWork) / 4);

@@ -233,3 +233,43 @@ def lognormal_sizes(k: int, seed: int, median: float = 3e5, sigma: float = 1.2,
     z = torch.sqrt(-2.0 * torch.log(u1)) * torch.cos(2.0 * math.pi * u2)
     return [int(v) for v in torch.clamp(torch.exp(math.log(median) + sigma * z),
                                         lo, hi).round().tolist()]
+
+
+def _uniform_ints(seed: int, tag: int, k: int, lo: int, hi: int):
+    """k seeded integers uniform on [lo, hi]."""
+    h = _stream(seed, tag, 0, k, "cpu")
+    return [lo + int(v) for v in _below(_lsr(h, 32), hi - lo + 1).tolist()]
+
+
+def many_streams(nstreams: int = 256, seed: int = 404, device="cpu",
+                 size_scale: float = 1.0):
+    """Independent streams of uneven length for the batched form.
+
+    Stream lengths are lognormal (median 3e5, sigma 1.2, clipped to
+    [1e4, 1e7]; `size_scale` shrinks them for tests).  Even-indexed streams
+    are R-MAT with scale ~ U{16..22} (raised until m/n <= 16), odd-indexed
+    ones Chung-Lu with n = m/8 and degree exponent 2.1.  Each stream has its
+    own bank of r = 2^U{14..18} estimators and its own seed.
+    """
+    sizes = lognormal_sizes(nstreams, seed)
+    scales = _uniform_ints(seed, 12, nstreams, 16, 22)
+    rlog = _uniform_ints(seed, 13, nstreams, 14, 18)
+    out = []
+    for s in range(nstreams):
+        m = max(64, int(sizes[s] * size_scale))
+        gseed = hash64_int(seed * 1000003 + s) & 0x7FFFFFFF
+        if s % 2 == 0:
+            sc = scales[s]
+            while m > 16 * (1 << sc):
+                sc += 1
+            e = rmat(sc, m, seed=gseed, device=device)
+            kind = f"rmat{sc}"
+        else:
+            n = max(64, m // 8)
+            e = chung_lu(n, m, seed=gseed, device=device)
+            kind = f"chunglu{n}"
+        r = 1 << rlog[s]
+        if size_scale < 1.0:
+            r = max(16, int(r * size_scale))
+        out.append({"edges": e, "r": r, "seed": gseed ^ 0x5A5A, "kind": kind})
+    return out

@@ -272,3 +272,91 @@ def test_rmat24_first_batches(tc):
     del G
     torch.cuda.empty_cache()
     run_both(tc, E, r, seed, w)
+
+
+# -- reset and HIP-graph replay ---------------------------------------------------------
+
+def test_reset_gives_a_fresh_bank(tc):
+    E = np_edges(inputs.gnm(500, 6000, seed=12))
+    dev = to_dev(E)
+    g = tc.Bank(3000, 21)
+    for j in range(0, 6000, 1500):
+        g.process(dev[j:j + 1500])
+    tc.tc_reset(g.h)
+    assert g.m == 0 and g.batch == 0
+    for j in range(0, 6000, 2000):
+        g.process(dev[j:j + 2000])
+    o = O.run_stream(E, 3000, 21, 2000)
+    assert_same(g.state(), o.state(), "after reset")
+
+
+def _graph_workload(tc, nb=5, K=4):
+    streams = [np_edges(inputs.rmat(11 + b % 3, 3000 + 2000 * b, seed=60 + b)) for b in range(nb)]
+    rs = [500 + 700 * b for b in range(nb)]
+    seeds = [70 + b for b in range(nb)]
+    devs = [to_dev(E) for E in streams]
+    steps = []
+    for k in range(K):
+        ids, chunks = [], []
+        for b, E in enumerate(streams):
+            w = (len(E) + K - 1) // K
+            if k * w < len(E):
+                ids.append(b)
+                chunks.append(devs[b][k * w:(k + 1) * w])
+        steps.append((ids, chunks))
+    return streams, rs, seeds, steps, K
+
+
+def test_graph_replay_matches_eager(tc):
+    streams, rs, seeds, steps, K = _graph_workload(tc)
+    mb = tc.MultiBank(rs, seeds)
+    tc.tc_multi_reserve(mb.h, steps[0][0], [c.shape[0] for c in steps[0][1]])
+    st = torch.cuda.current_stream()
+    tc.tc_multi_reset(mb.h, st)
+    for ids, chunks in steps:
+        mb.process(ids, chunks, st)
+    eager = [mb.state(b) for b in range(len(rs))]
+    for b, E in enumerate(streams):  # eager == the oracle
+        o = O.run_stream(E, rs[b], seeds[b], (len(E) + K - 1) // K)
+        assert_same(eager[b], o.state(), f"eager bank {b}")
+
+    tc.tc_multi_graph_reserve(mb.h, K)
+    gr = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(st)
+    with torch.cuda.graph(gr, stream=cs):
+        tc.tc_multi_reset(mb.h, cs)
+        for ids, chunks in steps:
+            mb.process(ids, chunks, cs)
+    other = tc.Bank(900, 5)
+    filler = to_dev(np_edges(inputs.gnm(300, 4000, seed=13)))
+    for rep in range(3):
+        gr.replay()
+        torch.cuda.synchronize()
+        for b in range(len(rs)):
+            assert_same(mb.state(b), eager[b], f"replay {rep} bank {b}")
+        # the program's own eager work between replays
+        other.process(filler[rep * 1000:(rep + 1) * 1000])
+        _ = (filler.float() * 2).sum().item()
+        torch.cuda.synchronize()
+
+
+def test_graph_replay_single_bank(tc):
+    E = np_edges(inputs.rmat(13, 20000, seed=14))
+    dev = to_dev(E)
+    mb = tc.MultiBank([4000], [31])
+    tc.tc_multi_reserve(mb.h, [0], [5000])
+    tc.tc_multi_graph_reserve(mb.h, 4)
+    gr = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(gr, stream=cs):
+        tc.tc_multi_reset(mb.h, cs)
+        for j in range(0, 20000, 5000):
+            mb.process([0], [dev[j:j + 5000]], cs)
+    o = O.run_stream(E, 4000, 31, 5000)
+    for rep in range(3):
+        gr.replay()
+        torch.cuda.synchronize()
+        assert_same(mb.state(0), o.state(), f"replay {rep}")
+        _ = torch.ones(1000, device="cuda").sum().item()
