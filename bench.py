@@ -196,6 +196,90 @@ def batched_comparison(tc, inputs, nstreams=256, ks=(4, 8, 16), replays=3):
     }
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1308_2166_amd", "csrc", "tc_kernels.hip")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_rmat20.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _short(name: str) -> str:
+    import re
+    n = re.sub(r"\(.*", "", name).replace("void ", "").replace("tc::", "")
+    return n.strip()
+
+
+def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command):
+    """Turn rocprofv3 CSV output of this benchmark into the committed
+    summaries: per-kernel average duration (kernel trace) and per-kernel HBM
+    traffic from FETCH_SIZE / WRITE_SIZE, each scaled by what the counter
+    reads for the calibration copy of calib_mib MiB."""
+    import csv
+    import glob
+    import statistics as stt
+
+    def rows(d, pattern):
+        f = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+        if not f:
+            raise FileNotFoundError(f"{pattern} under {d}")
+        with open(f[0]) as fh:
+            return list(csv.DictReader(fh))
+
+    durs = {}
+    for r in rows(trace_dir, "*kernel_trace.csv"):
+        durs.setdefault(_short(r["Kernel_Name"]), []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    ctr = {}
+    for d, name in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        for r in rows(d, "*counter_collection.csv"):
+            if r["Counter_Name"] == name:
+                ctr.setdefault((_short(r["Kernel_Name"]), name), []).append(
+                    float(r["Counter_Value"]))
+    copy = [k for (k, n) in ctr if "copyBuffer" in k and n == "FETCH_SIZE"]
+    calib_bytes = calib_mib * 2**20
+    fcopy = max(ctr[(copy[0], "FETCH_SIZE")]) if copy else None
+    wcopy = max(ctr[(copy[0], "WRITE_SIZE")]) if copy else None
+    ff = calib_bytes / (fcopy * 1024) if fcopy else None
+    fw = calib_bytes / (wcopy * 1024) if wcopy else None
+    kernels = [k for k in durs if k.startswith("k_")]
+    order = ["k_hist", "k_pass<0>", "k_pass<1>", "k_pass<2>", "k_pass<3>",
+             "k_dir", "k_est", "k_probe"]
+    kernels.sort(key=lambda k: order.index(k) if k in order else 99)
+    per = {}
+    lines = ["| kernel | launches | avg us | min us | max us | FETCH KiB/launch | WRITE KiB/launch | HBM bytes/launch (calibrated) |",
+             "|---|---|---|---|---|---|---|---|"]
+    for k in kernels:
+        d = durs[k]
+        fk = stt.mean(ctr.get((k, "FETCH_SIZE"), [float("nan")]))
+        wk = stt.mean(ctr.get((k, "WRITE_SIZE"), [float("nan")]))
+        tb = fk * 1024 * ff + wk * 1024 * fw if ff and fw else None
+        per[k] = {"launches": len(d), "avg_us": stt.mean(d), "fetch_kib": fk,
+                  "write_kib": wk, "hbm_bytes": tb}
+        lines.append(f"| {k} | {len(d)} | {stt.mean(d):.2f} | {min(d):.2f} | {max(d):.2f} | "
+                     f"{fk:.0f} | {wk:.0f} | {tb:.4g} |" if tb else
+                     f"| {k} | {len(d)} | {stt.mean(d):.2f} | {min(d):.2f} | {max(d):.2f} | "
+                     f"{fk:.0f} | {wk:.0f} | n/a |")
+    os.makedirs(out_dir, exist_ok=True)
+    rec = {"kernel_source_sha256_16": kernel_source_hash(), "calib_copy_mib": calib_mib,
+           "fetch_factor": ff, "write_factor": fw, "per_kernel": per,
+           "command": command}
+    with open(os.path.join(out_dir, "traffic_rmat20.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    with open(os.path.join(out_dir, "step_kernels_rmat20.md"), "w") as f:
+        f.write("# Step kernels, R-MAT scale 20 (r=2^20, w=2^22), plain form\n\n")
+        f.write("Commands (run from the repository root on one MI355X):\n\n```\n"
+                + command + "\n```\n\n")
+        f.write(f"Calibration: a {calib_mib} MiB device copy (`__amd_rocclr_copyBuffer`) "
+                f"reads FETCH_SIZE {fcopy} KiB and WRITE_SIZE {wcopy} KiB; "
+                f"scale factors {ff:.4f} (fetch) and {fw:.4f} (write) convert the "
+                "counters to bytes.\n\n" if ff and fw else "No calibration copy found.\n\n")
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps(rec, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,7 +292,16 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the plain vs batched comparison on many streams")
     ap.add_argument("--streams", type=int, default=256)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this size first (profiler calibration)")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
+                    help="summarize rocprofv3 CSV dirs of this benchmark into profiles/")
+    ap.add_argument("--summary-command", default="")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(*args.summarize, calib_mib=args.calib_copy_mib,
+                  out_dir=os.path.join(ROOT, "profiles"), command=args.summary_command)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
               "the multi-GPU sharding is a design note, not built", file=sys.stderr)
@@ -222,6 +315,16 @@ def main():
 
     torch.cuda.set_device(0)
     tc.lib()
+    if args.calib_copy_mib:
+        # a cold source: the copied first quarter was written before three
+        # more quarters pushed it out of the 256 MB memory-side cache
+        n = args.calib_copy_mib << 20
+        big = torch.ones(4 * n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty(n, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        dst.copy_(big[:n])
+        torch.cuda.synchronize()
+        del big, dst
     log(f"[bench] generating {args.workload} on the GPU")
     G, r, w, seed = inputs.workload(args.workload, device="cuda")
     G = G.contiguous()
@@ -288,6 +391,15 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                     "kernel": dom, "avg_launch_us": round(avg_ms * 1e3, 2),
                     "alg_bytes_per_launch": ab}
+        try:
+            with open(TRAFFIC_JSON) as f:
+                rec = json.load(f)
+            if (args.workload == "rmat20"
+                    and rec["kernel_source_sha256_16"] == kernel_source_hash()
+                    and rec["per_kernel"].get(dom, {}).get("hbm_bytes")):
+                roofline["traffic"] = rec["per_kernel"][dom]["hbm_bytes"]
+        except (OSError, KeyError, ValueError):
+            pass
         step_alg = sum(alg_bytes(k_, w, r, nontrivial) for k_ in per_kernel)
         roofline["step_alg_bytes"] = step_alg
         roofline["step_alg_GBs"] = round(step_alg / (dt / steps) / 1e9, 1)
