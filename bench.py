@@ -280,6 +280,70 @@ def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command):
     print(json.dumps(rec, indent=1))
 
 
+def served_comparison(tc, inputs, nstreams=1024, ngraphs=64, r=1 << 16,
+                      loads=(0.5, 0.9), tight_slots=256):
+    """Continuous batching of Poisson-arriving chunks (1K-1M pairs) from
+    `nstreams` streams (each replays one of `ngraphs` resident graphs with
+    its own estimator seed); banks of r estimators.  Capacity is measured
+    with every chunk available at time 0; then arrivals are paced at each
+    load fraction of it, and once with a budget of only `tight_slots`
+    resident banks.  Reports ingest latency p50/p99 and throughput."""
+    import numpy as np
+    import torch
+    from paper_1308_2166_amd import serve
+    log(f"[bench] serving: generating {ngraphs} graphs for {nstreams} streams")
+    pool = inputs.many_streams(ngraphs, seed=505, device="cuda")
+    graphs = [pool[s % ngraphs]["edges"] for s in range(nstreams)]
+    seeds = [(0x9E3779B97F4A7C15 * (s + 1)) & ((1 << 63) - 1) for s in range(nstreams)]
+    chunks = serve.chunk_streams(graphs, seed=6)
+    nchunks = sum(len(c) for c in chunks)
+    total_w = sum(int(c.shape[0]) for cs in chunks for c in cs)
+    mean_chunk = total_w / nchunks
+    budget = 200 << 30
+    slots = min(nstreams, serve.slots_for_budget(budget, r, reserve_bytes=64 << 30))
+    servers = {}
+
+    def run(rate, nslots, seed):
+        srv = servers.get(nslots) or servers.setdefault(nslots, serve.Server(slots=nslots, r=r))
+        lat, res, el, rw = srv.run(serve.poisson_arrivals(chunks, rate, seed), seeds)
+        lat = np.array(lat) * 1e3
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "value": rw / el, "elapsed_s": el}, res
+
+    log("[bench]   capacity run")
+    run(0.0, slots, 1)
+    cap, res_cap = run(0.0, slots, 1)
+    capacity = cap["value"]
+    out = {"workload": f"{nstreams} streams replaying {ngraphs} R-MAT/Chung-Lu graphs, "
+                       f"chunks log-uniform in [1e3, 1e6] pairs, Poisson arrivals, r={r}",
+           "chunks": nchunks, "edges": total_w, "budget_bytes": budget, "slots": slots,
+           "capacity": capacity, "unit": "estimator-edge updates/s", "loads": []}
+    for f in loads:
+        rate = f * capacity / (r * mean_chunk)
+        log(f"[bench]   load {f:.0%}")
+        d, res = run(rate, slots, 2)
+        d["load"] = f
+        out["loads"].append(d)
+    log(f"[bench]   tight budget: {tight_slots} slots")
+    run(0.0, tight_slots, 1)  # warm-up of this server's scratch
+    d, res_t = run(0.5 * capacity / (r * mean_chunk), tight_slots, 3)
+    d["load"], d["slots"] = 0.5, tight_slots
+    out["tight_budget"] = d
+    same = all((res_cap[s].S, res_cap[s].m) == (res_t[s].S, res_t[s].m) for s in range(nstreams))
+    # a sample of streams alone, through the plain entry point
+    for s in range(0, nstreams, max(1, nstreams // 16)):
+        b = tc.Bank(r, seeds[s])
+        for c in chunks[s]:
+            b.process(c)
+        S, m, _ = tc.tc_estimate_ex(b.h)
+        b.close()
+        same = same and (S, m) == (res_cap[s].S, res_cap[s].m)
+    out["identical_results"] = bool(same)
+    for srv in servers.values():
+        srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +356,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the plain vs batched comparison on many streams")
     ap.add_argument("--streams", type=int, default=256)
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the continuous-batching serving run")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (profiler calibration)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
@@ -420,6 +486,9 @@ def main():
 
     if not args.no_batched:
         out["batched"] = batched_comparison(tc, inputs, nstreams=args.streams)
+
+    if not args.no_served:
+        out["served"] = served_comparison(tc, inputs)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")

@@ -135,6 +135,11 @@ int tc_multi_reserve(tc_multi *s, uint32_t nchunks, const uint32_t *bank_ids,
 /* Enqueue a reset of every bank (see tc_reset). */
 int tc_multi_reset(tc_multi *s, void *stream);
 
+/* Enqueue a restart of bank `bank` as an empty bank with a new seed (|E| = 0,
+ * batch index 0; its size r stays).  Lets a serving loop hand a bank slot
+ * to a new stream once the previous stream is finished and read out. */
+int tc_multi_assign(tc_multi *s, uint32_t bank, uint64_t seed, void *stream);
+
 /* Prepare to capture up to nsteps tc_multi_process calls into a HIP graph:
  * each captured step gets its own pinned descriptor buffer, left unchanged
  * so that every replay of the graph reads the step it captured.  Call after

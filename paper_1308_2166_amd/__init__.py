@@ -77,6 +77,7 @@ def lib():
         "tc_reset": ([vp, vp], i32),
         "tc_multi_reset": ([vp, vp], i32),
         "tc_multi_graph_reserve": ([vp, u32], i32),
+        "tc_multi_assign": ([vp, u32, u64, vp], i32),
         "tc_multi_reserve": ([vp, u32, vp, vp], i32),
         "tc_set_kernel_timing": ([vp, i32], i32),
         "tc_kernel_times": ([vp, vp, P64], i32),
@@ -100,7 +101,7 @@ EXPORTS = ("tc_create", "tc_process_batch", "tc_estimate", "tc_estimate_ex",
            "tc_set_kernel_timing", "tc_kernel_times", "tc_multi_set_kernel_timing",
            "tc_multi_kernel_times", "tc_num_kernels", "tc_kernel_name",
            "tc_reserve", "tc_multi_reserve", "tc_reset", "tc_multi_reset",
-           "tc_multi_graph_reserve")
+           "tc_multi_graph_reserve", "tc_multi_assign")
 
 
 def _check(rc: int):
@@ -260,6 +261,10 @@ def tc_multi_reserve(multi: int, bank_ids, ws) -> None:
 
 def tc_multi_reset(multi: int, stream=None) -> None:
     _check(lib().tc_multi_reset(multi, _stream_handle(stream)))
+
+
+def tc_multi_assign(multi: int, bank: int, seed: int, stream=None) -> None:
+    _check(lib().tc_multi_assign(multi, bank, seed & ((1 << 64) - 1), _stream_handle(stream)))
 
 
 def tc_multi_graph_reserve(multi: int, nsteps: int) -> None:

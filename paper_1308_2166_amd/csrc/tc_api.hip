@@ -377,6 +377,20 @@ struct Engine {
     return TC_OK;
   }
 
+  // bank b starts over as an empty bank with a new seed (kernels only)
+  int assign(uint32_t b, uint64_t new_seed, hipStream_t st) {
+    const uint64_t off = est_off[b], n = r[b];
+    if (launch_fill64(R1 + off, n, kEmpty, st) || launch_fill64(R2 + off, n, kEmpty, st) ||
+        launch_fill32(CC + off, n, 0, st))
+      return fail(TC_EHIP, "bank reset failed");
+    seed[b] = new_seed;
+    key0[b] = host_mix64(new_seed ^ kGolden);
+    m[b] = 0;
+    batch[b] = 0;
+    last = st;
+    return TC_OK;
+  }
+
   int graph_reserve(uint32_t nsteps) {
     if (last) (void)hipStreamSynchronize(last);
     for (SegDesc* g : graph_stage) (void)hipHostFree(g);
@@ -627,6 +641,12 @@ int tc_multi_reserve(tc_multi* s, uint32_t nchunks, const uint32_t* bank_ids,
 int tc_multi_reset(tc_multi* s, void* stream) {
   if (!s) return fail(TC_EINVAL, "null object");
   return s->e.reset(static_cast<hipStream_t>(stream));
+}
+
+int tc_multi_assign(tc_multi* s, uint32_t bank, uint64_t seed, void* stream) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  if (bank >= s->e.nbanks) return fail(TC_EINVAL, "bank id out of range");
+  return s->e.assign(bank, seed, static_cast<hipStream_t>(stream));
 }
 
 int tc_multi_graph_reserve(tc_multi* s, uint32_t nsteps) {

@@ -1,0 +1,187 @@
+"""Continuous-batching ingest of many edge streams on one GPU.
+
+A request is one chunk of one stream: a batch of that stream's edges,
+already resident in device memory.  The loop
+
+* admits a stream (gives it a bank slot of r estimators) when its first
+  chunk arrives and the memory budget has a free slot; later streams wait;
+* keeps every admitted stream's estimator state resident in HBM;
+* whenever fewer than `depth` steps are in flight, launches one step that
+  takes the oldest waiting chunk of every admitted stream that has one
+  (never two chunks of a stream in one step: a chunk is a batch, and the
+  random key depends on the batch index);
+* records each step's completion with a GPU event, so a chunk's ingest
+  latency is its step's completion time minus its arrival time;
+* frees a stream's slot once its last chunk is done and its estimate read.
+
+Every stream therefore gets exactly the result it would get alone (each
+chunk processed as one batch of its own bank, in order), whatever the mix.
+All arithmetic runs in the kernels behind tc_multi_process.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import torch
+
+from . import MultiBank, tc_multi_assign, tc_multi_estimate, tc_multi_reserve
+
+
+@dataclasses.dataclass
+class Chunk:
+    t: float            # arrival time (seconds from the start of the run)
+    stream: int         # stream id
+    edges: torch.Tensor  # (w, 2) int32 device tensor
+    last: bool          # the stream's final chunk
+
+
+@dataclasses.dataclass
+class Result:
+    S: int
+    m: int
+    tau: float
+
+
+def bank_bytes(r: int) -> int:
+    """Device bytes of one resident bank (f1, f2, packed chi/closed)."""
+    return 20 * r
+
+
+def slots_for_budget(budget_bytes: int, r: int, reserve_bytes: int) -> int:
+    """Bank slots that fit the budget after the step scratch reservation."""
+    return max(0, (budget_bytes - reserve_bytes) // bank_bytes(r))
+
+
+def poisson_arrivals(chunks_per_stream, rate_per_s: float, seed: int):
+    """Merge per-stream chunk lists (each in stream order) into one arrival
+    sequence: aggregate Poisson arrivals at `rate_per_s` (rate 0: everything
+    at time 0), each arrival taking the next chunk of a stream drawn with
+    probability proportional to its remaining chunks.  Returns Chunk list."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    left = np.array([len(c) for c in chunks_per_stream], dtype=np.int64)
+    total = int(left.sum())
+    times = (np.cumsum(rng.exponential(1.0 / rate_per_s, total)) if rate_per_s > 0
+             else np.zeros(total))
+    nxt = [0] * len(left)
+    out = []
+    for k in range(total):
+        cum = np.cumsum(left)
+        s = int(np.searchsorted(cum, rng.random() * cum[-1], side="right"))
+        s = min(s, len(left) - 1)
+        while left[s] == 0:
+            s = (s + 1) % len(left)
+        i = nxt[s]
+        nxt[s] += 1
+        left[s] -= 1
+        out.append(Chunk(float(times[k]), s, chunks_per_stream[s][i],
+                         nxt[s] == len(chunks_per_stream[s])))
+    return out
+
+
+class Server:
+    """Admission, continuous batching and latency bookkeeping."""
+
+    def __init__(self, slots: int, r: int, depth: int = 2,
+                 stream: torch.cuda.Stream | None = None):
+        """`slots` resident banks of r estimators.  Step scratch grows to
+        the largest step seen (the first run is a warm-up) and is reused;
+        every run reassigns the slots it uses, so a Server serves many runs."""
+        if slots < 1:
+            raise ValueError("the memory budget leaves no bank slot")
+        self.slots, self.r, self.depth = slots, r, depth
+        self.bank = MultiBank([r] * slots, [0] * slots)
+        self.stream = stream or torch.cuda.current_stream()
+
+    def reserve(self, chunk_sizes) -> None:
+        """Pre-size the step scratch for one step with these chunk sizes."""
+        n = min(len(chunk_sizes), self.slots)
+        tc_multi_reserve(self.bank.h, list(range(n)), list(chunk_sizes)[:n])
+
+    def run(self, arrivals, seeds, spin_s: float = 2e-5):
+        """arrivals: list of Chunk sorted by time.  Returns (latencies in
+        seconds per chunk, results per stream, elapsed seconds, r*w done)."""
+        st = self.stream
+        pending = collections.deque(arrivals)
+        ready = collections.defaultdict(collections.deque)
+        slot_of, waitlist, free = {}, collections.deque(), list(range(self.slots))[::-1]
+        done_streams, results, lat = [], {}, []
+        inflight = collections.deque()
+        rw = 0
+        torch.cuda.synchronize()
+        ref = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ref.record(st)
+        while pending or inflight or waitlist or any(ready.values()):
+            now = time.perf_counter() - t0
+            while pending and pending[0].t <= now:
+                c = pending.popleft()
+                if c.stream not in slot_of and not ready[c.stream]:
+                    waitlist.append(c.stream)
+                ready[c.stream].append(c)
+            # retire finished steps (in order)
+            while inflight and inflight[0][0].query():
+                ev, items = inflight.popleft()
+                t_done = ref.elapsed_time(ev) / 1e3
+                for c in items:
+                    lat.append(t_done - c.t)
+                    if c.last:
+                        done_streams.append(c.stream)
+            # a finished stream's slot is read out and freed only when needed
+            if waitlist and not free and done_streams:
+                S, m, tau = tc_multi_estimate(self.bank.h)
+                for sid in done_streams:
+                    b = slot_of.pop(sid)
+                    results[sid] = Result(int(S[b]), int(m[b]), float(tau[b]))
+                    free.append(b)
+                done_streams = []
+            while waitlist and free:
+                sid = waitlist.popleft()
+                b = free.pop()
+                tc_multi_assign(self.bank.h, b, seeds[sid], st)
+                slot_of[sid] = b
+            if len(inflight) < self.depth:
+                ids, chunks, items = [], [], []
+                for sid, b in slot_of.items():
+                    if ready[sid]:
+                        c = ready[sid].popleft()
+                        ids.append(b)
+                        chunks.append(c.edges)
+                        items.append(c)
+                        rw += self.r * c.edges.shape[0]
+                if ids:
+                    self.bank.process(ids, chunks, st)
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(st)
+                    inflight.append((ev, items))
+                    continue
+            if inflight or pending:
+                time.sleep(spin_s)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        S, m, tau = tc_multi_estimate(self.bank.h)
+        for sid in done_streams:
+            b = slot_of.pop(sid)
+            results[sid] = Result(int(S[b]), int(m[b]), float(tau[b]))
+        return lat, results, elapsed, rw
+
+    def close(self):
+        self.bank.close()
+
+
+def chunk_streams(streams, seed: int, lo: int = 1000, hi: int = 1_000_000):
+    """Cut every stream into chunks of log-uniform size in [lo, hi] pairs."""
+    g = torch.Generator().manual_seed(seed)
+    out = []
+    for e in streams:
+        m = e.shape[0]
+        pieces, j = [], 0
+        while j < m:
+            u = float(torch.rand(1, generator=g, dtype=torch.float64))
+            w = int(round(lo * (hi / lo) ** u))
+            pieces.append(e[j:j + w])
+            j += w
+        out.append(pieces)
+    return out

@@ -360,3 +360,34 @@ def test_graph_replay_single_bank(tc):
         torch.cuda.synchronize()
         assert_same(mb.state(0), o.state(), f"replay {rep}")
         _ = torch.ones(1000, device="cuda").sum().item()
+
+
+# -- continuous batching: each stream's result alone == in the mix -----------------------
+
+def test_served_streams_equal_their_alone_runs(tc):
+    from paper_1308_2166_amd import serve
+    nstreams, r = 24, 3000
+    graphs = [inputs.rmat(10 + s % 4, 4000 + 900 * s, seed=80 + s, device="cuda")
+              if s % 2 == 0 else inputs.chung_lu(600 + 50 * s, 3000 + 700 * s, seed=90 + s,
+                                                 device="cuda")
+              for s in range(nstreams)]
+    chunks = serve.chunk_streams(graphs, seed=3, lo=200, hi=5000)
+    seeds = [1000 + s for s in range(nstreams)]
+    arrivals = serve.poisson_arrivals(chunks, rate_per_s=20000.0, seed=4)
+    srv = serve.Server(slots=7, r=r)  # tight: streams wait for slots
+    lat, results, elapsed, rw = srv.run(arrivals, seeds)
+    srv.close()
+    assert len(lat) == sum(len(c) for c in chunks) and len(results) == nstreams
+    assert min(lat) > 0
+    for s in range(nstreams):
+        alone = tc.Bank(r, seeds[s])
+        for c in chunks[s]:
+            alone.process(c)
+        S, m, tau = tc.tc_estimate_ex(alone.h)
+        assert (results[s].S, results[s].m) == (S, m), s
+        if s < 6:  # and the oracle agrees with the alone run
+            o = O.Bank(r, seeds[s])
+            for c in chunks[s]:
+                o.process(np_edges(c))
+            assert_same(alone.state(), o.state(), f"stream {s}")
+            assert S == o.sum()
