@@ -52,8 +52,12 @@ def alg_bytes(kernel: str, w: int, r: int, nontrivial: list) -> float:
         return arcs * ((4.0 if first else 8.0) + 8.0)
     if kernel == "k_dir":
         return arcs * 8.0
+    if kernel == "k_step1":
+        return r * 4.0
     if kernel == "k_est":
-        return r * (20.0 + 20.0)
+        return r * (20.0 + 4.0 + 12.0 + 12.0)
+    if kernel == "k_post":
+        return r * 12.0
     if kernel == "k_probe":
         return 8.0 * w
     return 0.0
@@ -245,8 +249,8 @@ def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command):
     ff = calib_bytes / (fcopy * 1024) if fcopy else None
     fw = calib_bytes / (wcopy * 1024) if wcopy else None
     kernels = [k for k in durs if k.startswith("k_")]
-    order = ["k_hist", "k_pass<0>", "k_pass<1>", "k_pass<2>", "k_pass<3>",
-             "k_dir", "k_est", "k_probe"]
+    order = ["k_hist", "k_step1", "k_pass<0>", "k_pass<1>", "k_pass<2>", "k_pass<3>",
+             "k_dir", "k_est", "k_post", "k_probe"]
     kernels.sort(key=lambda k: order.index(k) if k in order else 99)
     per = {}
     lines = ["| kernel | launches | avg us | min us | max us | FETCH KiB/launch | WRITE KiB/launch | HBM bytes/launch (calibrated) |",

@@ -83,6 +83,9 @@ struct Engine {
   uint64_t* R1 = nullptr;
   uint64_t* R2 = nullptr;
   uint32_t* CC = nullptr;
+  uint32_t* J1 = nullptr;  // scratch: Step-1 replacement index per estimator
+  uint64_t* QQ = nullptr;  // scratch: closing edge each estimator waits for
+  uint32_t* QT = nullptr;  // scratch: its first closing batch position
   uint64_t* bank_off = nullptr;  // device copy of est_off
   unsigned long long* sums = nullptr;
   uint32_t* err = nullptr;
@@ -91,13 +94,17 @@ struct Engine {
   uint32_t* h_err = nullptr;             // pinned
 
   // step scratch
-  uint64_t cap_arcs = 0, cap_tiles = 0, cap_dir = 0, cap_qt = 0;
+  uint64_t cap_arcs = 0, cap_tiles = 0, cap_dir = 0, cap_qt = 0, cap_bm = 0,
+           cap_need = 0;
   uint32_t cap_segs = 0;
   uint64_t* arcs[2] = {nullptr, nullptr};
   uint32_t* status[2] = {nullptr, nullptr};
   SegWork* work = nullptr;
   DirSlot* dir = nullptr;
   QSlot* qt = nullptr;
+  uint32_t* bm = nullptr;
+  uint8_t* need = nullptr;
+  uint32_t* inv = nullptr;
   SegDesc* segs_dev = nullptr;
 
   // pinned staging ring for multi-segment descriptors
@@ -134,7 +141,7 @@ struct Engine {
       }
     ev_pending.clear();
     ev_free.clear();
-    dfree(R1), dfree(R2), dfree(CC), dfree(bank_off);
+    dfree(R1), dfree(R2), dfree(CC), dfree(J1), dfree(QQ), dfree(QT), dfree(bank_off);
     dfree(sums), dfree(err), dfree(tagp);
     for (SegDesc* g : graph_stage) (void)hipHostFree(g);
     graph_stage.clear();
@@ -151,8 +158,9 @@ struct Engine {
 
   void free_scratch() {
     dfree(arcs[0]), dfree(arcs[1]), dfree(status[0]), dfree(status[1]);
-    dfree(work), dfree(dir), dfree(qt), dfree(segs_dev);
-    cap_arcs = cap_tiles = cap_dir = cap_qt = 0;
+    dfree(work), dfree(dir), dfree(qt), dfree(bm), dfree(need), dfree(inv);
+    dfree(segs_dev);
+    cap_arcs = cap_tiles = cap_dir = cap_qt = cap_bm = cap_need = 0;
     cap_segs = 0;
   }
 
@@ -175,6 +183,7 @@ struct Engine {
     if (total >= 0x7FFFFFFFull)
       return fail(TC_EINVAL, "too many estimators in one object (max 2^31-2)");
     if (dalloc(&R1, total) || dalloc(&R2, total) || dalloc(&CC, total) ||
+        dalloc(&J1, total) || dalloc(&QQ, total) || dalloc(&QT, total) ||
         dalloc(&bank_off, n + 1) ||
         dalloc(&sums, n) || dalloc(&err, 1) || dalloc(&tagp, 1))
       return fail(TC_ENOMEM, "device allocation of the estimator banks failed");
@@ -194,9 +203,10 @@ struct Engine {
   }
 
   int ensure_scratch(uint64_t arcs_n, uint64_t tiles, uint64_t dir_n,
-                     uint64_t qt_n, uint32_t nseg, hipStream_t st) {
+                     uint64_t qt_n, uint64_t bm_n, uint64_t need_n, uint32_t nseg,
+                     hipStream_t st) {
     if (arcs_n <= cap_arcs && tiles <= cap_tiles && dir_n <= cap_dir &&
-        qt_n <= cap_qt && nseg <= cap_segs)
+        qt_n <= cap_qt && bm_n <= cap_bm && need_n <= cap_need && nseg <= cap_segs)
       return TC_OK;
     if (last) (void)hipStreamSynchronize(last);
     (void)hipStreamSynchronize(st);
@@ -205,12 +215,15 @@ struct Engine {
     cap_tiles = std::max(tiles, cap_tiles);
     cap_dir = std::max(dir_n, cap_dir);
     cap_qt = std::max(qt_n, cap_qt);
+    cap_bm = std::max(bm_n, cap_bm);
+    cap_need = std::max(need_n, cap_need);
     cap_segs = std::max(nseg, cap_segs);
     if (dalloc(&arcs[0], cap_arcs) || dalloc(&arcs[1], cap_arcs) ||
         dalloc(&status[0], cap_tiles * kDigits) ||
         dalloc(&status[1], cap_tiles * kDigits) ||
         dalloc(&work, cap_segs) ||
-        dalloc(&dir, cap_dir) || dalloc(&qt, cap_qt) ||
+        dalloc(&dir, cap_dir) || dalloc(&qt, cap_qt) || dalloc(&bm, cap_bm) ||
+        dalloc(&need, cap_need) || dalloc(&inv, cap_arcs) ||
         dalloc(&segs_dev, cap_segs)) {
       free_scratch();
       return fail(TC_ENOMEM, "device allocation of step scratch failed");
@@ -221,6 +234,8 @@ struct Engine {
         hipMemsetAsync(work, 0, sizeof(SegWork) * cap_segs, st) ||
         hipMemsetAsync(dir, 0, sizeof(DirSlot) * cap_dir, st) ||
         hipMemsetAsync(qt, 0, sizeof(QSlot) * cap_qt, st) ||
+        hipMemsetAsync(bm, 0, 4 * cap_bm, st) ||
+        hipMemsetAsync(need, 0, cap_need, st) ||
         hipStreamSynchronize(st))
       return fail(TC_EHIP, "clearing step scratch failed");
     return TC_OK;
@@ -272,7 +287,8 @@ struct Engine {
     std::vector<SegDesc> segs;
     segs.reserve(nchunks);
     std::vector<char> seen(nbanks, 0);
-    uint64_t arcs_n = 0, tiles = 0, dir_n = 0, qt_n = 0, nest = 0, hblks = 0;
+    uint64_t arcs_n = 0, tiles = 0, dir_n = 0, qt_n = 0, bm_n = 0, need_n = 0, nest = 0,
+             hblks = 0;
     for (uint32_t k = 0; k < nchunks; ++k) {
       const uint32_t b = ids[k];
       if (b >= nbanks) return fail(TC_EINVAL, "bank id out of range");
@@ -302,6 +318,11 @@ struct Engine {
       hblks += d.nhblk;
       d.dir_log2 = dir_log2_for(w[k]);
       d.qt_log2 = qt_log2_for(r[b]);
+      d.bm_log2 = qt_log2_for(r[b]) + 3;  // 16 bits per estimator
+      d.bm_off = bm_n;
+      bm_n += (1ull << d.bm_log2) / 32;
+      d.need_off = (uint32_t)need_n;
+      need_n += (w[k] + 15) / 16 * 16;
       arcs_n += 2ull * w[k];
       tiles += d.ntiles;
       dir_n += 1ull << d.dir_log2;
@@ -311,7 +332,9 @@ struct Engine {
     }
     if (segs.empty()) return TC_OK;
     if (tiles >= 0x7FFFFFFFull) return fail(TC_EINVAL, "step too large");
-    int rc = ensure_scratch(arcs_n, tiles, dir_n, qt_n, (uint32_t)segs.size(), st);
+    if (need_n >= 0xFFFFFFFFull) return fail(TC_EINVAL, "step too large");
+    int rc = ensure_scratch(arcs_n, tiles, dir_n, qt_n, bm_n, need_n,
+                            (uint32_t)segs.size(), st);
     if (rc || reserve) return rc;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cap) != hipSuccess)
@@ -338,6 +361,14 @@ struct Engine {
     a.dir = dir;
     a.qt = qt;
     a.qt_slots = qt_n;
+    a.bm = bm;
+    a.bm_words = bm_n;
+    a.j1 = J1;
+    a.qq = QQ;
+    a.qthr = QT;
+    a.need = need;
+    a.need_bytes = need_n;
+    a.inv = inv;
     a.err = err;
     if (a.nseg > 1) {
       rc = stage_descs(segs, st, capturing);
@@ -548,8 +579,8 @@ int tc_sync(tc_state* s) {
 }
 
 static const char* const kKernelNames[kNumKernels] = {
-    "k_hist", "k_pass<0>", "k_pass<1>", "k_pass<2>",
-    "k_pass<3>", "k_dir", "k_est", "k_probe"};
+    "k_hist", "k_step1", "k_pass<0>", "k_pass<1>", "k_pass<2>",
+    "k_pass<3>", "k_dir", "k_est", "k_post", "k_probe"};
 
 static int set_timing(Engine& e, int enable) {
   int rc = e.collect_times();

@@ -21,9 +21,19 @@ constexpr int kItems = 16;               // arcs per thread per tile
 constexpr int kTile = kBlock * kItems;   // 4096 arcs per tile
 constexpr int kDigits = 256;
 constexpr int kPasses = 4;
-constexpr int kNumKernels = 8;  // launches per step (k_hist .. k_probe)
-constexpr int kHistTiles = 8;   // tiles per k_hist block
+constexpr int kNumKernels = 10;  // launches per step (k_hist .. k_probe)
+constexpr int kHistTiles = 1;   // tiles per k_hist block
 constexpr int kLookback = 16;   // predecessor statuses read per look-back round
+
+// j1[] word: kNone, or the replacement position with kSideV set when the
+// smaller endpoint u of W[j1] is its second vertex
+constexpr uint32_t kSideV = 0x40000000u;
+constexpr uint32_t kPosMask = 0x3FFFFFFFu;
+
+// low word of a sorted arc: arc id (2 pos + side) and, in bit 31, a flag
+// marking arcs of positions Step 1 takes an f1 from (ids stay below 2^29)
+constexpr uint32_t kNeedFlag = 0x80000000u;
+constexpr uint32_t kIdMask = 0x7FFFFFFFu;
 
 // packed estimator word: chi in bits 0..30, closed flag in bit 31
 constexpr uint32_t kClosed = 0x80000000u;
@@ -60,6 +70,9 @@ struct SegDesc {
   uint32_t nhblk;         // ceil(ntiles / kHistTiles)
   uint32_t dir_log2;      // log2 of the directory region (slots)
   uint32_t qt_log2;       // log2 of the query-table region (slots)
+  uint64_t bm_off;        // first word of the query filter region
+  uint32_t bm_log2;       // log2 of the query filter region (bits)
+  uint32_t need_off;      // first byte of the "position needed" bytes (w bytes)
 };
 
 // per-segment values produced during a step (device)
@@ -111,6 +124,16 @@ struct StepArgs {
   DirSlot* dir;
   QSlot* qt;
   uint64_t qt_slots;      // query-table slots over all segments
+  uint32_t* bm;           // query filter: one bit per hashed closing edge
+  uint64_t bm_words;      // filter words over all segments
+  uint32_t* j1;           // per estimator: Step-1 replacement (see kSideV)
+  uint64_t* qq;           // per estimator: closing edge it waits for, or kEmpty
+  uint32_t* qthr;         // per estimator: first batch position that closes it
+  uint8_t* need;          // per segment, one byte per batch position: 1 if
+                          // some estimator takes its f1 from it this step
+  uint64_t need_bytes;    // over all segments (a multiple of 16)
+  uint32_t* inv;          // per arc slot: its index in the sorted arcs (only
+                          // for arcs of needed positions)
   uint32_t* err;          // sticky error bits
 };
 

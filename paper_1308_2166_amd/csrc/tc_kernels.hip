@@ -1,18 +1,22 @@
 // Device kernels of the bulk estimator update (Tangwongsan, Pavan,
 // Tirthapura, Sec. 4: bulkUpdateAll) for gfx950.
 //
-// One step = k_hist -> k_pass<0..3> -> k_dir -> k_est -> k_probe.
+// One step = k_hist -> k_step1 -> k_pass<0..3> -> k_dir -> k_est -> k_post
+// -> k_probe.
 //
 //  k_hist   digit histograms of the 2w arcs (+ max id, self-loop check)
+//  k_step1  Step 1: which estimators take a new f1, from where; writes f1
 //  k_pass   stable LSD radix pass over 8 bits of the vertex id (onesweep:
 //           wave64 ballot ranking, decoupled look-back, LDS-staged coalesced
-//           scatter).  Arcs are (vertex << 32 | pos); stability keeps every
+//           scatter).  Arcs are (vertex << 32 | 2 pos + side); stability keeps every
 //           vertex's arcs in arrival order, which is the rankAll grouping
 //           of the Lemma on rankAll read in increasing pos (rank = arcs
 //           after it in the segment).  Digits constant over a chunk are
 //           skipped on the device.
-//  k_dir    vertex -> [start, end) of its arcs (tag-versioned directory)
-//  k_est    Steps 1 and 2 for every estimator; posts the Step-3 query
+//  k_dir    vertex -> [start, end) of its arcs (tag-versioned directory),
+//           and the sorted index of the arcs of positions Step 1 picked
+//  k_est    Step 2 for every estimator; records its Step-3 closing edge
+//  k_post   Step 3 queries into a hash table (+ an L2-sized filter)
 //  k_probe  Step 3: one pass over W closes the estimators waiting for it
 #include <algorithm>
 
@@ -180,6 +184,14 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
     for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.qt_slots;
          t += (uint64_t)a.nhblk * kBlock)
       q4[t] = ones;
+    uint4* b4 = reinterpret_cast<uint4*>(a.bm);
+    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.bm_words / 4;
+         t += (uint64_t)a.nhblk * kBlock)
+      b4[t] = make_uint4(0, 0, 0, 0);
+    uint4* n4 = reinterpret_cast<uint4*>(a.need);
+    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.need_bytes / 16;
+         t += (uint64_t)a.nhblk * kBlock)
+      n4[t] = make_uint4(0, 0, 0, 0);
   }
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
@@ -308,11 +320,15 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
   uint64_t el[kItems];
   uint32_t rk[kItems];
   if (k == 0) {
+    // arcs straight from W: arc id = 2 pos + side, flagged when Step 1
+    // takes some f1 from that position (read in order, so coalesced)
     const uint32_t* E = S.edges;
+    const uint8_t* need = a.need + S.need_off;
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
       const uint32_t gi = min(base + wave * 64 * kItems + i * 64 + lane, n - 1);
-      el[i] = ((uint64_t)E[gi] << 32) | (gi >> 1);
+      const uint32_t flag = need[gi >> 1] ? kNeedFlag : 0u;
+      el[i] = ((uint64_t)E[gi] << 32) | gi | flag;
     }
   } else {
 #pragma unroll
@@ -438,6 +454,30 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// k_step1: Step 1 (Sec. 4.2) draws for every estimator; the replacement
+// index goes to j1[] and its batch position is marked as needed
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_step1(StepArgs a) {
+  const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= a.nest) return;
+  const uint32_t sidx = seg_of_est(a, gid);
+  const SegDesc S = seg_desc(a, sidx);
+  const uint32_t i = (uint32_t)(gid - S.gest_off);
+  const uint64_t kb = mix64(mix64(S.key0 ^ (uint64_t)i) ^ S.batch);
+  // replace f1 with probability w / (m + w): x uniform on [0, m + w)
+  const uint64_t x = bounded(kb, 1, S.m + S.w);
+  uint32_t j1 = kNone;
+  if (x >= S.m) {
+    const uint32_t p = (uint32_t)(x - S.m);
+    a.need[S.need_off + p] = 1;  // idempotent byte store: no atomic needed
+    const uint2 ed = reinterpret_cast<const uint2*>(S.edges)[p];
+    a.r1[S.est_off + i] = canon(ed.x, ed.y);
+    j1 = p | (ed.x < ed.y ? 0u : kSideV);
+  }
+  a.j1[S.est_off + i] = j1;
+}
+
+// ---------------------------------------------------------------------------
 // vertex directory
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t dir_claim(DirSlot* dir, uint32_t mask,
@@ -501,7 +541,10 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
   const bool dense = wk->dense != 0;
   const uint32_t mask = (1u << S.dir_log2) - 1u;
   const uint32_t tag = uniform(*a.tagp);
+  uint32_t* inv = a.inv + S.arc_off;
   for (uint32_t i = base + tid; i < end; i += kBlock) {
+    const uint32_t id = (uint32_t)arc[i];
+    if (id & kNeedFlag) inv[id & kIdMask] = i;
     const uint32_t x = (uint32_t)(arc[i] >> 32);
     const bool head = i == 0 || (uint32_t)(arc[i - 1] >> 32) != x;
     const bool tail = i + 1 == n || (uint32_t)(arc[i + 1] >> 32) != x;
@@ -523,44 +566,6 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
 // ---------------------------------------------------------------------------
 // k_est: Steps 1 and 2 per estimator, Step-3 query posted
 // ---------------------------------------------------------------------------
-// Index of arc (x, p) inside x's segment [lo, hi) of the sorted arcs, whose
-// positions (low 32 bits) ascend.  Positions of a vertex are spread over the
-// batch, so the search interpolates on them; a step that fails to halve the
-// interval is followed by a bisection, which bounds the probes by
-// 2 log2(hi - lo).  Returns hi if p is larger than every position.
-__device__ __forceinline__ uint32_t seg_search(const uint64_t* v, uint32_t lo,
-                                               uint32_t hi, uint32_t p) {
-  if (lo >= hi) return hi;
-  uint32_t plo = (uint32_t)v[lo];
-  uint32_t b = hi - 1;
-  uint32_t pb = (uint32_t)v[b];
-  if (p <= plo) return lo;
-  if (p > pb) return hi;
-  // invariant: pos[lo] < p <= pos[b]
-  bool bisect = false;
-  while (b - lo > 1) {
-    uint32_t g;
-    if (bisect) {
-      g = lo + ((b - lo) >> 1);
-    } else {
-      const float f = (float)(p - plo) / (float)(pb - plo);
-      g = lo + (uint32_t)(f * (float)(b - lo));
-      g = min(max(g, lo + 1), b - 1);
-    }
-    const uint32_t pg = (uint32_t)v[g];
-    const uint32_t before = b - lo;
-    if (pg < p) {
-      lo = g;
-      plo = pg;
-    } else {
-      b = g;
-      pb = pg;
-    }
-    bisect = !bisect && 2 * (b - lo) > before;
-  }
-  return b;
-}
-
 // register estimator `est` as waiting for closing edge q at a position
 // >= thr: claim an empty slot of q's probe sequence with one CAS (relaxed:
 // the slot's other fields are read only by the next kernel)
@@ -592,19 +597,18 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   const uint64_t e = S.est_off + i;
   const uint2* W = reinterpret_cast<const uint2*>(S.edges);
 
-  uint64_t r1 = a.r1[e], r2 = a.r2[e];
+  const uint64_t r1 = a.r1[e];  // Step 1 (k_step1) already wrote a new f1
+  uint64_t r2 = a.r2[e];
   const uint32_t ccw = a.cc[e];
+  const uint32_t jw = a.j1[e];
   uint64_t c = ccw & kChiMax;
   bool closed = (ccw & kClosed) != 0;
   const uint64_t kb = mix64(mix64(S.key0 ^ (uint64_t)i) ^ S.batch);
 
-  // Step 1 (Sec. 4.2): replace f1 with probability w / (m + w)
-  uint32_t j1 = kNone;
-  const uint64_t x = bounded(kb, 1, S.m + S.w);
-  if (x >= S.m) {
-    j1 = (uint32_t)(x - S.m);
-    const uint2 ed = W[j1];
-    r1 = canon(ed.x, ed.y);
+  // Step 1 (Sec. 4.2): a new f1 = W[j1] starts with chi = 0 and no f2
+  const uint32_t j1 = jw == kNone ? kNone : (jw & kPosMask);
+  const uint32_t side_u = (jw != kNone && (jw & kSideV)) ? 1u : 0u;
+  if (j1 != kNone) {
     c = 0;
     r2 = kEmpty;
     closed = false;
@@ -619,13 +623,16 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   const uint64_t* arc = a.arcs[wk->final_buf] + S.arc_off;
   uint32_t ld, rd;
   if (j1 != kNone) {
-    // f1 is W[j1]: count the arcs after it on each endpoint (the arc of
-    // W[j1] itself is always present; the guard only keeps every later
-    // index inside the segment)
-    const uint32_t iu = seg_search(arc, su.x, su.y, j1);
-    const uint32_t iv = seg_search(arc, sv.x, sv.y, j1);
-    ld = iu < su.y ? su.y - 1 - iu : 0u;
-    rd = iv < sv.y ? sv.y - 1 - iv : 0u;
+    // f1 is W[j1]: the arcs after it on each endpoint are those after its
+    // own arcs in their segments (the guard only keeps every later index
+    // inside the segment)
+    const uint2 iv2 = *reinterpret_cast<const uint2*>(a.inv + S.arc_off + 2ull * j1);
+    const uint32_t iu = side_u ? iv2.y : iv2.x;
+    const uint32_t iv = side_u ? iv2.x : iv2.y;
+    const bool ok = iu >= su.x && iu < su.y && iv >= sv.x && iv < sv.y;
+    if (!ok) atomicOr(a.err, kErrStall);
+    ld = ok ? su.y - 1 - iu : 0u;
+    rd = ok ? sv.y - 1 - iv : 0u;
   } else {
     ld = su.y - su.x;
     rd = sv.y - sv.x;
@@ -641,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
       const uint64_t phi = y - c;
       const uint32_t idx = phi < ld ? su.y - 1 - (uint32_t)phi
                                     : sv.y - 1 - (uint32_t)(phi - ld);
-      p2 = (uint32_t)arc[idx];
+      p2 = ((uint32_t)arc[idx] & kIdMask) >> 1;  // arc id -> batch position
       if (p2 >= S.w) {  // cannot happen: arcs carry positions < w
         atomicOr(a.err, kErrStall);
         p2 = 0;
@@ -658,18 +665,31 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
     }
   }
 
-  // Step 3 (Sec. 4.4) query: wait for the closing edge in this batch
-  if (r2 != kEmpty && !closed) {
-    const uint64_t q = closing(r1, r2);
-    if (q != kEmpty) {
-      const uint32_t thr = (p2 == kNone) ? 0u : p2 + 1;  // need pos >= thr
-      qt_post(a.qt + S.qt_off, (1u << S.qt_log2) - 1u, q, (uint32_t)e, thr,
-              a.err);
-    }
-  }
-  a.r1[e] = r1;
+  // Step 3 (Sec. 4.4): the closing edge this estimator waits for in W
+  uint64_t q = kEmpty;
+  if (r2 != kEmpty && !closed) q = closing(r1, r2);
+  a.qq[e] = q;
+  a.qthr[e] = (p2 == kNone) ? 0u : p2 + 1;  // closes at a position >= this
   a.r2[e] = r2;
   a.cc[e] = (uint32_t)c | (closed ? kClosed : 0u);
+}
+
+// ---------------------------------------------------------------------------
+// k_post: every waiting estimator into its segment's query table and filter
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_post(StepArgs a) {
+  const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= a.nest) return;
+  if (*a.err & kErrFatal) return;
+  const uint32_t sidx = seg_of_est(a, gid);
+  const SegDesc S = seg_desc(a, sidx);
+  const uint64_t e = S.est_off + (gid - S.gest_off);
+  const uint64_t q = a.qq[e];
+  if (q == kEmpty) return;
+  qt_post(a.qt + S.qt_off, (1u << S.qt_log2) - 1u, q, (uint32_t)e, a.qthr[e],
+          a.err);
+  const uint32_t bit = (uint32_t)(mix64(q) >> 32) & ((1u << S.bm_log2) - 1u);
+  atomicOr(&a.bm[S.bm_off + (bit >> 5)], 1u << (bit & 31));
 }
 
 // ---------------------------------------------------------------------------
@@ -691,32 +711,22 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
     const uint2* W = reinterpret_cast<const uint2*>(S.edges);
     const QSlot* qt = a.qt + S.qt_off;
     const uint32_t mask = (1u << S.qt_log2) - 1u;
-    // issue every load before walking any probe sequence
-    uint64_t q[kProbeEdges];
-    uint32_t h[kProbeEdges];
-#pragma unroll
+    const uint32_t* bm = a.bm + S.bm_off;
+    const uint32_t bmask = (1u << S.bm_log2) - 1u;
     for (int k = 0; k < kProbeEdges; ++k) {
       const uint32_t j = ebase + k * kBlock + tid;
-      q[k] = kEmpty;
-      if (j < S.w) {
-        const uint2 ed = W[j];
-        q[k] = canon(ed.x, ed.y);
-      }
-      h[k] = (uint32_t)mix64(q[k]) & mask;
-    }
-    uint64_t first[kProbeEdges];
-#pragma unroll
-    for (int k = 0; k < kProbeEdges; ++k)
-      first[k] = q[k] == kEmpty ? kEmpty : qt[h[k]].key;
-#pragma unroll
-    for (int k = 0; k < kProbeEdges; ++k) {
-      if (first[k] == kEmpty) continue;  // the usual case: nobody waits
-      const uint32_t j = ebase + k * kBlock + tid;
-      uint32_t hh = h[k];
+      if (j >= S.w) break;
+      const uint2 ed = W[j];
+      const uint64_t q = canon(ed.x, ed.y);
+      const uint64_t hq = mix64(q);
+      // the filter (a few MB, stays in L2) rules out nearly every edge
+      const uint32_t bit = (uint32_t)(hq >> 32) & bmask;
+      if (!((bm[bit >> 5] >> (bit & 31)) & 1u)) continue;
+      uint32_t hh = (uint32_t)hq & mask;
       for (uint32_t probe = 0; probe <= mask; ++probe) {
         const QSlot sl = qt[hh];
         if (sl.key == kEmpty) break;
-        if (sl.key == q[k] && j >= sl.thr) atomicOr(&a.cc[sl.est], kClosed);
+        if (sl.key == q && j >= sl.thr) atomicOr(&a.cc[sl.est], kClosed);
         hh = (hh + 1) & mask;
       }
     }
@@ -781,6 +791,8 @@ hipError_t launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
   mark();
   hipLaunchKernelGGL(k_hist, dim3(a.nhblk), blk, 0, st, a);
   mark();
+  hipLaunchKernelGGL(k_step1, ests, blk, 0, st, a);
+  mark();
   hipLaunchKernelGGL(k_pass<0>, tiles, blk, 0, st, a);
   mark();
   hipLaunchKernelGGL(k_pass<1>, tiles, blk, 0, st, a);
@@ -792,6 +804,8 @@ hipError_t launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
   hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a);
   mark();
   hipLaunchKernelGGL(k_est, ests, blk, 0, st, a);
+  mark();
+  hipLaunchKernelGGL(k_post, ests, blk, 0, st, a);
   mark();
   hipLaunchKernelGGL(k_probe, tiles, blk, 0, st, a);
   mark();
