@@ -216,11 +216,14 @@ def _short(name: str) -> str:
     return n.strip()
 
 
-def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command):
+def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command, timed=0):
     """Turn rocprofv3 CSV output of this benchmark into the committed
     summaries: per-kernel average duration (kernel trace) and per-kernel HBM
     traffic from FETCH_SIZE / WRITE_SIZE, each scaled by what the counter
-    reads for the calibration copy of calib_mib MiB."""
+    reads for the calibration copy of calib_mib MiB.  timed > 0: the last
+    `timed` launches of each step kernel are the benchmark's timed region
+    (run with --no-batched --no-served --no-cpu-baseline) and get their own
+    average."""
     import csv
     import glob
     import statistics as stt
@@ -249,23 +252,25 @@ def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command):
     ff = calib_bytes / (fcopy * 1024) if fcopy else None
     fw = calib_bytes / (wcopy * 1024) if wcopy else None
     kernels = [k for k in durs if k.startswith("k_")]
-    order = ["k_hist", "k_step1", "k_pass<0>", "k_pass<1>", "k_pass<2>", "k_pass<3>",
+    order = ["k_hist", "k_fold", "k_step1", "k_pass<0>", "k_pass<1>", "k_pass<2>", "k_pass<3>",
              "k_dir", "k_est", "k_post", "k_probe"]
     kernels.sort(key=lambda k: order.index(k) if k in order else 99)
     per = {}
-    lines = ["| kernel | launches | avg us | min us | max us | FETCH KiB/launch | WRITE KiB/launch | HBM bytes/launch (calibrated) |",
-             "|---|---|---|---|---|---|---|---|"]
+    lines = ["| kernel | launches | avg us | min us | max us | avg us, timed region "
+             "| FETCH KiB/launch | WRITE KiB/launch | HBM bytes/launch (calibrated) |",
+             "|---|---|---|---|---|---|---|---|---|"]
     for k in kernels:
         d = durs[k]
+        dt_ = d[-timed:] if timed and len(d) >= timed else []
+        tavg = stt.mean(dt_) if dt_ else None
         fk = stt.mean(ctr.get((k, "FETCH_SIZE"), [float("nan")]))
         wk = stt.mean(ctr.get((k, "WRITE_SIZE"), [float("nan")]))
         tb = fk * 1024 * ff + wk * 1024 * fw if ff and fw else None
-        per[k] = {"launches": len(d), "avg_us": stt.mean(d), "fetch_kib": fk,
-                  "write_kib": wk, "hbm_bytes": tb}
+        per[k] = {"launches": len(d), "avg_us": stt.mean(d), "avg_us_timed": tavg,
+                  "fetch_kib": fk, "write_kib": wk, "hbm_bytes": tb}
         lines.append(f"| {k} | {len(d)} | {stt.mean(d):.2f} | {min(d):.2f} | {max(d):.2f} | "
-                     f"{fk:.0f} | {wk:.0f} | {tb:.4g} |" if tb else
-                     f"| {k} | {len(d)} | {stt.mean(d):.2f} | {min(d):.2f} | {max(d):.2f} | "
-                     f"{fk:.0f} | {wk:.0f} | n/a |")
+                     + (f"{tavg:.2f}" if tavg else "n/a")
+                     + f" | {fk:.0f} | {wk:.0f} | " + (f"{tb:.4g} |" if tb else "n/a |"))
     os.makedirs(out_dir, exist_ok=True)
     rec = {"kernel_source_sha256_16": kernel_source_hash(), "calib_copy_mib": calib_mib,
            "fetch_factor": ff, "write_factor": fw, "per_kernel": per,
@@ -370,7 +375,8 @@ def main():
     args = ap.parse_args()
     if args.summarize:
         summarize(*args.summarize, calib_mib=args.calib_copy_mib,
-                  out_dir=os.path.join(ROOT, "profiles"), command=args.summary_command)
+                  out_dir=os.path.join(ROOT, "profiles"), command=args.summary_command,
+                  timed=args.steps)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
@@ -417,50 +423,96 @@ def main():
         warm_bank.process(batches[k % nb], stream)
     warm_bank.sync()
     warm_bank.close()
-    banks = []
-    for _ in range(nbanks):
-        b = tc.Bank(r, seed)
-        tc.tc_reserve(b.h, w)
-        if not args.no_kernel_timing:
-            tc.tc_set_kernel_timing(b.h, True)
-        banks.append(b)
-    torch.cuda.synchronize()
 
+    def fresh_banks(timing):
+        """timing: False, True (every kernel) or a list of kernel names."""
+        out = []
+        for _ in range(nbanks):
+            b = tc.Bank(r, seed)
+            tc.tc_reserve(b.h, w)
+            if timing:
+                tc.tc_set_kernel_timing(b.h, timing)
+            out.append(b)
+        torch.cuda.synchronize()
+        return out
+
+    def timed_run(banks, one_call_per_stream):
+        """Walk the banks through the steps; returns wall seconds.  With
+        one_call_per_stream each bank takes its batches in one
+        tc_process_stream call (Step 3 of a batch overlaps the grouping of
+        the next), else one tc_process_batch call per batch."""
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if one_call_per_stream:
+            k = 0
+            for b in banks:
+                cnt = min(nb, steps - k)
+                b.process_stream(G[:min(m, cnt * w)], w, stream)
+                k += cnt
+        else:
+            for k in range(steps):
+                banks[k // nb].process(batches[k % nb], stream)
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t0
+        for b in banks:
+            b.sync()
+        return dt_
+
+    def kernel_totals(banks):
+        tot, n = {}, 0
+        for b in banks:
+            t, s_ = tc.tc_kernel_times(b.h)
+            n += s_
+            for k_, v in t.items():
+                tot[k_] = tot.get(k_, 0.0) + v
+        return tot, n
+
+    def close_all(banks):
+        for b in banks:
+            b.close()
+
+    # 1. per-kernel breakdown: every kernel bracketed by events, one call per
+    #    batch (kernels run one at a time, so each time is the kernel's own)
+    per_kernel, timed, dom = {}, 0, None
+    if not args.no_kernel_timing:
+        bk = fresh_banks(True)
+        timed_run(bk, False)
+        per_kernel, timed = kernel_totals(bk)
+        close_all(bk)
+        dom = max(per_kernel, key=per_kernel.get)
+        log(f"[bench] dominant kernel {dom}")
+    # 2. one call per batch, no events (for comparison)
+    bk = fresh_banks(False)
+    per_batch_ms = timed_run(bk, False) * 1e3 / steps
+    close_all(bk)
+    # 3. the timed region: one tc_process_stream call per bank, events only
+    #    around the dominant kernel
+    banks = fresh_banks([dom] if dom else False)
     log(f"[bench] timing {steps} steps")
-    t0 = time.perf_counter()
-    for k in range(steps):
-        banks[k // nb].process(batches[k % nb], stream)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    for b in banks:
-        b.sync()
+    dt = timed_run(banks, True)
+    call_forms = {"per_batch_calls": round(per_batch_ms, 4),
+                  "stream_call": round(dt * 1e3 / steps, 4)}
+    log(f"[bench] ms/step by call form: {call_forms}")
     edges_done = sum(batches[k % nb].shape[0] for k in range(steps))
     value = r * edges_done / dt
     log(f"[bench] {dt * 1e3 / steps:.3f} ms/step, {value:.3e} r*m/s")
 
-    # per-kernel time over the timed region (events on the step's stream)
-    per_kernel, timed = {}, 0
-    if not args.no_kernel_timing:
-        for b in banks:
-            t, s = tc.tc_kernel_times(b.h)
-            timed += s
-            for k_, v in t.items():
-                per_kernel[k_] = per_kernel.get(k_, 0.0) + v
     roofline = None
-    if per_kernel and timed:
+    if dom:
+        live, live_n = kernel_totals(banks)
         # non-trivial digit passes of this stream (vertex id width)
         maxid = int(G.max().item())
         bits = max(1, math.ceil(math.log2(maxid + 1)))
         nontrivial = [8 * p < bits for p in range(4)]
-        dom = max(per_kernel, key=per_kernel.get)
-        avg_ms = per_kernel[dom] / timed
+        avg_ms = live[dom] / live_n
         ab = alg_bytes(dom, w, r, nontrivial)
         achieved = ab / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                     "kernel": dom, "avg_launch_us": round(avg_ms * 1e3, 2),
-                    "alg_bytes_per_launch": ab}
+                    "alg_bytes_per_launch": ab,
+                    "avg_launch_us_alone": round(per_kernel[dom] / timed * 1e3, 2)}
         try:
             with open(TRAFFIC_JSON) as f:
                 rec = json.load(f)
@@ -483,9 +535,10 @@ def main():
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "r": r, "w": w, "m_stream": m, "form": "plain"},
         "edges_per_s": edges_done / dt,
+        "ms_per_step_by_call_form": call_forms,
         "roofline": roofline,
-        "kernel_ms_per_step": {k_: round(v / timed, 4) for k_, v in per_kernel.items()}
-        if timed else None,
+        "kernel_ms_per_step_alone": {k_: round(v / timed, 4)
+                                     for k_, v in per_kernel.items()} if timed else None,
     }
 
     if not args.no_batched:
@@ -505,8 +558,7 @@ def main():
                       f"paper-steps oracle variant, single thread, {odt:.1f} s"}
         # the same batches on the GPU must give the oracle's state
         chk = tc.Bank(r, seed)
-        for j in range(nbo):
-            chk.process(batches[j], stream)
+        chk.process_stream(G[:min(m, nbo * w)], w, stream)
         same = all(np.array_equal(a, b_) for a, b_ in zip(chk.state(), ob.state()))
         out["bit_exact_vs_oracle"] = bool(same)
         out["parity_sample"] = f"state after {nbo} batch(es), all {r} estimators"

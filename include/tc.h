@@ -72,6 +72,20 @@ tc_state *tc_create(uint32_t r, uint64_t seed);
 int tc_process_batch(tc_state *s, const uint32_t *edges, uint32_t w,
                      void *stream);
 
+/* Enqueue a whole resident stream: the m edges at DEVICE address edges
+ * (uint32_t[2*m], 8-byte aligned) cut into ceil(m/w) consecutive batches of
+ * w edges (the last one ragged), each one bulkUpdateAll in stream order.
+ * The result is bit-identical to that many tc_process_batch calls on the
+ * same cuts.  Inside the call, the closing-edge check (Step 3) of batch k
+ * runs on an internal stream while batch k+1 is grouped on `stream`; the
+ * call joins that stream back before it returns, so work enqueued on
+ * `stream` afterwards sees every batch complete, and the call may be
+ * captured into a HIP graph.  TC_EINVAL for a NULL state, NULL edges with
+ * m > 0, w == 0 or w > TC_MAX_BATCH; on any error the batches before the
+ * failing one stay enqueued. */
+int tc_process_stream(tc_state *s, const uint32_t *edges, uint64_t m,
+                      uint32_t w, void *stream);
+
 /* Pre-size the bank's step scratch for batches of up to max_w edges so that
  * later tc_process_batch calls with w <= max_w allocate nothing (needed
  * before capturing them into a HIP graph).  Blocking.  TC_ENOMEM on
@@ -163,15 +177,20 @@ uint32_t tc_multi_num_banks(const tc_multi *s);
 void tc_multi_destroy(tc_multi *s);
 
 /* ---- diagnostics: per-kernel device time --------------------------------
- * While enabled, every step records HIP events between its kernels on the
- * step's own stream (a few microseconds of overhead per step).  Enabling or
- * disabling resets the totals.  tc_kernel_times blocks, then writes the
- * accumulated milliseconds of each of the tc_num_kernels() launches of a
- * step (launch order; names from tc_kernel_name) into the HOST array `ms`
- * and the number of timed steps into *steps. */
-int tc_set_kernel_timing(tc_state *s, int enable);
+ * mask: bit k (k < tc_num_kernels()) times kernel k; TC_TIME_ALL times every
+ * kernel; 0 turns timing off.  While on, every step records a HIP event
+ * before and after each timed kernel on the stream that kernel runs on
+ * (about 2 us of device time per event, so time few kernels when the step
+ * time itself matters).  Changing the mask resets the totals.
+ * tc_kernel_times blocks, then writes the accumulated milliseconds of each
+ * of the tc_num_kernels() launches of a step (launch order; names from
+ * tc_kernel_name; 0 for untimed kernels) into the HOST array `ms` and the
+ * number of timed steps into *steps.  Timing must be off while a stream is
+ * being captured into a HIP graph (TC_EINVAL otherwise). */
+#define TC_TIME_ALL 0xFFFFFFFFu
+int tc_set_kernel_timing(tc_state *s, uint32_t mask);
 int tc_kernel_times(tc_state *s, double *ms, uint64_t *steps);
-int tc_multi_set_kernel_timing(tc_multi *s, int enable);
+int tc_multi_set_kernel_timing(tc_multi *s, uint32_t mask);
 int tc_multi_kernel_times(tc_multi *s, double *ms, uint64_t *steps);
 int tc_num_kernels(void);
 const char *tc_kernel_name(int k);

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libtc.so")
 TC_OK, TC_EINVAL, TC_EBADEDGE, TC_EOVERFLOW, TC_ENOMEM, TC_EHIP = 0, -1, -2, -3, -4, -5
 TC_EMPTY_EDGE = (1 << 64) - 1
 TC_MAX_BATCH = 1 << 28
+TC_TIME_ALL = 0xFFFFFFFF
 
 _NAMES = {TC_EINVAL: "TC_EINVAL", TC_EBADEDGE: "TC_EBADEDGE",
           TC_EOVERFLOW: "TC_EOVERFLOW", TC_ENOMEM: "TC_ENOMEM", TC_EHIP: "TC_EHIP"}
@@ -57,6 +58,7 @@ def lib():
     sig = {
         "tc_create": ([u32, u64], vp),
         "tc_process_batch": ([vp, vp, u32, vp], i32),
+        "tc_process_stream": ([vp, vp, u64, u32, vp], i32),
         "tc_estimate": ([vp], ctypes.c_double),
         "tc_estimate_ex": ([vp, P64, P64, ctypes.POINTER(ctypes.c_double)], i32),
         "tc_read_state": ([vp, vp, vp, vp, vp], i32),
@@ -79,9 +81,9 @@ def lib():
         "tc_multi_graph_reserve": ([vp, u32], i32),
         "tc_multi_assign": ([vp, u32, u64, vp], i32),
         "tc_multi_reserve": ([vp, u32, vp, vp], i32),
-        "tc_set_kernel_timing": ([vp, i32], i32),
+        "tc_set_kernel_timing": ([vp, u32], i32),
         "tc_kernel_times": ([vp, vp, P64], i32),
-        "tc_multi_set_kernel_timing": ([vp, i32], i32),
+        "tc_multi_set_kernel_timing": ([vp, u32], i32),
         "tc_multi_kernel_times": ([vp, vp, P64], i32),
         "tc_num_kernels": ([], i32),
         "tc_kernel_name": ([i32], ctypes.c_char_p),
@@ -93,7 +95,7 @@ def lib():
     return L
 
 
-EXPORTS = ("tc_create", "tc_process_batch", "tc_estimate", "tc_estimate_ex",
+EXPORTS = ("tc_create", "tc_process_batch", "tc_process_stream", "tc_estimate", "tc_estimate_ex",
            "tc_read_state", "tc_sync", "tc_num_estimators", "tc_edges_seen",
            "tc_batches_seen", "tc_destroy", "tc_last_error", "tc_multi_create",
            "tc_multi_process", "tc_multi_estimate", "tc_multi_read_state",
@@ -142,6 +144,15 @@ def tc_process_batch(state: int, edges, w: int | None = None, stream=None) -> No
     ptr, n = _edge_ptr(edges) if edges is not None else (0, 0)
     _check(lib().tc_process_batch(state, ptr or None, n if w is None else w,
                                   _stream_handle(stream)))
+
+
+def tc_process_stream(state: int, edges, w: int, stream=None) -> None:
+    """All of `edges` ((m, 2) device tensor) as consecutive batches of w."""
+    if edges is None or edges.shape[0] == 0:
+        ptr, m = 0, 0
+    else:
+        ptr, m = _edge_ptr(edges)
+    _check(lib().tc_process_stream(state, ptr or None, m, w, _stream_handle(stream)))
 
 
 def tc_reserve(state: int, max_w: int) -> None:
@@ -205,8 +216,19 @@ def tc_kernel_name(k: int) -> str:
     return lib().tc_kernel_name(k).decode()
 
 
-def tc_set_kernel_timing(state: int, enable: bool) -> None:
-    _check(lib().tc_set_kernel_timing(state, int(enable)))
+def _mask(enable) -> int:
+    """True -> every kernel, False -> off, an int -> that kernel mask,
+    a collection of kernel names -> their bits."""
+    if isinstance(enable, bool):
+        return TC_TIME_ALL if enable else 0
+    if isinstance(enable, int):
+        return enable & TC_TIME_ALL
+    names = [tc_kernel_name(k) for k in range(tc_num_kernels())]
+    return sum(1 << names.index(n) for n in enable)
+
+
+def tc_set_kernel_timing(state: int, enable) -> None:
+    _check(lib().tc_set_kernel_timing(state, _mask(enable)))
 
 
 def tc_kernel_times(state: int):
@@ -218,8 +240,8 @@ def tc_kernel_times(state: int):
     return {tc_kernel_name(k): float(ms[k]) for k in range(n)}, steps.value
 
 
-def tc_multi_set_kernel_timing(multi: int, enable: bool) -> None:
-    _check(lib().tc_multi_set_kernel_timing(multi, int(enable)))
+def tc_multi_set_kernel_timing(multi: int, enable) -> None:
+    _check(lib().tc_multi_set_kernel_timing(multi, _mask(enable)))
 
 
 def tc_multi_kernel_times(multi: int):
@@ -309,6 +331,9 @@ class Bank:
 
     def process(self, edges, stream=None):
         tc_process_batch(self.h, edges, stream=stream)
+
+    def process_stream(self, edges, w: int, stream=None):
+        tc_process_stream(self.h, edges, w, stream=stream)
 
     def estimate(self) -> float:
         return tc_estimate_ex(self.h)[2]

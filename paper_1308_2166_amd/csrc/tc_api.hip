@@ -18,7 +18,7 @@
 #include "tc_internal.h"
 
 namespace tc {
-hipError_t launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev);
+hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st, hipEvent_t* ev);
 hipError_t launch_sum(const uint32_t* cc, const uint64_t* bank_off,
                       uint32_t nbanks, uint64_t total,
                       unsigned long long* sums, hipStream_t st);
@@ -72,6 +72,17 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+// Per-parity scratch: the Step-3 phase of step s (on the engine's second
+// stream) overlaps the grouping phase of step s+1, so everything both
+// phases touch exists twice and step s uses copy s & 1.
+struct ParityScratch {
+  SegWork* work = nullptr;    // per-segment histograms, counters, modes
+  QSlot* qt = nullptr;        // Step-3 query tables
+  uint32_t* bm = nullptr;     // Step-3 query filters
+  uint64_t* wq = nullptr;     // canonical copy of the batch edges
+  SegDesc* segs = nullptr;    // device copy of the step's descriptors
+};
+
 struct Engine {
   int device = 0;
   uint32_t nbanks = 0;
@@ -79,33 +90,38 @@ struct Engine {
   std::vector<uint64_t> seed, key0, m, batch, est_off;  // est_off: nbanks+1
   uint64_t total = 0;
 
-  // bank state (all banks, contiguous)
+  // bank state (all banks, contiguous) and per-estimator step scratch
   uint64_t* R1 = nullptr;
   uint64_t* R2 = nullptr;
   uint32_t* CC = nullptr;
-  uint32_t* J1 = nullptr;  // scratch: Step-1 replacement index per estimator
-  uint64_t* QQ = nullptr;  // scratch: closing edge each estimator waits for
-  uint32_t* QT = nullptr;  // scratch: its first closing batch position
+  uint32_t* J1 = nullptr;  // Step-1 replacement per estimator
+  uint64_t* QQ = nullptr;  // closing edge each estimator waits for
+  uint32_t* QT = nullptr;  // its first closing batch position
   uint64_t* bank_off = nullptr;  // device copy of est_off
   unsigned long long* sums = nullptr;
   uint32_t* err = nullptr;
-  uint32_t* tagp = nullptr;  // directory tag of the next step (device)
+  uint32_t* tagp = nullptr;  // directory tag (advanced by every step)
   unsigned long long* h_sums = nullptr;  // pinned
   uint32_t* h_err = nullptr;             // pinned
 
-  // step scratch
+  // step scratch shared by the phases that never overlap
   uint64_t cap_arcs = 0, cap_tiles = 0, cap_dir = 0, cap_qt = 0, cap_bm = 0,
            cap_need = 0;
   uint32_t cap_segs = 0;
   uint64_t* arcs[2] = {nullptr, nullptr};
   uint32_t* status[2] = {nullptr, nullptr};
-  SegWork* work = nullptr;
   DirSlot* dir = nullptr;
-  QSlot* qt = nullptr;
-  uint32_t* bm = nullptr;
   uint8_t* need = nullptr;
   uint32_t* inv = nullptr;
-  SegDesc* segs_dev = nullptr;
+  uint32_t* hpart = nullptr;  // k_hist partial counts (one row per tile)
+  uint32_t* mpart = nullptr;  // k_hist partial max ids
+  ParityScratch par[2];
+
+  // the Step-3 phase runs on st2; evB orders it after k_est, evC orders
+  // the next k_est (and any state access) after it
+  hipStream_t st2 = nullptr;
+  hipEvent_t evB = nullptr, evC = nullptr;
+  bool c_pending = false;
 
   // pinned staging ring for multi-segment descriptors
   static constexpr int kRing = 4;
@@ -115,7 +131,7 @@ struct Engine {
   uint32_t stage_cap = 0;
   int ring = 0;
 
-  uint64_t steps = 0;  // steps enqueued (tag wrap guard)
+  uint64_t steps = 0;  // steps enqueued (parity, tag wrap guard)
   hipStream_t last = nullptr;
   // descriptor staging for steps captured into a HIP graph: one pinned
   // buffer per captured step, kept unchanged so every replay reads it
@@ -123,20 +139,37 @@ struct Engine {
   size_t graph_next = 0;
   int sticky = TC_OK;
 
-  // optional per-kernel timing: one set of kNumKernels+1 events per step
+  // optional per-kernel timing: a start/end event pair per timed kernel
+  // and step (bit k of timing_mask times kernel k)
   bool timing = false;
+  uint32_t timing_mask = 0;
   std::vector<hipEvent_t*> ev_pending, ev_free;
   double kernel_ms[kNumKernels] = {};
   uint64_t timed_steps = 0;
 
   ~Engine() { release(); }
 
-  void release() {
+  void wait_all() {
     if (last) (void)hipStreamSynchronize(last);
+    if (st2) (void)hipStreamSynchronize(st2);
+  }
+
+  // make `st` wait for a Step-3 phase left on st2 by an overlapped step
+  int join(hipStream_t st) {
+    if (!c_pending) return TC_OK;
+    c_pending = false;
+    if (hipStreamWaitEvent(st, evC, 0) != hipSuccess)
+      return fail(TC_EHIP, "hipStreamWaitEvent failed");
+    return TC_OK;
+  }
+
+  void release() {
+    wait_all();
     (void)hipDeviceSynchronize();
     for (auto* v : {&ev_pending, &ev_free})
       for (hipEvent_t* e : *v) {
-        for (int k = 0; k <= kNumKernels; ++k) (void)hipEventDestroy(e[k]);
+        for (int k = 0; k < 2 * kNumKernels; ++k)
+          if (e[k]) (void)hipEventDestroy(e[k]);
         delete[] e;
       }
     ev_pending.clear();
@@ -154,12 +187,19 @@ struct Engine {
       if (stage_ev[i]) (void)hipEventDestroy(stage_ev[i]);
       stage[i] = nullptr, stage_ev[i] = nullptr;
     }
+    if (evB) (void)hipEventDestroy(evB);
+    if (evC) (void)hipEventDestroy(evC);
+    if (st2) (void)hipStreamDestroy(st2);
+    evB = evC = nullptr;
+    st2 = nullptr;
   }
 
   void free_scratch() {
     dfree(arcs[0]), dfree(arcs[1]), dfree(status[0]), dfree(status[1]);
-    dfree(work), dfree(dir), dfree(qt), dfree(bm), dfree(need), dfree(inv);
-    dfree(segs_dev);
+    dfree(dir), dfree(need), dfree(inv), dfree(hpart), dfree(mpart);
+    for (ParityScratch& p : par) {
+      dfree(p.work), dfree(p.qt), dfree(p.bm), dfree(p.wq), dfree(p.segs);
+    }
     cap_arcs = cap_tiles = cap_dir = cap_qt = cap_bm = cap_need = 0;
     cap_segs = 0;
   }
@@ -182,6 +222,11 @@ struct Engine {
     total = est_off[n];
     if (total >= 0x7FFFFFFFull)
       return fail(TC_EINVAL, "too many estimators in one object (max 2^31-2)");
+    // default priority (same as the caller's streams)
+    if (hipStreamCreateWithFlags(&st2, hipStreamNonBlocking) ||
+        hipEventCreateWithFlags(&evB, hipEventDisableTiming) ||
+        hipEventCreateWithFlags(&evC, hipEventDisableTiming))
+      return fail(TC_EHIP, "stream or event creation failed");
     if (dalloc(&R1, total) || dalloc(&R2, total) || dalloc(&CC, total) ||
         dalloc(&J1, total) || dalloc(&QQ, total) || dalloc(&QT, total) ||
         dalloc(&bank_off, n + 1) ||
@@ -208,7 +253,7 @@ struct Engine {
     if (arcs_n <= cap_arcs && tiles <= cap_tiles && dir_n <= cap_dir &&
         qt_n <= cap_qt && bm_n <= cap_bm && need_n <= cap_need && nseg <= cap_segs)
       return TC_OK;
-    if (last) (void)hipStreamSynchronize(last);
+    wait_all();
     (void)hipStreamSynchronize(st);
     free_scratch();
     cap_arcs = std::max(arcs_n, cap_arcs);
@@ -218,31 +263,37 @@ struct Engine {
     cap_bm = std::max(bm_n, cap_bm);
     cap_need = std::max(need_n, cap_need);
     cap_segs = std::max(nseg, cap_segs);
-    if (dalloc(&arcs[0], cap_arcs) || dalloc(&arcs[1], cap_arcs) ||
-        dalloc(&status[0], cap_tiles * kDigits) ||
-        dalloc(&status[1], cap_tiles * kDigits) ||
-        dalloc(&work, cap_segs) ||
-        dalloc(&dir, cap_dir) || dalloc(&qt, cap_qt) || dalloc(&bm, cap_bm) ||
-        dalloc(&need, cap_need) || dalloc(&inv, cap_arcs) ||
-        dalloc(&segs_dev, cap_segs)) {
+    bool bad = dalloc(&arcs[0], cap_arcs) || dalloc(&arcs[1], cap_arcs) ||
+               dalloc(&status[0], cap_tiles * kDigits) ||
+               dalloc(&status[1], cap_tiles * kDigits) ||
+               dalloc(&dir, cap_dir) || dalloc(&need, cap_need) ||
+               dalloc(&inv, cap_arcs) ||
+               dalloc(&hpart, cap_tiles * kPasses * kDigits) ||
+               dalloc(&mpart, cap_tiles);
+    for (ParityScratch& p : par)
+      bad = bad || dalloc(&p.work, cap_segs) || dalloc(&p.qt, cap_qt) ||
+            dalloc(&p.bm, cap_bm) || dalloc(&p.wq, cap_arcs / 2 + 1) ||
+            dalloc(&p.segs, cap_segs);
+    if (bad) {
       free_scratch();
       return fail(TC_ENOMEM, "device allocation of step scratch failed");
     }
-    // zero = "no tag" for the tables, cleared look-back and work areas
-    if (hipMemsetAsync(status[0], 0, cap_tiles * kDigits * 4, st) ||
-        hipMemsetAsync(status[1], 0, cap_tiles * kDigits * 4, st) ||
-        hipMemsetAsync(work, 0, sizeof(SegWork) * cap_segs, st) ||
-        hipMemsetAsync(dir, 0, sizeof(DirSlot) * cap_dir, st) ||
-        hipMemsetAsync(qt, 0, sizeof(QSlot) * cap_qt, st) ||
-        hipMemsetAsync(bm, 0, 4 * cap_bm, st) ||
-        hipMemsetAsync(need, 0, cap_need, st) ||
-        hipStreamSynchronize(st))
+    // zero = "no tag" for the directory, cleared look-back and work areas
+    bad = hipMemsetAsync(status[0], 0, cap_tiles * kDigits * 4, st) ||
+          hipMemsetAsync(status[1], 0, cap_tiles * kDigits * 4, st) ||
+          hipMemsetAsync(dir, 0, sizeof(DirSlot) * cap_dir, st) ||
+          hipMemsetAsync(need, 0, cap_need, st);
+    for (ParityScratch& p : par)
+      bad = bad || hipMemsetAsync(p.work, 0, sizeof(SegWork) * cap_segs, st) ||
+            hipMemsetAsync(p.qt, 0, sizeof(QSlot) * cap_qt, st) ||
+            hipMemsetAsync(p.bm, 0, 4 * cap_bm, st);
+    if (bad || hipStreamSynchronize(st))
       return fail(TC_EHIP, "clearing step scratch failed");
     return TC_OK;
   }
 
-  int stage_descs(const std::vector<SegDesc>& segs, hipStream_t st,
-                  bool capturing) {
+  int stage_descs(const std::vector<SegDesc>& segs, SegDesc* dst,
+                  hipStream_t st, bool capturing) {
     const uint32_t n = (uint32_t)segs.size();
     if (capturing) {
       if (graph_next >= graph_stage.size())
@@ -250,8 +301,7 @@ struct Engine {
       if (n > nbanks) return fail(TC_EINVAL, "too many chunks");
       SegDesc* buf = graph_stage[graph_next++];
       std::memcpy(buf, segs.data(), sizeof(SegDesc) * n);
-      if (hipMemcpyAsync(segs_dev, buf, sizeof(SegDesc) * n,
-                         hipMemcpyHostToDevice, st))
+      if (hipMemcpyAsync(dst, buf, sizeof(SegDesc) * n, hipMemcpyHostToDevice, st))
         return fail(TC_EHIP, "descriptor upload failed");
       return TC_OK;
     }
@@ -272,8 +322,7 @@ struct Engine {
     ring = (ring + 1) % kRing;
     if (stage_used[k]) (void)hipEventSynchronize(stage_ev[k]);
     std::memcpy(stage[k], segs.data(), sizeof(SegDesc) * n);
-    if (hipMemcpyAsync(segs_dev, stage[k], sizeof(SegDesc) * n,
-                       hipMemcpyHostToDevice, st) ||
+    if (hipMemcpyAsync(dst, stage[k], sizeof(SegDesc) * n, hipMemcpyHostToDevice, st) ||
         hipEventRecord(stage_ev[k], st))
       return fail(TC_EHIP, "descriptor upload failed");
     stage_used[k] = true;
@@ -281,14 +330,18 @@ struct Engine {
   }
 
   // reserve == true: size the scratch for this step without launching it
+  // overlap == true: Step 3 runs on st2 and the next step (of the same API
+  // call) waits for it before its Steps 1-2; the call's last step must not
+  // overlap, so every call returns with all its work ordered on st
   int step(uint32_t nchunks, const uint32_t* ids, const uint32_t* const* edges,
-           const uint32_t* w, hipStream_t st, bool reserve = false) {
+           const uint32_t* w, hipStream_t st, bool reserve = false,
+           bool overlap = false) {
     if (sticky != TC_OK) return fail(sticky, "an earlier batch failed on the device");
     std::vector<SegDesc> segs;
     segs.reserve(nchunks);
     std::vector<char> seen(nbanks, 0);
     uint64_t arcs_n = 0, tiles = 0, dir_n = 0, qt_n = 0, bm_n = 0, need_n = 0, nest = 0,
-             hblks = 0;
+             hblks = 0, folds = 0;
     for (uint32_t k = 0; k < nchunks; ++k) {
       const uint32_t b = ids[k];
       if (b >= nbanks) return fail(TC_EINVAL, "bank id out of range");
@@ -316,6 +369,8 @@ struct Engine {
       d.hblk_off = (uint32_t)hblks;
       d.nhblk = (d.ntiles + kHistTiles - 1) / kHistTiles;
       hblks += d.nhblk;
+      d.fold_off = (uint32_t)folds;
+      folds += (d.nhblk + kFoldRows - 1) / kFoldRows;
       d.dir_log2 = dir_log2_for(w[k]);
       d.qt_log2 = qt_log2_for(r[b]);
       d.bm_log2 = qt_log2_for(r[b]) + 3;  // 16 bits per estimator
@@ -343,25 +398,29 @@ struct Engine {
     if (capturing && timing) return fail(TC_EINVAL, "kernel timing is on while capturing");
     if (++steps % 0xFFFF0000ull == 0 && !capturing) {
       // directory tags are about to wrap: forget every entry (fill, not memset)
-      if (launch_fill32(reinterpret_cast<uint32_t*>(dir), cap_dir * 4, 0, st))
+      if (join(st) || launch_fill32(reinterpret_cast<uint32_t*>(dir), cap_dir * 4, 0, st))
         return fail(TC_EHIP, "table reset failed");
     }
+    ParityScratch& P = par[steps & 1];
     StepArgs a{};
     a.nseg = (uint32_t)segs.size();
-    a.segs = segs_dev;
+    a.segs = P.segs;
     a.seg0 = segs[0];
     a.ntiles = (uint32_t)tiles;
     a.nhblk = (uint32_t)hblks;
+    a.nfold = (uint32_t)folds;
+    a.hpart = hpart;
+    a.mpart = mpart;
     a.nest = nest;
     a.tagp = tagp;
     a.r1 = R1, a.r2 = R2, a.cc = CC;
-    a.work = work;
+    a.work = P.work;
     a.arcs[0] = arcs[0], a.arcs[1] = arcs[1];
     a.status[0] = status[0], a.status[1] = status[1];
     a.dir = dir;
-    a.qt = qt;
+    a.qt = P.qt;
     a.qt_slots = qt_n;
-    a.bm = bm;
+    a.bm = P.bm;
     a.bm_words = bm_n;
     a.j1 = J1;
     a.qq = QQ;
@@ -369,9 +428,10 @@ struct Engine {
     a.need = need;
     a.need_bytes = need_n;
     a.inv = inv;
+    a.wq = P.wq;
     a.err = err;
     if (a.nseg > 1) {
-      rc = stage_descs(segs, st, capturing);
+      rc = stage_descs(segs, P.segs, st, capturing);
       if (rc) return rc;
     }
     hipEvent_t* ev = nullptr;
@@ -380,13 +440,31 @@ struct Engine {
         ev = ev_free.back();
         ev_free.pop_back();
       } else {
-        ev = new hipEvent_t[kNumKernels + 1];
-        for (int k = 0; k <= kNumKernels; ++k)
-          if (hipEventCreate(&ev[k])) return fail(TC_EHIP, "hipEventCreate failed");
+        ev = new hipEvent_t[2 * kNumKernels]();
+        for (int k = 0; k < kNumKernels; ++k)
+          if (timing_mask >> k & 1u)
+            if (hipEventCreate(&ev[2 * k]) || hipEventCreate(&ev[2 * k + 1]))
+              return fail(TC_EHIP, "hipEventCreate failed");
       }
       ev_pending.push_back(ev);
     }
-    if (launch_step(a, st, ev) != hipSuccess) return fail(TC_EHIP, "kernel launch failed");
+    // A: group the batch; B: Steps 1-2, after the previous step's Step 3;
+    // C: Step 3, on st2 when it may overlap the next step's A
+    if (launch_phase(0, a, st, ev) != hipSuccess)
+      return fail(TC_EHIP, "kernel launch failed");
+    if ((rc = join(st)) != TC_OK) return rc;
+    if (launch_phase(1, a, st, ev) != hipSuccess)
+      return fail(TC_EHIP, "kernel launch failed");
+    if (overlap) {
+      if (hipEventRecord(evB, st) != hipSuccess ||
+          hipStreamWaitEvent(st2, evB, 0) != hipSuccess ||
+          launch_phase(2, a, st2, ev) != hipSuccess ||
+          hipEventRecord(evC, st2) != hipSuccess)
+        return fail(TC_EHIP, "kernel launch failed");
+      c_pending = true;
+    } else if (launch_phase(2, a, st, ev) != hipSuccess) {
+      return fail(TC_EHIP, "kernel launch failed");
+    }
     for (uint32_t k = 0; k < nchunks; ++k) {
       if (w[k] == 0) continue;
       m[ids[k]] += w[k];
@@ -399,8 +477,8 @@ struct Engine {
   // every bank back to empty, |E| = 0, batch 0 (fill kernels only, so a
   // reset can be captured into a graph ahead of captured steps)
   int reset(hipStream_t st) {
-    if (launch_fill64(R1, total, kEmpty, st) || launch_fill64(R2, total, kEmpty, st) ||
-        launch_fill32(CC, total, 0, st))
+    if (join(st) || launch_fill64(R1, total, kEmpty, st) ||
+        launch_fill64(R2, total, kEmpty, st) || launch_fill32(CC, total, 0, st))
       return fail(TC_EHIP, "bank reset failed");
     std::fill(m.begin(), m.end(), 0);
     std::fill(batch.begin(), batch.end(), 0);
@@ -411,8 +489,8 @@ struct Engine {
   // bank b starts over as an empty bank with a new seed (kernels only)
   int assign(uint32_t b, uint64_t new_seed, hipStream_t st) {
     const uint64_t off = est_off[b], n = r[b];
-    if (launch_fill64(R1 + off, n, kEmpty, st) || launch_fill64(R2 + off, n, kEmpty, st) ||
-        launch_fill32(CC + off, n, 0, st))
+    if (join(st) || launch_fill64(R1 + off, n, kEmpty, st) ||
+        launch_fill64(R2 + off, n, kEmpty, st) || launch_fill32(CC + off, n, 0, st))
       return fail(TC_EHIP, "bank reset failed");
     seed[b] = new_seed;
     key0[b] = host_mix64(new_seed ^ kGolden);
@@ -423,7 +501,10 @@ struct Engine {
   }
 
   int graph_reserve(uint32_t nsteps) {
-    if (last) (void)hipStreamSynchronize(last);
+    // outstanding eager work is finished, so a capture starts from a state
+    // that depends on no event recorded outside it
+    wait_all();
+    c_pending = false;
     for (SegDesc* g : graph_stage) (void)hipHostFree(g);
     graph_stage.assign(nsteps, nullptr);
     graph_next = 0;
@@ -436,6 +517,8 @@ struct Engine {
 
   int sync() {
     if (last && hipStreamSynchronize(last) != hipSuccess)
+      return fail(TC_EHIP, "hipStreamSynchronize failed");
+    if (st2 && hipStreamSynchronize(st2) != hipSuccess)
       return fail(TC_EHIP, "hipStreamSynchronize failed");
     if (hipMemcpy(h_err, err, 4, hipMemcpyDeviceToHost) != hipSuccess)
       return fail(TC_EHIP, "reading the device error word failed");
@@ -452,10 +535,12 @@ struct Engine {
   // accumulate the elapsed time of every pending timed step
   int collect_times() {
     for (hipEvent_t* e : ev_pending) {
-      if (hipEventSynchronize(e[kNumKernels])) return fail(TC_EHIP, "event sync failed");
       for (int k = 0; k < kNumKernels; ++k) {
+        if (!e[2 * k]) continue;
         float ms = 0;
-        if (hipEventElapsedTime(&ms, e[k], e[k + 1])) return fail(TC_EHIP, "event timing failed");
+        if (hipEventSynchronize(e[2 * k + 1]) ||
+            hipEventElapsedTime(&ms, e[2 * k], e[2 * k + 1]))
+          return fail(TC_EHIP, "event timing failed");
         kernel_ms[k] += ms;
       }
       ++timed_steps;
@@ -538,6 +623,27 @@ int tc_process_batch(tc_state* s, const uint32_t* edges, uint32_t w,
   return s->e.step(1, &id, &edges, &w, static_cast<hipStream_t>(stream));
 }
 
+int tc_process_stream(tc_state* s, const uint32_t* edges, uint64_t m,
+                      uint32_t w, void* stream) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  if (w == 0 || w > TC_MAX_BATCH) return fail(TC_EINVAL, "w must be in [1, TC_MAX_BATCH]");
+  if (m == 0) return TC_OK;
+  if (!edges) return fail(TC_EINVAL, "null edge pointer with m > 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t id = 0;
+  for (uint64_t j = 0; j < m; j += w) {
+    const uint32_t wk = (uint32_t)std::min<uint64_t>(w, m - j);
+    const uint32_t* ek = edges + 2 * j;
+    const bool more = j + w < m;
+    int rc = s->e.step(1, &id, &ek, &wk, st, false, more);
+    if (rc) {
+      (void)s->e.join(st);
+      return rc;
+    }
+  }
+  return TC_OK;
+}
+
 int tc_reserve(tc_state* s, uint32_t max_w) {
   if (!s) return fail(TC_EINVAL, "null state");
   const uint32_t id = 0;
@@ -579,13 +685,24 @@ int tc_sync(tc_state* s) {
 }
 
 static const char* const kKernelNames[kNumKernels] = {
-    "k_hist", "k_step1", "k_pass<0>", "k_pass<1>", "k_pass<2>",
+    "k_hist", "k_fold", "k_step1", "k_pass<0>", "k_pass<1>", "k_pass<2>",
     "k_pass<3>", "k_dir", "k_est", "k_post", "k_probe"};
 
-static int set_timing(Engine& e, int enable) {
+static int set_timing(Engine& e, uint32_t mask) {
   int rc = e.collect_times();
   if (rc) return rc;
-  e.timing = enable != 0;
+  mask &= (1u << kNumKernels) - 1u;
+  if (mask != e.timing_mask) {
+    // event sets are made for one mask
+    for (hipEvent_t* ev : e.ev_free) {
+      for (int k = 0; k < 2 * kNumKernels; ++k)
+        if (ev[k]) (void)hipEventDestroy(ev[k]);
+      delete[] ev;
+    }
+    e.ev_free.clear();
+  }
+  e.timing_mask = mask;
+  e.timing = mask != 0;
   for (double& v : e.kernel_ms) v = 0;
   e.timed_steps = 0;
   return TC_OK;
@@ -600,9 +717,9 @@ static int read_times(Engine& e, double* ms, uint64_t* steps) {
   return TC_OK;
 }
 
-int tc_set_kernel_timing(tc_state* s, int enable) {
+int tc_set_kernel_timing(tc_state* s, uint32_t mask) {
   if (!s) return fail(TC_EINVAL, "null state");
-  return set_timing(s->e, enable);
+  return set_timing(s->e, mask);
 }
 
 int tc_kernel_times(tc_state* s, double* ms, uint64_t* steps) {
@@ -610,9 +727,9 @@ int tc_kernel_times(tc_state* s, double* ms, uint64_t* steps) {
   return read_times(s->e, ms, steps);
 }
 
-int tc_multi_set_kernel_timing(tc_multi* s, int enable) {
+int tc_multi_set_kernel_timing(tc_multi* s, uint32_t mask) {
   if (!s) return fail(TC_EINVAL, "null object");
-  return set_timing(s->e, enable);
+  return set_timing(s->e, mask);
 }
 
 int tc_multi_kernel_times(tc_multi* s, double* ms, uint64_t* steps) {

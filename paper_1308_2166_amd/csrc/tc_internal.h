@@ -21,9 +21,13 @@ constexpr int kItems = 16;               // arcs per thread per tile
 constexpr int kTile = kBlock * kItems;   // 4096 arcs per tile
 constexpr int kDigits = 256;
 constexpr int kPasses = 4;
-constexpr int kNumKernels = 10;  // launches per step (k_hist .. k_probe)
+constexpr int kNumKernels = 11;  // launches per step (k_hist .. k_probe)
+constexpr uint32_t kFoldRows = 32;  // k_hist partials summed per k_fold block
 constexpr int kHistTiles = 1;   // tiles per k_hist block
-constexpr int kLookback = 16;   // predecessor statuses read per look-back round
+#ifndef TC_LOOKBACK
+#define TC_LOOKBACK 16
+#endif
+constexpr int kLookback = TC_LOOKBACK;  // predecessor statuses read per look-back round
 
 // j1[] word: kNone, or the replacement position with kSideV set when the
 // smaller endpoint u of W[j1] is its second vertex
@@ -68,6 +72,7 @@ struct SegDesc {
   uint32_t ntiles;        // ceil(2w / kTile)
   uint32_t hblk_off;      // first k_hist block of the segment
   uint32_t nhblk;         // ceil(ntiles / kHistTiles)
+  uint32_t fold_off;      // first k_fold block of the segment
   uint32_t dir_log2;      // log2 of the directory region (slots)
   uint32_t qt_log2;       // log2 of the query-table region (slots)
   uint64_t bm_off;        // first word of the query filter region
@@ -110,6 +115,9 @@ struct StepArgs {
   uint32_t nseg;
   uint32_t ntiles;        // total tiles over segments
   uint32_t nhblk;         // total k_hist blocks over segments
+  uint32_t nfold;         // total k_fold blocks over segments
+  uint32_t* hpart;        // per k_hist block: kPasses x kDigits digit counts
+  uint32_t* mpart;        // per k_hist block: largest vertex id
   uint64_t nest;          // total estimator threads over segments
   uint32_t* tagp;         // device word: this step's directory tag (never 0);
                           // advanced by the step's last kernel
@@ -134,6 +142,8 @@ struct StepArgs {
   uint64_t need_bytes;    // over all segments (a multiple of 16)
   uint32_t* inv;          // per arc slot: its index in the sorted arcs (only
                           // for arcs of needed positions)
+  uint64_t* wq;           // per batch edge: its canonical code (Step 3 reads
+                          // this copy, not the caller's buffer)
   uint32_t* err;          // sticky error bits
 };
 

@@ -1,10 +1,11 @@
 // Device kernels of the bulk estimator update (Tangwongsan, Pavan,
 // Tirthapura, Sec. 4: bulkUpdateAll) for gfx950.
 //
-// One step = k_hist -> k_step1 -> k_pass<0..3> -> k_dir -> k_est -> k_post
-// -> k_probe.
+// One step = k_hist -> k_fold -> k_step1 -> k_pass<0..3> -> k_dir -> k_est
+// -> k_post -> k_probe.
 //
-//  k_hist   digit histograms of the 2w arcs (+ max id, self-loop check)
+//  k_hist   per-tile digit counts of the 2w arcs (+ max id, self-loop check)
+//  k_fold   per-segment digit histograms from the per-tile counts
 //  k_step1  Step 1: which estimators take a new f1, from where; writes f1
 //  k_pass   stable LSD radix pass over 8 bits of the vertex id (onesweep:
 //           wave64 ballot ranking, decoupled look-back, LDS-staged coalesced
@@ -103,6 +104,18 @@ __device__ __forceinline__ uint32_t seg_of_hblk(const StepArgs& a,
   return lo;
 }
 
+// segment of a k_fold block
+__device__ __forceinline__ uint32_t seg_of_fold(const StepArgs& a,
+                                                uint32_t b) {
+  if (a.nseg == 1) return 0;
+  uint32_t lo = 0, hi = a.nseg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (a.segs[mid].fold_off <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // segment of a flat estimator thread
 __device__ __forceinline__ uint32_t seg_of_est(const StepArgs& a,
                                                uint64_t gid) {
@@ -175,6 +188,12 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
     s_seg = seg_of_hblk(a, hb);
     s_max = 0;
   }
+  // this step's directory entries get a fresh tag (0 means empty); every
+  // reader of the tag runs after this kernel
+  if (hb == 0 && tid == 0) {
+    const uint32_t t = *a.tagp + 1u;
+    *a.tagp = t ? t : 1u;
+  }
 #pragma unroll
   for (int d = 0; d < kPasses; ++d) h[d][tid] = 0;
   // empty the Step-3 query tables (first used by k_est of this step)
@@ -202,9 +221,14 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
   uint32_t vmax = 0;
   bool loop = false;
   const bool vec = (reinterpret_cast<uintptr_t>(S.edges) & 15u) == 0;
-  // four arcs (two edges) per thread and iteration; the block covers
-  // kHistTiles tiles so each global bin sees few atomic adds
-  for (uint32_t i = abase + 4 * tid; i < aend; i += 4 * kBlock) {
+  uint64_t* wq = a.wq + S.arc_off / 2;
+  // four arcs (two edges) per thread and round; every round's load is
+  // issued before the first is used
+  constexpr int kRounds = kHistTiles * kTile / (4 * kBlock);
+  uint4 xs[kRounds];
+#pragma unroll
+  for (int it = 0; it < kRounds; ++it) {
+    const uint32_t i = abase + 4 * tid + it * 4 * kBlock;
     uint4 x = make_uint4(0, 0, 0, 0);
     const bool full = i + 4 <= aend;
     if (full && vec) {
@@ -218,14 +242,22 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
       x.x = e0.x;
       x.y = e0.y;
     }
-    const bool v01 = i < aend, v23 = full;
+    xs[it] = x;
+  }
+#pragma unroll
+  for (int it = 0; it < kRounds; ++it) {
+    const uint32_t i = abase + 4 * tid + it * 4 * kBlock;
+    const uint4 x = xs[it];
+    const bool v01 = i < aend, v23 = i + 4 <= aend;
     if (v01) {
       loop |= x.x == x.y;
       vmax = max(vmax, max(x.x, x.y));
+      wq[i >> 1] = canon(x.x, x.y);
     }
     if (v23) {
       loop |= x.z == x.w;
       vmax = max(vmax, max(x.z, x.w));
+      wq[(i >> 1) + 1] = canon(x.z, x.w);
     }
 #pragma unroll
     for (int d = 0; d < kPasses; ++d) {
@@ -238,11 +270,44 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
   if (loop) atomicOr(a.err, kErrSelfLoop);
   atomicMax(&s_max, vmax);
   __syncthreads();
+  // the block's counts go out with plain stores; k_fold sums them, so no
+  // global bin takes one atomic per block
+  uint32_t* hp = a.hpart + (size_t)hb * (kPasses * kDigits);
+#pragma unroll
+  for (int d = 0; d < kPasses; ++d) hp[d * kDigits + tid] = h[d][tid];
+  if (tid == 0) a.mpart[hb] = s_max;
+}
+
+// ---------------------------------------------------------------------------
+// k_fold: per segment, sum the k_hist partials into the digit histograms
+// (kFoldRows partials per block) and take the largest vertex id
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_fold(StepArgs a) {
+  __shared__ uint32_t s_seg, s_max;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_seg = seg_of_fold(a, blockIdx.x);
+    s_max = 0;
+  }
+  __syncthreads();
+  const uint32_t sidx = uniform(s_seg);
+  const SegDesc S = seg_desc(a, sidx);
+  const uint32_t r0 = S.hblk_off + (blockIdx.x - S.fold_off) * kFoldRows;
+  const uint32_t r1 = min(r0 + kFoldRows, S.hblk_off + S.nhblk);
+  uint32_t acc[kPasses] = {};
+#pragma unroll 4
+  for (uint32_t rr = r0; rr < r1; ++rr) {
+    const uint32_t* row = a.hpart + (size_t)rr * (kPasses * kDigits);
+#pragma unroll
+    for (int d = 0; d < kPasses; ++d) acc[d] += row[d * kDigits + tid];
+  }
+  if ((uint32_t)tid < r1 - r0) atomicMax(&s_max, a.mpart[r0 + tid]);
+  __syncthreads();
   SegWork* wk = a.work + sidx;
-  if (tid == 0) atomicMax(&wk->maxid, s_max);
 #pragma unroll
   for (int d = 0; d < kPasses; ++d)
-    if (h[d][tid]) atomicAdd(&wk->hist[d][tid], h[d][tid]);
+    if (acc[d]) atomicAdd(&wk->hist[d][tid], acc[d]);
+  if (tid == 0) atomicMax(&wk->maxid, s_max);
 }
 
 // ---------------------------------------------------------------------------
@@ -344,36 +409,38 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
   __syncthreads();
 
   // stable rank of each arc among equal digits of its wave: a ballot match
-  // finds the lanes sharing the digit; the lowest of them adds the group
-  // size to the wave's bin with a returning LDS atomic (the atomics of the
-  // kItems rounds are issued back to back and land in program order, so
-  // each returns the count of earlier equal digits); the group then reads
-  // the returned base from its leader lane
+  // finds the lanes sharing the digit (per digit bit one ballot and one
+  // three-input bit operation per mask half: mask &= ~(bit ^ ballot)); the
+  // lowest of them adds the group size to the wave's bin with a returning
+  // LDS atomic (the atomics of the kItems rounds are issued back to back
+  // and land in program order, so each returns the count of earlier equal
+  // digits); the group then reads the returned base from its leader lane
   const uint64_t lt_mask = (1ull << lane) - 1ull;
-  uint32_t lead[kItems];
+  uint32_t lb[kItems];  // leader lane | (equal digits in lower lanes) << 8
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
     const uint32_t li = wave * 64 * kItems + i * 64 + lane;
     const bool valid = li < nv;
     const uint32_t dg = (uint32_t)(el[i] >> (32 + 8 * P)) & 255u;
-    uint64_t mm = __ballot(valid);
+    const uint64_t vm = __ballot(valid);
+    uint32_t lo = (uint32_t)vm, hi = (uint32_t)(vm >> 32);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const bool bit = (dg >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      mm &= bit ? bb : ~bb;
+      const uint32_t t = (uint32_t)((int32_t)(dg << (31 - b)) >> 31);  // 0 or ~0
+      const uint64_t bb = __ballot(t != 0u);
+      lo = __builtin_amdgcn_bitop3_b32(lo, t, (uint32_t)bb, 0x90);
+      hi = __builtin_amdgcn_bitop3_b32(hi, t, (uint32_t)(bb >> 32), 0x90);
     }
+    const uint64_t mm = ((uint64_t)hi << 32) | lo;
     const uint32_t below = __popcll(mm & lt_mask);
-    lead[i] = (uint32_t)__ffsll((long long)mm) - 1u;  // lowest lane of the group
     uint32_t base = 0;
     if (valid && below == 0) base = atomicAdd(&s_wh[wave][dg], (uint32_t)__popcll(mm));
-    rk[i] = base | (below << 16);
+    rk[i] = base;
+    lb[i] = (((uint32_t)__ffsll((long long)mm) - 1u) & 63u) | (below << 8);
   }
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    const uint32_t base = __shfl(rk[i] & 0xFFFFu, (int)lead[i]);
-    rk[i] = base + (rk[i] >> 16);
-  }
+  for (int i = 0; i < kItems; ++i)
+    rk[i] = __shfl(rk[i], (int)(lb[i] & 63u)) + (lb[i] >> 8);
   __syncthreads();
 
   // per digit (thread = digit): wave offsets, tile count, tile offsets
@@ -401,11 +468,17 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
     uint32_t polls = 0;
     bool done = false;
     while (!done) {
+      // branch-free: indexes below tile 0 read tile 0 and count as an
+      // inclusive zero, so every load of the window is in flight at once
       uint32_t v[kLookback];
 #pragma unroll
+      for (int t = 0; t < kLookback; ++t) {
+        const uint32_t jt = j > (uint32_t)t ? j - 1 - t : 0u;
+        v[t] = ld_relaxed(&st[(size_t)jt * kDigits + tid]);
+      }
+#pragma unroll
       for (int t = 0; t < kLookback; ++t)
-        v[t] = (j > (uint32_t)t) ? ld_relaxed(&st[(size_t)(j - 1 - t) * kDigits + tid])
-                                 : (kFlagInc | 0u);
+        if (j <= (uint32_t)t) v[t] = kFlagInc | 0u;
       uint32_t used = 0;
       bool wait = false;
 #pragma unroll
@@ -708,7 +781,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
   const SegDesc S = seg_desc(a, sidx);
   if ((*a.err & kErrFatal) == 0) {
     const uint32_t ebase = (gtile - S.tile_off) * (kTile / 2);
-    const uint2* W = reinterpret_cast<const uint2*>(S.edges);
+    const uint64_t* wq = a.wq + S.arc_off / 2;
     const QSlot* qt = a.qt + S.qt_off;
     const uint32_t mask = (1u << S.qt_log2) - 1u;
     const uint32_t* bm = a.bm + S.bm_off;
@@ -716,8 +789,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
     for (int k = 0; k < kProbeEdges; ++k) {
       const uint32_t j = ebase + k * kBlock + tid;
       if (j >= S.w) break;
-      const uint2 ed = W[j];
-      const uint64_t q = canon(ed.x, ed.y);
+      const uint64_t q = wq[j];
       const uint64_t hq = mix64(q);
       // the filter (a few MB, stays in L2) rules out nearly every edge
       const uint32_t bit = (uint32_t)(hq >> 32) & bmask;
@@ -730,11 +802,6 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
         hh = (hh + 1) & mask;
       }
     }
-  }
-  // the next step's directory entries get a fresh tag (0 means empty)
-  if (gtile == 0 && tid == 0) {
-    const uint32_t t = *a.tagp + 1u;
-    *a.tagp = t ? t : 1u;
   }
   // this step no longer needs the per-segment work area: reset it
   const uint32_t words = a.nseg * (uint32_t)(sizeof(SegWork) / 4);
@@ -779,36 +846,37 @@ __global__ __launch_bounds__(kBlock) void k_fill32(uint32_t* p, uint64_t n,
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-// ev: optional kNumKernels + 1 events recorded around the kernels
-hipError_t launch_step(const StepArgs& a, hipStream_t st, hipEvent_t* ev) {
+// The step runs in three phases (see the engine): A groups the batch
+// (k_hist .. k_dir), B is k_est, C is Step 3 (k_post, k_probe) and may run
+// on another stream, overlapping the next step's phase A.  ev: optional
+// 2 * kNumKernels events; kernel k is bracketed by ev[2k] and ev[2k+1]
+// when those are non-null (untimed kernels get no event).
+hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st,
+                        hipEvent_t* ev) {
   const dim3 blk(kBlock);
   const dim3 tiles(a.ntiles);
   const dim3 ests((uint32_t)((a.nest + kBlock - 1) / kBlock));
-  int k = 0;
-  auto mark = [&]() {
-    if (ev) (void)hipEventRecord(ev[k++], st);
+  auto run = [&](int k, auto&& launch) {
+    const bool t = ev && ev[2 * k];
+    if (t) (void)hipEventRecord(ev[2 * k], st);
+    launch();
+    if (t) (void)hipEventRecord(ev[2 * k + 1], st);
   };
-  mark();
-  hipLaunchKernelGGL(k_hist, dim3(a.nhblk), blk, 0, st, a);
-  mark();
-  hipLaunchKernelGGL(k_step1, ests, blk, 0, st, a);
-  mark();
-  hipLaunchKernelGGL(k_pass<0>, tiles, blk, 0, st, a);
-  mark();
-  hipLaunchKernelGGL(k_pass<1>, tiles, blk, 0, st, a);
-  mark();
-  hipLaunchKernelGGL(k_pass<2>, tiles, blk, 0, st, a);
-  mark();
-  hipLaunchKernelGGL(k_pass<3>, tiles, blk, 0, st, a);
-  mark();
-  hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a);
-  mark();
-  hipLaunchKernelGGL(k_est, ests, blk, 0, st, a);
-  mark();
-  hipLaunchKernelGGL(k_post, ests, blk, 0, st, a);
-  mark();
-  hipLaunchKernelGGL(k_probe, tiles, blk, 0, st, a);
-  mark();
+  if (phase == 0) {
+    run(0, [&] { hipLaunchKernelGGL(k_hist, dim3(a.nhblk), blk, 0, st, a); });
+    run(1, [&] { hipLaunchKernelGGL(k_fold, dim3(a.nfold), blk, 0, st, a); });
+    run(2, [&] { hipLaunchKernelGGL(k_step1, ests, blk, 0, st, a); });
+    run(3, [&] { hipLaunchKernelGGL(k_pass<0>, tiles, blk, 0, st, a); });
+    run(4, [&] { hipLaunchKernelGGL(k_pass<1>, tiles, blk, 0, st, a); });
+    run(5, [&] { hipLaunchKernelGGL(k_pass<2>, tiles, blk, 0, st, a); });
+    run(6, [&] { hipLaunchKernelGGL(k_pass<3>, tiles, blk, 0, st, a); });
+    run(7, [&] { hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a); });
+  } else if (phase == 1) {
+    run(8, [&] { hipLaunchKernelGGL(k_est, ests, blk, 0, st, a); });
+  } else {
+    run(9, [&] { hipLaunchKernelGGL(k_post, ests, blk, 0, st, a); });
+    run(10, [&] { hipLaunchKernelGGL(k_probe, tiles, blk, 0, st, a); });
+  }
   return hipGetLastError();
 }
 

@@ -391,3 +391,68 @@ def test_served_streams_equal_their_alone_runs(tc):
                 o.process(np_edges(c))
             assert_same(alone.state(), o.state(), f"stream {s}")
             assert S == o.sum()
+
+
+# -- a resident stream in one call (Step 3 of batch k overlaps batch k+1) -------
+
+@pytest.mark.parametrize("m,w,r", [(20000, 2048, 4096), (60000, 9001, 20000),
+                                   (5000, 5000, 3000), (4999, 5000, 3000),
+                                   (700, 1, 50), (3001, 1000, 2000)])
+def test_process_stream_equals_batches(tc, m, w, r):
+    n = max(60, m // 8)
+    E = np_edges(inputs.gnm(n, m, seed=m + w))
+    say(f"  stream m={m} w={w} r={r}")
+    dev = to_dev(E)
+    g = tc.Bank(r, 17)
+    g.process_stream(dev, w)
+    o = O.run_stream(E, r, 17, w)
+    assert_same(g.state(), o.state(), "process_stream")
+    S, mm, tau = tc.tc_estimate_ex(g.h)
+    assert S == o.sum() and mm == m and g.batch == o.batch == -(-m // w)
+    # a second call continues the same bank (batch indices carry on)
+    E2 = np_edges(inputs.gnm(n + 50, 2 * w + 3, seed=m))
+    E2 = E2 + np.uint32(n + 100)  # new vertex ids: no repeated edge
+    g.process_stream(to_dev(E2), w)
+    for j in range(0, len(E2), w):
+        assert o.process(E2[j:j + w], "bulk") == O.OK
+    assert_same(g.state(), o.state(), "second call")
+
+
+def test_process_stream_rmat20_first_batches(tc):
+    G, r, w, seed = inputs.workload("rmat20", device="cuda")
+    k = 3
+    sub = G[:k * w]
+    g = tc.Bank(r, seed)
+    g.process_stream(sub, w)
+    o = O.run_stream(np_edges(sub), r, seed, w)
+    assert_same(g.state(), o.state(), "rmat20 3 batches")
+
+
+def test_process_stream_in_a_graph(tc):
+    E = np_edges(inputs.rmat(13, 20000, seed=15))
+    dev = to_dev(E)
+    g = tc.Bank(4000, 33)
+    tc.tc_reserve(g.h, 3000)
+    gr = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(gr, stream=cs):
+        tc.tc_reset(g.h, cs)
+        g.process_stream(dev, 3000, cs)
+    o = O.run_stream(E, 4000, 33, 3000)
+    for rep in range(3):
+        gr.replay()
+        torch.cuda.synchronize()
+        assert_same(g.state(), o.state(), f"replay {rep}")
+        _ = torch.ones(1000, device="cuda").sum().item()
+
+
+def test_process_stream_arguments(tc):
+    g = tc.Bank(100, 1)
+    dev = to_dev(np_edges(inputs.gnm(50, 200, seed=1)))
+    for w in (0, (1 << 28) + 1):
+        with pytest.raises(tc.TcError) as ei:
+            g.process_stream(dev, w)
+        assert ei.value.code == tc.TC_EINVAL
+    g.process_stream(dev[:0], 10)  # empty stream: nothing happens
+    assert g.m == 0 and g.batch == 0
