@@ -77,9 +77,10 @@ void dfree(T*& p) {
 // phases touch exists twice and step s uses copy s & 1.
 struct ParityScratch {
   SegWork* work = nullptr;    // per-segment histograms, counters, modes
-  QSlot* qt = nullptr;        // Step-3 query tables
-  uint32_t* bm = nullptr;     // Step-3 query filters
-  uint64_t* wq = nullptr;     // canonical copy of the batch edges
+  uint32_t* qown = nullptr;   // Step-3 query tables (structure of arrays)
+  uint64_t* qkey = nullptr;
+  uint32_t* qlim = nullptr;
+  uint8_t* qfp = nullptr;
   SegDesc* segs = nullptr;    // device copy of the step's descriptors
 };
 
@@ -105,7 +106,7 @@ struct Engine {
   uint32_t* h_err = nullptr;             // pinned
 
   // step scratch shared by the phases that never overlap
-  uint64_t cap_arcs = 0, cap_tiles = 0, cap_dir = 0, cap_qt = 0, cap_bm = 0,
+  uint64_t cap_arcs = 0, cap_tiles = 0, cap_dir = 0, cap_qt = 0,
            cap_need = 0;
   uint32_t cap_segs = 0;
   uint64_t* arcs[2] = {nullptr, nullptr};
@@ -198,9 +199,10 @@ struct Engine {
     dfree(arcs[0]), dfree(arcs[1]), dfree(status[0]), dfree(status[1]);
     dfree(dir), dfree(need), dfree(inv), dfree(hpart), dfree(mpart);
     for (ParityScratch& p : par) {
-      dfree(p.work), dfree(p.qt), dfree(p.bm), dfree(p.wq), dfree(p.segs);
+      dfree(p.work), dfree(p.qown), dfree(p.qkey), dfree(p.qlim), dfree(p.qfp);
+      dfree(p.segs);
     }
-    cap_arcs = cap_tiles = cap_dir = cap_qt = cap_bm = cap_need = 0;
+    cap_arcs = cap_tiles = cap_dir = cap_qt = cap_need = 0;
     cap_segs = 0;
   }
 
@@ -248,10 +250,10 @@ struct Engine {
   }
 
   int ensure_scratch(uint64_t arcs_n, uint64_t tiles, uint64_t dir_n,
-                     uint64_t qt_n, uint64_t bm_n, uint64_t need_n, uint32_t nseg,
+                     uint64_t qt_n, uint64_t need_n, uint32_t nseg,
                      hipStream_t st) {
     if (arcs_n <= cap_arcs && tiles <= cap_tiles && dir_n <= cap_dir &&
-        qt_n <= cap_qt && bm_n <= cap_bm && need_n <= cap_need && nseg <= cap_segs)
+        qt_n <= cap_qt && need_n <= cap_need && nseg <= cap_segs)
       return TC_OK;
     wait_all();
     (void)hipStreamSynchronize(st);
@@ -260,7 +262,6 @@ struct Engine {
     cap_tiles = std::max(tiles, cap_tiles);
     cap_dir = std::max(dir_n, cap_dir);
     cap_qt = std::max(qt_n, cap_qt);
-    cap_bm = std::max(bm_n, cap_bm);
     cap_need = std::max(need_n, cap_need);
     cap_segs = std::max(nseg, cap_segs);
     bool bad = dalloc(&arcs[0], cap_arcs) || dalloc(&arcs[1], cap_arcs) ||
@@ -271,8 +272,8 @@ struct Engine {
                dalloc(&hpart, cap_tiles * kPasses * kDigits) ||
                dalloc(&mpart, cap_tiles);
     for (ParityScratch& p : par)
-      bad = bad || dalloc(&p.work, cap_segs) || dalloc(&p.qt, cap_qt) ||
-            dalloc(&p.bm, cap_bm) || dalloc(&p.wq, cap_arcs / 2 + 1) ||
+      bad = bad || dalloc(&p.work, cap_segs) || dalloc(&p.qown, cap_qt) ||
+            dalloc(&p.qkey, cap_qt) || dalloc(&p.qlim, cap_qt) || dalloc(&p.qfp, cap_qt) ||
             dalloc(&p.segs, cap_segs);
     if (bad) {
       free_scratch();
@@ -285,8 +286,8 @@ struct Engine {
           hipMemsetAsync(need, 0, cap_need, st);
     for (ParityScratch& p : par)
       bad = bad || hipMemsetAsync(p.work, 0, sizeof(SegWork) * cap_segs, st) ||
-            hipMemsetAsync(p.qt, 0, sizeof(QSlot) * cap_qt, st) ||
-            hipMemsetAsync(p.bm, 0, 4 * cap_bm, st);
+            hipMemsetAsync(p.qown, 0xFF, 4 * cap_qt, st) ||
+            hipMemsetAsync(p.qfp, 0, cap_qt, st);
     if (bad || hipStreamSynchronize(st))
       return fail(TC_EHIP, "clearing step scratch failed");
     return TC_OK;
@@ -340,7 +341,7 @@ struct Engine {
     std::vector<SegDesc> segs;
     segs.reserve(nchunks);
     std::vector<char> seen(nbanks, 0);
-    uint64_t arcs_n = 0, tiles = 0, dir_n = 0, qt_n = 0, bm_n = 0, need_n = 0, nest = 0,
+    uint64_t arcs_n = 0, tiles = 0, dir_n = 0, qt_n = 0, need_n = 0, nest = 0,
              hblks = 0, folds = 0;
     for (uint32_t k = 0; k < nchunks; ++k) {
       const uint32_t b = ids[k];
@@ -373,9 +374,6 @@ struct Engine {
       folds += (d.nhblk + kFoldRows - 1) / kFoldRows;
       d.dir_log2 = dir_log2_for(w[k]);
       d.qt_log2 = qt_log2_for(r[b]);
-      d.bm_log2 = qt_log2_for(r[b]) + 3;  // 16 bits per estimator
-      d.bm_off = bm_n;
-      bm_n += (1ull << d.bm_log2) / 32;
       d.need_off = (uint32_t)need_n;
       need_n += (w[k] + 15) / 16 * 16;
       arcs_n += 2ull * w[k];
@@ -388,7 +386,7 @@ struct Engine {
     if (segs.empty()) return TC_OK;
     if (tiles >= 0x7FFFFFFFull) return fail(TC_EINVAL, "step too large");
     if (need_n >= 0xFFFFFFFFull) return fail(TC_EINVAL, "step too large");
-    int rc = ensure_scratch(arcs_n, tiles, dir_n, qt_n, bm_n, need_n,
+    int rc = ensure_scratch(arcs_n, tiles, dir_n, qt_n, need_n,
                             (uint32_t)segs.size(), st);
     if (rc || reserve) return rc;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -418,17 +416,17 @@ struct Engine {
     a.arcs[0] = arcs[0], a.arcs[1] = arcs[1];
     a.status[0] = status[0], a.status[1] = status[1];
     a.dir = dir;
-    a.qt = P.qt;
+    a.qown = P.qown;
+    a.qkey = P.qkey;
+    a.qlim = P.qlim;
+    a.qfp = P.qfp;
     a.qt_slots = qt_n;
-    a.bm = P.bm;
-    a.bm_words = bm_n;
     a.j1 = J1;
     a.qq = QQ;
     a.qthr = QT;
     a.need = need;
     a.need_bytes = need_n;
     a.inv = inv;
-    a.wq = P.wq;
     a.err = err;
     if (a.nseg > 1) {
       rc = stage_descs(segs, P.segs, st, capturing);

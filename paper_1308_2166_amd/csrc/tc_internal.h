@@ -75,8 +75,6 @@ struct SegDesc {
   uint32_t fold_off;      // first k_fold block of the segment
   uint32_t dir_log2;      // log2 of the directory region (slots)
   uint32_t qt_log2;       // log2 of the query-table region (slots)
-  uint64_t bm_off;        // first word of the query filter region
-  uint32_t bm_log2;       // log2 of the query filter region (bits)
   uint32_t need_off;      // first byte of the "position needed" bytes (w bytes)
 };
 
@@ -99,15 +97,12 @@ struct DirSlot {
   uint32_t end;
 };
 
-// Step-3 query table entry: estimator `est` waits for closing edge `key` at
-// a batch position >= `thr`.  Every waiting estimator owns one slot (equal
-// keys share a probe cluster).  The table is reset to key = kEmpty at the
-// start of every step, so the key itself is the claim word.
-struct QSlot {
-  uint64_t key;
-  uint32_t est;
-  uint32_t thr;
-};
+// Step-3 query table (structure of arrays, one region per segment, linear
+// probing): slot s belongs to estimator qown[s] (kNone = free), which waits
+// for closing edge qkey[s] at a batch position >= qlim[s]; qfp[s] is a
+// nonzero 8-bit fingerprint of the key's hash (0 = free) and is what a
+// probe scans.  Every waiting estimator owns one slot (equal keys share a
+// probe cluster).  qown and qfp are reset at the start of every step.
 
 struct StepArgs {
   const SegDesc* segs;    // device copy of all segment descriptors
@@ -130,10 +125,11 @@ struct StepArgs {
   uint64_t* arcs[2];      // ping-pong arc buffers
   uint32_t* status[2];    // look-back status, [ntiles][kDigits] each
   DirSlot* dir;
-  QSlot* qt;
+  uint32_t* qown;         // query table: owning estimator per slot
+  uint64_t* qkey;         // query table: closing edge per slot
+  uint32_t* qlim;         // query table: first closing position per slot
+  uint8_t* qfp;           // query table: key fingerprint per slot
   uint64_t qt_slots;      // query-table slots over all segments
-  uint32_t* bm;           // query filter: one bit per hashed closing edge
-  uint64_t bm_words;      // filter words over all segments
   uint32_t* j1;           // per estimator: Step-1 replacement (see kSideV)
   uint64_t* qq;           // per estimator: closing edge it waits for, or kEmpty
   uint32_t* qthr;         // per estimator: first batch position that closes it
@@ -142,8 +138,6 @@ struct StepArgs {
   uint64_t need_bytes;    // over all segments (a multiple of 16)
   uint32_t* inv;          // per arc slot: its index in the sorted arcs (only
                           // for arcs of needed positions)
-  uint64_t* wq;           // per batch edge: its canonical code (Step 3 reads
-                          // this copy, not the caller's buffer)
   uint32_t* err;          // sticky error bits
 };
 

@@ -17,7 +17,7 @@
 //  k_dir    vertex -> [start, end) of its arcs (tag-versioned directory),
 //           and the sorted index of the arcs of positions Step 1 picked
 //  k_est    Step 2 for every estimator; records its Step-3 closing edge
-//  k_post   Step 3 queries into a hash table (+ an L2-sized filter)
+//  k_post   Step 3 queries into a hash table with a fingerprint byte per slot
 //  k_probe  Step 3: one pass over W closes the estimators waiting for it
 #include <algorithm>
 
@@ -198,15 +198,16 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
   for (int d = 0; d < kPasses; ++d) h[d][tid] = 0;
   // empty the Step-3 query tables (first used by k_est of this step)
   {
-    uint4* q4 = reinterpret_cast<uint4*>(a.qt);
-    const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
-    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.qt_slots;
+    // (slot counts are multiples of 1024, so whole uint4s cover them)
+    uint4* o4 = reinterpret_cast<uint4*>(a.qown);
+    const uint4 none = make_uint4(kNone, kNone, kNone, kNone);
+    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.qt_slots / 4;
          t += (uint64_t)a.nhblk * kBlock)
-      q4[t] = ones;
-    uint4* b4 = reinterpret_cast<uint4*>(a.bm);
-    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.bm_words / 4;
+      o4[t] = none;
+    uint4* f4 = reinterpret_cast<uint4*>(a.qfp);
+    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.qt_slots / 16;
          t += (uint64_t)a.nhblk * kBlock)
-      b4[t] = make_uint4(0, 0, 0, 0);
+      f4[t] = make_uint4(0, 0, 0, 0);
     uint4* n4 = reinterpret_cast<uint4*>(a.need);
     for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.need_bytes / 16;
          t += (uint64_t)a.nhblk * kBlock)
@@ -221,7 +222,6 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
   uint32_t vmax = 0;
   bool loop = false;
   const bool vec = (reinterpret_cast<uintptr_t>(S.edges) & 15u) == 0;
-  uint64_t* wq = a.wq + S.arc_off / 2;
   // four arcs (two edges) per thread and round; every round's load is
   // issued before the first is used
   constexpr int kRounds = kHistTiles * kTile / (4 * kBlock);
@@ -252,12 +252,10 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
     if (v01) {
       loop |= x.x == x.y;
       vmax = max(vmax, max(x.x, x.y));
-      wq[i >> 1] = canon(x.x, x.y);
     }
     if (v23) {
       loop |= x.z == x.w;
       vmax = max(vmax, max(x.z, x.w));
-      wq[(i >> 1) + 1] = canon(x.z, x.w);
     }
 #pragma unroll
     for (int d = 0; d < kPasses; ++d) {
@@ -642,21 +640,13 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
 // register estimator `est` as waiting for closing edge q at a position
 // >= thr: claim an empty slot of q's probe sequence with one CAS (relaxed:
 // the slot's other fields are read only by the next kernel)
-__device__ __forceinline__ void qt_post(QSlot* qt, uint32_t mask, uint64_t q,
-                                        uint32_t est, uint32_t thr,
-                                        uint32_t* err) {
-  uint32_t h = (uint32_t)mix64(q) & mask;
-  for (uint32_t probe = 0; probe <= mask; ++probe) {
-    unsigned long long* k = reinterpret_cast<unsigned long long*>(&qt[h].key);
-    if (atomicCAS(k, (unsigned long long)kEmpty, (unsigned long long)q) ==
-        kEmpty) {
-      qt[h].est = est;
-      qt[h].thr = thr;
-      return;
-    }
-    h = (h + 1) & mask;
-  }
-  atomicOr(err, kErrProbe);
+// query-table home slot and fingerprint of a closing edge (independent
+// bits of one hash)
+__device__ __forceinline__ uint32_t q_home(uint64_t hq, uint32_t mask) {
+  return (uint32_t)hq & mask;
+}
+__device__ __forceinline__ uint8_t q_fp(uint64_t hq) {
+  return (uint8_t)(1u + (uint32_t)(hq >> 56) % 255u);  // never 0 (free)
 }
 
 __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
@@ -742,13 +732,22 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   uint64_t q = kEmpty;
   if (r2 != kEmpty && !closed) q = closing(r1, r2);
   a.qq[e] = q;
+  // first claim on the query's home slot: a plain store (among racing
+  // stores one value lands whole); k_post checks which estimator won and
+  // moves the others on, so the common case needs no atomic
+  if (q != kEmpty)
+    a.qown[S.qt_off + q_home(mix64(q), (1u << S.qt_log2) - 1u)] = (uint32_t)e;
   a.qthr[e] = (p2 == kNone) ? 0u : p2 + 1;  // closes at a position >= this
   a.r2[e] = r2;
   a.cc[e] = (uint32_t)c | (closed ? kClosed : 0u);
 }
 
 // ---------------------------------------------------------------------------
-// k_post: every waiting estimator into its segment's query table and filter
+// k_post: every waiting estimator owns a slot of its segment's query table:
+// the home slot if its claim there stood, else the first free slot after
+// it, taken with a CAS (a slot once owned stays owned, so the slots
+// between a key's home and its slot are all occupied); then the slot's key,
+// limit and fingerprint
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_post(StepArgs a) {
   const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -759,10 +758,23 @@ __global__ __launch_bounds__(kBlock) void k_post(StepArgs a) {
   const uint64_t e = S.est_off + (gid - S.gest_off);
   const uint64_t q = a.qq[e];
   if (q == kEmpty) return;
-  qt_post(a.qt + S.qt_off, (1u << S.qt_log2) - 1u, q, (uint32_t)e, a.qthr[e],
-          a.err);
-  const uint32_t bit = (uint32_t)(mix64(q) >> 32) & ((1u << S.bm_log2) - 1u);
-  atomicOr(&a.bm[S.bm_off + (bit >> 5)], 1u << (bit & 31));
+  const uint32_t mask = (1u << S.qt_log2) - 1u;
+  const uint64_t hq = mix64(q);
+  uint32_t* own = a.qown + S.qt_off;
+  uint32_t s = q_home(hq, mask);
+  if (own[s] != (uint32_t)e) {
+    uint32_t probe = 0;
+    do {
+      s = (s + 1) & mask;
+      if (++probe > mask) {  // cannot happen: at most half the slots are used
+        atomicOr(a.err, kErrProbe);
+        return;
+      }
+    } while (atomicCAS(&own[s], kNone, (uint32_t)e) != kNone);
+  }
+  a.qkey[S.qt_off + s] = q;
+  a.qlim[S.qt_off + s] = a.qthr[e];
+  a.qfp[S.qt_off + s] = q_fp(hq);
 }
 
 // ---------------------------------------------------------------------------
@@ -781,25 +793,27 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
   const SegDesc S = seg_desc(a, sidx);
   if ((*a.err & kErrFatal) == 0) {
     const uint32_t ebase = (gtile - S.tile_off) * (kTile / 2);
-    const uint64_t* wq = a.wq + S.arc_off / 2;
-    const QSlot* qt = a.qt + S.qt_off;
+    const uint2* W = reinterpret_cast<const uint2*>(S.edges);
     const uint32_t mask = (1u << S.qt_log2) - 1u;
-    const uint32_t* bm = a.bm + S.bm_off;
-    const uint32_t bmask = (1u << S.bm_log2) - 1u;
+    const uint8_t* fp = a.qfp + S.qt_off;
+    const uint64_t* key = a.qkey + S.qt_off;
+    const uint32_t* lim = a.qlim + S.qt_off;
+    const uint32_t* own = a.qown + S.qt_off;
     for (int k = 0; k < kProbeEdges; ++k) {
       const uint32_t j = ebase + k * kBlock + tid;
       if (j >= S.w) break;
-      const uint64_t q = wq[j];
+      const uint2 ed = W[j];
+      const uint64_t q = canon(ed.x, ed.y);
       const uint64_t hq = mix64(q);
-      // the filter (a few MB, stays in L2) rules out nearly every edge
-      const uint32_t bit = (uint32_t)(hq >> 32) & bmask;
-      if (!((bm[bit >> 5] >> (bit & 31)) & 1u)) continue;
-      uint32_t hh = (uint32_t)hq & mask;
+      const uint8_t f = q_fp(hq);
+      // the fingerprints (one byte per slot, a few MB, stay in L2) rule out
+      // nearly every edge; a matching one is checked against the key
+      uint32_t s = q_home(hq, mask);
       for (uint32_t probe = 0; probe <= mask; ++probe) {
-        const QSlot sl = qt[hh];
-        if (sl.key == kEmpty) break;
-        if (sl.key == q && j >= sl.thr) atomicOr(&a.cc[sl.est], kClosed);
-        hh = (hh + 1) & mask;
+        const uint8_t g = fp[s];
+        if (g == 0) break;
+        if (g == f && key[s] == q && j >= lim[s]) atomicOr(&a.cc[own[s]], kClosed);
+        s = (s + 1) & mask;
       }
     }
   }
