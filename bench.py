@@ -40,19 +40,22 @@ def log(*a):
 
 def alg_bytes(kernel: str, w: int, r: int, nontrivial: list) -> float:
     """Bytes the step's algorithm must move per launch of `kernel` (see the
-    design notes): streamed inputs/outputs only, no table or gather traffic."""
+    design notes): streamed inputs/outputs only, no table or gather traffic,
+    nothing for the radix bookkeeping (the fold, k_csum)."""
     arcs = 2 * w
     if kernel == "k_hist":
         return 8.0 * w
-    if kernel.startswith("k_pass"):
-        p = int(kernel[7])
+    if kernel.startswith("k_cnt") or kernel.startswith("k_scat"):
+        p = int(kernel[kernel.index("<") + 1])
         if not nontrivial[p]:
             return 0.0
         first = not any(nontrivial[:p])
+        if kernel.startswith("k_cnt"):
+            return 0.0 if first else arcs * 4.0
         return arcs * ((4.0 if first else 8.0) + 8.0)
     if kernel == "k_dir":
         return arcs * 8.0
-    if kernel == "k_step1":
+    if kernel == "k_fold_step1":
         return r * 4.0
     if kernel == "k_est":
         return r * (20.0 + 4.0 + 12.0 + 12.0)
@@ -252,8 +255,9 @@ def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command, time
     ff = calib_bytes / (fcopy * 1024) if fcopy else None
     fw = calib_bytes / (wcopy * 1024) if wcopy else None
     kernels = [k for k in durs if k.startswith("k_")]
-    order = ["k_hist", "k_fold", "k_step1", "k_pass<0>", "k_pass<1>", "k_pass<2>", "k_pass<3>",
-             "k_dir", "k_est", "k_post", "k_probe"]
+    order = (["k_hist", "k_fold_step1", "k_scat<0>"]
+             + [f"{k}<{p}>" for p in range(1, 4) for k in ("k_cnt", "k_csum", "k_scat")]
+             + ["k_dir", "k_est", "k_post", "k_probe"])
     kernels.sort(key=lambda k: order.index(k) if k in order else 99)
     per = {}
     lines = ["| kernel | launches | avg us | min us | max us | avg us, timed region "

@@ -110,7 +110,7 @@ struct Engine {
            cap_need = 0;
   uint32_t cap_segs = 0;
   uint64_t* arcs[2] = {nullptr, nullptr};
-  uint32_t* status[2] = {nullptr, nullptr};
+  uint32_t* csum = nullptr;  // radix chunk sums / prefixes
   DirSlot* dir = nullptr;
   uint8_t* need = nullptr;
   uint32_t* inv = nullptr;
@@ -196,7 +196,7 @@ struct Engine {
   }
 
   void free_scratch() {
-    dfree(arcs[0]), dfree(arcs[1]), dfree(status[0]), dfree(status[1]);
+    dfree(arcs[0]), dfree(arcs[1]), dfree(csum);
     dfree(dir), dfree(need), dfree(inv), dfree(hpart), dfree(mpart);
     for (ParityScratch& p : par) {
       dfree(p.work), dfree(p.qown), dfree(p.qkey), dfree(p.qlim), dfree(p.qfp);
@@ -265,8 +265,7 @@ struct Engine {
     cap_need = std::max(need_n, cap_need);
     cap_segs = std::max(nseg, cap_segs);
     bool bad = dalloc(&arcs[0], cap_arcs) || dalloc(&arcs[1], cap_arcs) ||
-               dalloc(&status[0], cap_tiles * kDigits) ||
-               dalloc(&status[1], cap_tiles * kDigits) ||
+               dalloc(&csum, ((cap_tiles + kChunk - 1) / kChunk + cap_segs) * kPasses * kDigits) ||
                dalloc(&dir, cap_dir) || dalloc(&need, cap_need) ||
                dalloc(&inv, cap_arcs) ||
                dalloc(&hpart, cap_tiles * kPasses * kDigits) ||
@@ -280,9 +279,7 @@ struct Engine {
       return fail(TC_ENOMEM, "device allocation of step scratch failed");
     }
     // zero = "no tag" for the directory, cleared look-back and work areas
-    bad = hipMemsetAsync(status[0], 0, cap_tiles * kDigits * 4, st) ||
-          hipMemsetAsync(status[1], 0, cap_tiles * kDigits * 4, st) ||
-          hipMemsetAsync(dir, 0, sizeof(DirSlot) * cap_dir, st) ||
+    bad = hipMemsetAsync(dir, 0, sizeof(DirSlot) * cap_dir, st) ||
           hipMemsetAsync(need, 0, cap_need, st);
     for (ParityScratch& p : par)
       bad = bad || hipMemsetAsync(p.work, 0, sizeof(SegWork) * cap_segs, st) ||
@@ -342,7 +339,7 @@ struct Engine {
     segs.reserve(nchunks);
     std::vector<char> seen(nbanks, 0);
     uint64_t arcs_n = 0, tiles = 0, dir_n = 0, qt_n = 0, need_n = 0, nest = 0,
-             hblks = 0, folds = 0;
+             hblks = 0, chunks = 0;
     for (uint32_t k = 0; k < nchunks; ++k) {
       const uint32_t b = ids[k];
       if (b >= nbanks) return fail(TC_EINVAL, "bank id out of range");
@@ -370,8 +367,9 @@ struct Engine {
       d.hblk_off = (uint32_t)hblks;
       d.nhblk = (d.ntiles + kHistTiles - 1) / kHistTiles;
       hblks += d.nhblk;
-      d.fold_off = (uint32_t)folds;
-      folds += (d.nhblk + kFoldRows - 1) / kFoldRows;
+      d.chunk_off = (uint32_t)chunks;
+      d.nchunks = (d.ntiles + kChunk - 1) / kChunk;
+      chunks += d.nchunks;
       d.dir_log2 = dir_log2_for(w[k]);
       d.qt_log2 = qt_log2_for(r[b]);
       d.need_off = (uint32_t)need_n;
@@ -406,7 +404,7 @@ struct Engine {
     a.seg0 = segs[0];
     a.ntiles = (uint32_t)tiles;
     a.nhblk = (uint32_t)hblks;
-    a.nfold = (uint32_t)folds;
+    a.nstep1 = (uint32_t)((nest + kBlock - 1) / kBlock);
     a.hpart = hpart;
     a.mpart = mpart;
     a.nest = nest;
@@ -414,7 +412,8 @@ struct Engine {
     a.r1 = R1, a.r2 = R2, a.cc = CC;
     a.work = P.work;
     a.arcs[0] = arcs[0], a.arcs[1] = arcs[1];
-    a.status[0] = status[0], a.status[1] = status[1];
+    a.csum = csum;
+    a.nchunk = (uint32_t)chunks;
     a.dir = dir;
     a.qown = P.qown;
     a.qkey = P.qkey;
@@ -683,8 +682,11 @@ int tc_sync(tc_state* s) {
 }
 
 static const char* const kKernelNames[kNumKernels] = {
-    "k_hist", "k_fold", "k_step1", "k_pass<0>", "k_pass<1>", "k_pass<2>",
-    "k_pass<3>", "k_dir", "k_est", "k_post", "k_probe"};
+    "k_hist", "k_fold_step1", "k_scat<0>",
+    "k_cnt<1>", "k_csum<1>", "k_scat<1>",
+    "k_cnt<2>", "k_csum<2>", "k_scat<2>",
+    "k_cnt<3>", "k_csum<3>", "k_scat<3>",
+    "k_dir", "k_est", "k_post", "k_probe"};
 
 static int set_timing(Engine& e, uint32_t mask) {
   int rc = e.collect_times();

@@ -21,13 +21,11 @@ constexpr int kItems = 16;               // arcs per thread per tile
 constexpr int kTile = kBlock * kItems;   // 4096 arcs per tile
 constexpr int kDigits = 256;
 constexpr int kPasses = 4;
-constexpr int kNumKernels = 11;  // launches per step (k_hist .. k_probe)
-constexpr uint32_t kFoldRows = 32;  // k_hist partials summed per k_fold block
-constexpr int kHistTiles = 1;   // tiles per k_hist block
-#ifndef TC_LOOKBACK
-#define TC_LOOKBACK 16
-#endif
-constexpr int kLookback = TC_LOOKBACK;  // predecessor statuses read per look-back round
+constexpr int kNumKernels = 16;  // launches per step (k_hist .. k_probe)
+constexpr int kHistTiles = 1;   // tiles per k_hist block (one: its counts are
+                                // the per-tile counts of the first radix pass)
+constexpr uint32_t kChunk = 32;  // tiles per chunk of the radix scans (and
+                                 // k_hist rows summed per k_fold block)
 
 // j1[] word: kNone, or the replacement position with kSideV set when the
 // smaller endpoint u of W[j1] is its second vertex
@@ -72,7 +70,8 @@ struct SegDesc {
   uint32_t ntiles;        // ceil(2w / kTile)
   uint32_t hblk_off;      // first k_hist block of the segment
   uint32_t nhblk;         // ceil(ntiles / kHistTiles)
-  uint32_t fold_off;      // first k_fold block of the segment
+  uint32_t chunk_off;     // first global radix chunk of the segment
+  uint32_t nchunks;       // ceil(ntiles / kChunk)
   uint32_t dir_log2;      // log2 of the directory region (slots)
   uint32_t qt_log2;       // log2 of the query-table region (slots)
   uint32_t need_off;      // first byte of the "position needed" bytes (w bytes)
@@ -81,7 +80,6 @@ struct SegDesc {
 // per-segment values produced during a step (device)
 struct SegWork {
   uint32_t hist[kPasses][kDigits];  // digit histograms of the 2w arcs
-  uint32_t tile_ctr[kPasses];       // next tile of each radix pass
   uint32_t maxid;                   // largest vertex id in the chunk
   uint32_t final_buf;               // arc buffer holding the sorted arcs
   uint32_t dense;                   // directory indexed by vertex id
@@ -110,7 +108,7 @@ struct StepArgs {
   uint32_t nseg;
   uint32_t ntiles;        // total tiles over segments
   uint32_t nhblk;         // total k_hist blocks over segments
-  uint32_t nfold;         // total k_fold blocks over segments
+  uint32_t nstep1;        // k_step1 blocks (run in the k_fold launch)
   uint32_t* hpart;        // per k_hist block: kPasses x kDigits digit counts
   uint32_t* mpart;        // per k_hist block: largest vertex id
   uint64_t nest;          // total estimator threads over segments
@@ -123,7 +121,8 @@ struct StepArgs {
   // scratch
   SegWork* work;          // [nseg]
   uint64_t* arcs[2];      // ping-pong arc buffers
-  uint32_t* status[2];    // look-back status, [ntiles][kDigits] each
+  uint32_t* csum;         // per radix chunk: digit sums [chunk][pass][digit]
+  uint32_t nchunk;        // total radix chunks over segments
   DirSlot* dir;
   uint32_t* qown;         // query table: owning estimator per slot
   uint64_t* qkey;         // query table: closing edge per slot

@@ -1,15 +1,18 @@
 // Device kernels of the bulk estimator update (Tangwongsan, Pavan,
 // Tirthapura, Sec. 4: bulkUpdateAll) for gfx950.
 //
-// One step = k_hist -> k_fold -> k_step1 -> k_pass<0..3> -> k_dir -> k_est
-// -> k_post -> k_probe.
+// One step = k_hist -> k_fold_step1 -> k_scat<0> -> 3 x (k_cnt -> k_csum ->
+// k_scat) -> k_dir -> k_est -> k_post -> k_probe.
 //
 //  k_hist   per-tile digit counts of the 2w arcs (+ max id, self-loop check)
-//  k_fold   per-segment digit histograms from the per-tile counts
-//  k_step1  Step 1: which estimators take a new f1, from where; writes f1
-//  k_pass   stable LSD radix pass over 8 bits of the vertex id (onesweep:
-//           wave64 ballot ranking, decoupled look-back, LDS-staged coalesced
-//           scatter).  Arcs are (vertex << 32 | 2 pos + side); stability keeps every
+//  k_fold_step1
+//           per-segment digit histograms and chunk sums from the per-tile
+//           counts; Step 1 (which estimators take a new f1, from where)
+//  k_cnt, k_csum, k_scat
+//           stable LSD radix pass over 8 bits of the vertex id
+//           (reduce-then-scan: tile counts, chunk sums, and a scatter that
+//           adds up its own offsets, ranks with wave64 ballots and writes
+//           through LDS, coalesced).  Arcs are (vertex << 32 | 2 pos + side); stability keeps every
 //           vertex's arcs in arrival order, which is the rankAll grouping
 //           of the Lemma on rankAll read in increasing pos (rank = arcs
 //           after it in the segment).  Digits constant over a chunk are
@@ -24,6 +27,8 @@
 #include "tc_internal.h"
 
 namespace tc {
+
+static_assert(kHistTiles == 1, "k_hist rows double as per-tile radix counts");
 
 // ---------------------------------------------------------------------------
 // small device helpers
@@ -73,12 +78,6 @@ __device__ __forceinline__ uint64_t closing(uint64_t f1, uint64_t f2) {
   return kEmpty;
 }
 
-__device__ __forceinline__ uint32_t ld_relaxed(uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // segment of a global tile: the last segment whose tile_off <= gtile
 __device__ __forceinline__ uint32_t seg_of_tile(const StepArgs& a,
@@ -100,18 +99,6 @@ __device__ __forceinline__ uint32_t seg_of_hblk(const StepArgs& a,
   while (lo < hi) {
     const uint32_t mid = (lo + hi + 1) >> 1;
     if (a.segs[mid].hblk_off <= b) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-// segment of a k_fold block
-__device__ __forceinline__ uint32_t seg_of_fold(const StepArgs& a,
-                                                uint32_t b) {
-  if (a.nseg == 1) return 0;
-  uint32_t lo = 0, hi = a.nseg - 1;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1) >> 1;
-    if (a.segs[mid].fold_off <= b) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
@@ -277,21 +264,36 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// k_fold: per segment, sum the k_hist partials into the digit histograms
-// (kFoldRows partials per block) and take the largest vertex id
+// k_fold (in the k_step1 launch): per radix chunk, the digit sums of its
+// tiles for every pass (the chunk sums of the first radix pass), added into
+// the segment's digit histograms; and the largest vertex id
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_fold(StepArgs a) {
+__device__ __forceinline__ uint32_t seg_of_chunk(const StepArgs& a, uint32_t c) {
+  if (a.nseg == 1) return 0;
+  uint32_t lo = 0, hi = a.nseg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (a.segs[mid].chunk_off <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t* csum_row(const StepArgs& a, uint32_t c, int P) {
+  return a.csum + ((size_t)c * kPasses + P) * kDigits;
+}
+
+__device__ void fold_chunk(const StepArgs& a, uint32_t c) {
   __shared__ uint32_t s_seg, s_max;
   const int tid = threadIdx.x;
   if (tid == 0) {
-    s_seg = seg_of_fold(a, blockIdx.x);
+    s_seg = seg_of_chunk(a, c);
     s_max = 0;
   }
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
-  const uint32_t r0 = S.hblk_off + (blockIdx.x - S.fold_off) * kFoldRows;
-  const uint32_t r1 = min(r0 + kFoldRows, S.hblk_off + S.nhblk);
+  const uint32_t r0 = S.hblk_off + (c - S.chunk_off) * kChunk;
+  const uint32_t r1 = min(r0 + kChunk, S.hblk_off + S.nhblk);
   uint32_t acc[kPasses] = {};
 #pragma unroll 4
   for (uint32_t rr = r0; rr < r1; ++rr) {
@@ -303,59 +305,133 @@ __global__ __launch_bounds__(kBlock) void k_fold(StepArgs a) {
   __syncthreads();
   SegWork* wk = a.work + sidx;
 #pragma unroll
-  for (int d = 0; d < kPasses; ++d)
+  for (int d = 0; d < kPasses; ++d) {
+    csum_row(a, c, d)[tid] = acc[d];
     if (acc[d]) atomicAdd(&wk->hist[d][tid], acc[d]);
+  }
   if (tid == 0) atomicMax(&wk->maxid, s_max);
 }
 
 // ---------------------------------------------------------------------------
-// k_pass<P>: one stable counting pass on digit P of the vertex id
+// Radix passes.  Pass P orders the arcs stably by bits 8P..8P+7 of the
+// vertex id (LSD), by reduce-then-scan: k_cnt<P> counts the digits of every
+// tile, k_csum<P> sums the counts of every chunk of kChunk tiles, k_cpre<P>
+// turns those sums into exclusive prefixes per segment, and k_scat<P>
+// derives its tile's global offsets from them and moves its arcs.  No block
+// waits for another.  A digit that is constant over a chunk (every arc in
+// one bin) makes its pass a no-op, skipped on the device; the first pass
+// that is not skipped takes its counts from k_hist.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kFlagAgg = 1u << 30;
-constexpr uint32_t kFlagInc = 2u << 30;
-constexpr uint32_t kValMask = (1u << 30) - 1;
+
+// which passes up to P are skipped for a segment (one thread per digit
+// reads the histograms); returns the number of passes before P that run
+template <int P>
+__device__ __forceinline__ int pass_plan(const SegWork* wk, uint32_t n,
+                                         int* s_triv) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int d = 0; d <= P; ++d)
+    if (wk->hist[d][tid] == n) s_triv[d] = 1;
+  __syncthreads();
+  int k = 0;
+#pragma unroll
+  for (int d = 0; d < P; ++d) k += s_triv[d] ? 0 : 1;
+  return (int)uniform((uint32_t)k);
+}
+
+// row of tile t's digit counts (pass P) in the partial-count array
+__device__ __forceinline__ uint32_t* cnt_row(const StepArgs& a, uint32_t t, int P) {
+  return a.hpart + (size_t)t * (kPasses * kDigits) + (size_t)P * kDigits;
+}
 
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
+__global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
+  __shared__ uint32_t s_h[kDigits];
+  __shared__ uint32_t s_seg;
+  __shared__ int s_triv[kPasses];
+  const int tid = threadIdx.x;
+  if (tid == 0) s_seg = seg_of_tile(a, blockIdx.x);
+  if (tid < kPasses) s_triv[tid] = 0;
+  s_h[tid] = 0;
+  __syncthreads();
+  const uint32_t sidx = uniform(s_seg);
+  const SegDesc S = seg_desc(a, sidx);
+  const uint32_t n = 2u * S.w;
+  const int k = pass_plan<P>(a.work + sidx, n, s_triv);
+  // skipped pass, or the first pass run (k_hist counted that order)
+  if (uniform((uint32_t)s_triv[P]) || k == 0) return;
+  const uint32_t base = (blockIdx.x - S.tile_off) * kTile;
+  const uint32_t nv = min((uint32_t)kTile, n - base);
+  // high words (vertex ids) of the pass input, read in order
+  const uint32_t* hi = reinterpret_cast<const uint32_t*>(a.arcs[(k + 1) & 1] + S.arc_off + base) + 1;
+  uint32_t v[kItems];
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) v[i] = hi[2u * min((uint32_t)(i * kBlock + tid), nv - 1)];
+  // lanes with equal digits add once (few distinct digits would otherwise
+  // serialize the LDS atomics)
+  const int lane = tid & 63;
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const bool valid = (uint32_t)(i * kBlock + tid) < nv;
+    const uint32_t dg = (v[i] >> (8 * P)) & 255u;
+    const uint64_t vm = __ballot(valid);
+    uint32_t lo = (uint32_t)vm, hi2 = (uint32_t)(vm >> 32);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint32_t t = (uint32_t)((int32_t)(dg << (31 - b)) >> 31);
+      const uint64_t bb = __ballot(t != 0u);
+      lo = __builtin_amdgcn_bitop3_b32(lo, t, (uint32_t)bb, 0x90);
+      hi2 = __builtin_amdgcn_bitop3_b32(hi2, t, (uint32_t)(bb >> 32), 0x90);
+    }
+    const uint64_t mm = ((uint64_t)hi2 << 32) | lo;
+    if (valid && __popcll(mm & ((1ull << lane) - 1ull)) == 0)
+      atomicAdd(&s_h[dg], (uint32_t)__popcll(mm));
+  }
+  __syncthreads();
+  cnt_row(a, blockIdx.x, P)[tid] = s_h[tid];
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_csum(StepArgs a) {
+  __shared__ uint32_t s_seg;
+  __shared__ int s_triv[kPasses];
+  const int tid = threadIdx.x;
+  if (tid == 0) s_seg = seg_of_chunk(a, blockIdx.x);
+  if (tid < kPasses) s_triv[tid] = 0;
+  __syncthreads();
+  const uint32_t sidx = uniform(s_seg);
+  const SegDesc S = seg_desc(a, sidx);
+  const int k = pass_plan<P>(a.work + sidx, 2u * S.w, s_triv);
+  // skipped pass, or the first pass run (k_fold summed that order)
+  if (uniform((uint32_t)s_triv[P]) || k == 0) return;
+  const uint32_t t0 = S.tile_off + (blockIdx.x - S.chunk_off) * kChunk;
+  const uint32_t t1 = min(t0 + kChunk, S.tile_off + S.ntiles);
+  uint32_t acc = 0;
+#pragma unroll 8
+  for (uint32_t t = t0; t < t1; ++t) acc += cnt_row(a, t, P)[tid];
+  csum_row(a, blockIdx.x, P)[tid] = acc;
+}
+
+template <int P>
+__device__ __forceinline__ void scat_body(const StepArgs& a) {
   __shared__ uint64_t s_el[kTile];
   __shared__ uint32_t s_wh[kWaves][kDigits];
   __shared__ uint32_t s_loc[kDigits];
   __shared__ uint32_t s_dst[kDigits];
   __shared__ uint32_t s_tmp[kWaves];
-  __shared__ uint32_t s_tile, s_seg;
+  __shared__ uint32_t s_seg;
   __shared__ int s_triv[kPasses];
-  __shared__ int s_stall;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // blocks [tile_off, tile_off + ntiles) serve one segment; within it the
-  // tiles are handed out in arrival order, so every tile's predecessors
-  // belong to blocks that are already running (look-back cannot deadlock)
-  if (tid == 0) {
-    s_seg = seg_of_tile(a, blockIdx.x);
-    s_stall = 0;
-  }
+  if (tid == 0) s_seg = seg_of_tile(a, blockIdx.x);
   if (tid < kPasses) s_triv[tid] = 0;
-  // the other look-back region is used by the next pass: clear one tile
-  a.status[(P + 1) & 1][(size_t)blockIdx.x * kDigits + tid] = 0;
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
   SegWork* wk = a.work + sidx;
   const uint32_t n = 2u * S.w;
-
-  // digits that are constant over the chunk need no pass
-  uint32_t hist_p = 0;
-#pragma unroll
-  for (int d = 0; d <= P; ++d) {
-    const uint32_t hv = wk->hist[d][tid];
-    if (hv == n) s_triv[d] = 1;
-    if (d == P) hist_p = hv;
-  }
-  __syncthreads();
-  int kk = 0;
-#pragma unroll
-  for (int d = 0; d < P; ++d) kk += s_triv[d] ? 0 : 1;
-  const int k = (int)uniform((uint32_t)kk);  // non-trivial passes before this one
+  const uint32_t hist_p = wk->hist[P][tid];
+  const int k = pass_plan<P>(wk, n, s_triv);
   if (P == kPasses - 1 && blockIdx.x == S.tile_off && tid == 0) {
     const int K = k + (s_triv[P] ? 0 : 1);
     wk->final_buf = (uint32_t)((K + 1) & 1);  // (K - 1) & 1, K >= 1
@@ -363,14 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
     wk->dense = span <= (1ull << S.dir_log2) ? 1u : 0u;
   }
   if (uniform((uint32_t)s_triv[P])) return;
-  if (tid == 0) s_tile = atomicAdd(&wk->tile_ctr[P], 1u);
-  __syncthreads();
-  const uint32_t ltile = uniform(s_tile);
-  if (ltile >= S.ntiles) {  // counters not reset: refuse to touch memory
-    if (tid == 0) atomicOr(a.err, kErrStall);
-    return;
-  }
-
+  const uint32_t ltile = blockIdx.x - S.tile_off;
   const uint64_t* src = a.arcs[(k + 1) & 1] + S.arc_off;  // (k-1)&1
   uint64_t* dst = a.arcs[k & 1] + S.arc_off;
   const uint32_t base = ltile * kTile;
@@ -387,17 +456,52 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
     // takes some f1 from that position (read in order, so coalesced)
     const uint32_t* E = S.edges;
     const uint8_t* need = a.need + S.need_off;
+    uint32_t ev[kItems], nb[kItems];
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
       const uint32_t gi = min(base + wave * 64 * kItems + i * 64 + lane, n - 1);
-      const uint32_t flag = need[gi >> 1] ? kNeedFlag : 0u;
-      el[i] = ((uint64_t)E[gi] << 32) | gi | flag;
+      ev[i] = E[gi];
+      nb[i] = need[gi >> 1];
     }
+    // (the arc id is recomputed, not kept; past the ragged end it is
+    // never used)
+#pragma unroll
+    for (int i = 0; i < kItems; ++i)
+      el[i] = ((uint64_t)ev[i] << 32) | (base + wave * 64 * kItems + i * 64 + lane) |
+              (nb[i] ? kNeedFlag : 0u);
   } else {
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
       const uint32_t gi = min(base + wave * 64 * kItems + i * 64 + lane, n - 1);
       el[i] = src[gi];
+    }
+  }
+  // this tile's first arc of digit tid goes to: the digit's bin start +
+  // the arcs of that digit in the segment's earlier chunks + those in this
+  // chunk's earlier tiles (the loads overlap the ranking below)
+  const uint32_t c = ltile / kChunk;
+  uint32_t off = 0;
+  {
+    // rows to add: c chunk sums, then ltile % kChunk tile counts, each
+    // kPasses * kDigits words apart; read in batches of independent loads
+    constexpr uint32_t kRow = kPasses * kDigits;
+    const uint32_t* crow = a.csum + ((size_t)S.chunk_off * kPasses + P) * kDigits + tid;
+    const uint32_t* trow =
+        a.hpart + ((size_t)(S.tile_off + c * kChunk) * kPasses + P) * kDigits + tid;
+    const uint32_t nt = ltile % kChunk;
+    for (uint32_t r0 = 0; r0 < c; r0 += 16) {
+      uint32_t v[16];
+#pragma unroll
+      for (uint32_t i = 0; i < 16; ++i) v[i] = r0 + i < c ? crow[(size_t)(r0 + i) * kRow] : 0u;
+#pragma unroll
+      for (uint32_t i = 0; i < 16; ++i) off += v[i];
+    }
+    for (uint32_t r0 = 0; r0 < nt; r0 += 16) {
+      uint32_t v[16];
+#pragma unroll
+      for (uint32_t i = 0; i < 16; ++i) v[i] = r0 + i < nt ? trow[(size_t)(r0 + i) * kRow] : 0u;
+#pragma unroll
+      for (uint32_t i = 0; i < 16; ++i) off += v[i];
     }
   }
   s_wh[wave][lane] = 0;
@@ -431,9 +535,9 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
     }
     const uint64_t mm = ((uint64_t)hi << 32) | lo;
     const uint32_t below = __popcll(mm & lt_mask);
-    uint32_t base = 0;
-    if (valid && below == 0) base = atomicAdd(&s_wh[wave][dg], (uint32_t)__popcll(mm));
-    rk[i] = base;
+    uint32_t bse = 0;
+    if (valid && below == 0) bse = atomicAdd(&s_wh[wave][dg], (uint32_t)__popcll(mm));
+    rk[i] = bse;
     lb[i] = (((uint32_t)__ffsll((long long)mm) - 1u) & 63u) | (below << 8);
   }
 #pragma unroll
@@ -445,67 +549,15 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
   uint32_t cnt = 0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) {
-    const uint32_t c = s_wh[w][tid];
+    const uint32_t cw = s_wh[w][tid];
     s_wh[w][tid] = cnt;
-    cnt += c;
+    cnt += cw;
   }
-  // publish this tile's counts first: successors can fold them meanwhile
-  uint32_t* st = a.status[P & 1] + (size_t)S.tile_off * kDigits;
-  st_relaxed(&st[(size_t)ltile * kDigits + tid],
-             (ltile == 0 ? kFlagInc : kFlagAgg) | cnt);
   uint32_t tot;
   s_loc[tid] = block_excl_scan(cnt, s_tmp, &tot);
   const uint32_t bin = block_excl_scan(hist_p, s_tmp, &tot);
-
-  // decoupled look-back over earlier tiles of this segment, per digit
-  uint32_t excl = 0;
-  if (ltile != 0) {
-    // read kLookback predecessors at once (independent loads), then fold
-    // the published ones nearest-first until an inclusive value
-    uint32_t j = ltile;  // tiles below j are still to be folded
-    uint32_t polls = 0;
-    bool done = false;
-    while (!done) {
-      // branch-free: indexes below tile 0 read tile 0 and count as an
-      // inclusive zero, so every load of the window is in flight at once
-      uint32_t v[kLookback];
-#pragma unroll
-      for (int t = 0; t < kLookback; ++t) {
-        const uint32_t jt = j > (uint32_t)t ? j - 1 - t : 0u;
-        v[t] = ld_relaxed(&st[(size_t)jt * kDigits + tid]);
-      }
-#pragma unroll
-      for (int t = 0; t < kLookback; ++t)
-        if (j <= (uint32_t)t) v[t] = kFlagInc | 0u;
-      uint32_t used = 0;
-      bool wait = false;
-#pragma unroll
-      for (int t = 0; t < kLookback; ++t) {
-        if (done || wait) continue;
-        const uint32_t f = v[t] & ~kValMask;
-        if (f == 0) {
-          wait = true;
-          continue;
-        }
-        excl += v[t] & kValMask;
-        ++used;
-        if (f == kFlagInc) done = true;
-      }
-      j -= min(used, j);
-      if (!done && used == 0) {
-        if (++polls > kSpinLimit) {  // a predecessor never published
-          s_stall = 1;
-          atomicOr(a.err, kErrStall);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    st_relaxed(&st[(size_t)ltile * kDigits + tid], kFlagInc | (excl + cnt));
-  }
-  s_dst[tid] = bin + excl - s_loc[tid];
+  s_dst[tid] = bin + off - s_loc[tid];
   __syncthreads();
-  if (s_stall) return;
 
   // scatter into LDS in digit order, then write runs out coalesced
 #pragma unroll
@@ -524,12 +576,25 @@ __global__ __launch_bounds__(kBlock) void k_pass(StepArgs a) {
   }
 }
 
+// The body needs about 140 registers; passes whose build fits in 128
+// without spilling run with four waves per SIMD (one more block per CU),
+// the others (the first pass reads W and the need bytes; the last one sets
+// up the directory mode) with three.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_scat(StepArgs a) {
+  scat_body<P>(a);
+}
+template <int P>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_scat4(StepArgs a) {
+  scat_body<P>(a);
+}
+
 // ---------------------------------------------------------------------------
 // k_step1: Step 1 (Sec. 4.2) draws for every estimator; the replacement
 // index goes to j1[] and its batch position is marked as needed
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_step1(StepArgs a) {
-  const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ void step1_block(const StepArgs& a, uint32_t blk) {
+  const uint64_t gid = (uint64_t)blk * kBlock + threadIdx.x;
   if (gid >= a.nest) return;
   const uint32_t sidx = seg_of_est(a, gid);
   const SegDesc S = seg_desc(a, sidx);
@@ -546,6 +611,13 @@ __global__ __launch_bounds__(kBlock) void k_step1(StepArgs a) {
     j1 = p | (ed.x < ed.y ? 0u : kSideV);
   }
   a.j1[S.est_off + i] = j1;
+}
+
+// one launch for two independent jobs: blocks [0, nchunk) fold the k_hist
+// counts, the rest run Step 1
+__global__ __launch_bounds__(kBlock) void k_fold_step1(StepArgs a) {
+  if (blockIdx.x < a.nchunk) fold_chunk(a, blockIdx.x);
+  else step1_block(a, blockIdx.x - a.nchunk);
 }
 
 // ---------------------------------------------------------------------------
@@ -799,21 +871,35 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
     const uint64_t* key = a.qkey + S.qt_off;
     const uint32_t* lim = a.qlim + S.qt_off;
     const uint32_t* own = a.qown + S.qt_off;
+    constexpr uint64_t k01 = 0x0101010101010101ull, k80 = 0x8080808080808080ull;
     for (int k = 0; k < kProbeEdges; ++k) {
       const uint32_t j = ebase + k * kBlock + tid;
       if (j >= S.w) break;
       const uint2 ed = W[j];
       const uint64_t q = canon(ed.x, ed.y);
       const uint64_t hq = mix64(q);
-      const uint8_t f = q_fp(hq);
+      const uint64_t fx = k01 * q_fp(hq);
       // the fingerprints (one byte per slot, a few MB, stay in L2) rule out
-      // nearly every edge; a matching one is checked against the key
-      uint32_t s = q_home(hq, mask);
-      for (uint32_t probe = 0; probe <= mask; ++probe) {
-        const uint8_t g = fp[s];
-        if (g == 0) break;
-        if (g == f && key[s] == q && j >= lim[s]) atomicOr(&a.cc[own[s]], kClosed);
-        s = (s + 1) & mask;
+      // nearly every edge; they are read eight at a time (aligned words):
+      // the scan ends at the first free slot (zero byte), and a byte equal
+      // to the edge's fingerprint before it is checked against the key
+      uint32_t sl = q_home(hq, mask);
+      for (uint32_t probe = 0; probe <= mask + 8; probe += 8) {
+        const uint32_t b8 = sl & ~7u;
+        const uint64_t wd = *reinterpret_cast<const uint64_t*>(fp + b8);
+        const uint64_t ign = (k01 << (8u * (sl & 7u))) ^ k01;  // 0x01 below sl
+        const uint64_t v = wd | ign;
+        const uint64_t z = (v - k01) & ~v & k80;  // lowest bit: first free slot
+        const uint64_t x = (wd ^ fx) | ign;
+        uint64_t mt = (x - k01) & ~x & k80;       // matches (extra bits are
+        if (z) mt &= (z & (~z + 1)) - 1;          // only ever rechecked)
+        while (mt) {
+          const uint32_t at = b8 + ((uint32_t)__ffsll((long long)mt) - 1u) / 8u;
+          if (key[at] == q && j >= lim[at]) atomicOr(&a.cc[own[at]], kClosed);
+          mt &= mt - 1;
+        }
+        if (z) break;
+        sl = (b8 + 8) & mask;
       }
     }
   }
@@ -878,18 +964,26 @@ hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st,
   };
   if (phase == 0) {
     run(0, [&] { hipLaunchKernelGGL(k_hist, dim3(a.nhblk), blk, 0, st, a); });
-    run(1, [&] { hipLaunchKernelGGL(k_fold, dim3(a.nfold), blk, 0, st, a); });
-    run(2, [&] { hipLaunchKernelGGL(k_step1, ests, blk, 0, st, a); });
-    run(3, [&] { hipLaunchKernelGGL(k_pass<0>, tiles, blk, 0, st, a); });
-    run(4, [&] { hipLaunchKernelGGL(k_pass<1>, tiles, blk, 0, st, a); });
-    run(5, [&] { hipLaunchKernelGGL(k_pass<2>, tiles, blk, 0, st, a); });
-    run(6, [&] { hipLaunchKernelGGL(k_pass<3>, tiles, blk, 0, st, a); });
-    run(7, [&] { hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a); });
+    run(1, [&] {
+      hipLaunchKernelGGL(k_fold_step1, dim3(a.nchunk + a.nstep1), blk, 0, st, a);
+    });
+    const dim3 chunks(a.nchunk);
+    run(2, [&] { hipLaunchKernelGGL(k_scat<0>, tiles, blk, 0, st, a); });
+    int k = 3;
+    auto pass = [&](auto cntk, auto csumk, auto scatk) {
+      run(k++, [&] { hipLaunchKernelGGL(cntk, tiles, blk, 0, st, a); });
+      run(k++, [&] { hipLaunchKernelGGL(csumk, chunks, blk, 0, st, a); });
+      run(k++, [&] { hipLaunchKernelGGL(scatk, tiles, blk, 0, st, a); });
+    };
+    pass(k_cnt<1>, k_csum<1>, k_scat4<1>);
+    pass(k_cnt<2>, k_csum<2>, k_scat4<2>);
+    pass(k_cnt<3>, k_csum<3>, k_scat<3>);
+    run(k++, [&] { hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a); });
   } else if (phase == 1) {
-    run(8, [&] { hipLaunchKernelGGL(k_est, ests, blk, 0, st, a); });
+    run(kNumKernels - 3, [&] { hipLaunchKernelGGL(k_est, ests, blk, 0, st, a); });
   } else {
-    run(9, [&] { hipLaunchKernelGGL(k_post, ests, blk, 0, st, a); });
-    run(10, [&] { hipLaunchKernelGGL(k_probe, tiles, blk, 0, st, a); });
+    run(kNumKernels - 2, [&] { hipLaunchKernelGGL(k_post, ests, blk, 0, st, a); });
+    run(kNumKernels - 1, [&] { hipLaunchKernelGGL(k_probe, tiles, blk, 0, st, a); });
   }
   return hipGetLastError();
 }
