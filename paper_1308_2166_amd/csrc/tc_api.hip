@@ -54,9 +54,10 @@ uint32_t log2_ceil(uint64_t x) {
 uint32_t dir_log2_for(uint32_t w) {
   return std::max<uint32_t>(10, log2_ceil(4ull * w));
 }
-// query-table slots for a bank of r estimators: at most r queries
+// query-table slots for a bank of r estimators: at most r queries, so the
+// load stays at or below 1/4
 uint32_t qt_log2_for(uint32_t r) {
-  return std::max<uint32_t>(10, log2_ceil(2ull * r));
+  return std::max<uint32_t>(10, log2_ceil(4ull * r));
 }
 
 template <class T>
@@ -77,9 +78,7 @@ void dfree(T*& p) {
 // phases touch exists twice and step s uses copy s & 1.
 struct ParityScratch {
   SegWork* work = nullptr;    // per-segment histograms, counters, modes
-  uint32_t* qown = nullptr;   // Step-3 query tables (structure of arrays)
-  uint64_t* qkey = nullptr;
-  uint32_t* qlim = nullptr;
+  QRec* qt = nullptr;         // Step-3 query tables
   uint8_t* qfp = nullptr;
   SegDesc* segs = nullptr;    // device copy of the step's descriptors
 };
@@ -199,7 +198,7 @@ struct Engine {
     dfree(arcs[0]), dfree(arcs[1]), dfree(csum);
     dfree(dir), dfree(need), dfree(inv), dfree(hpart), dfree(mpart);
     for (ParityScratch& p : par) {
-      dfree(p.work), dfree(p.qown), dfree(p.qkey), dfree(p.qlim), dfree(p.qfp);
+      dfree(p.work), dfree(p.qt), dfree(p.qfp);
       dfree(p.segs);
     }
     cap_arcs = cap_tiles = cap_dir = cap_qt = cap_need = 0;
@@ -271,8 +270,8 @@ struct Engine {
                dalloc(&hpart, cap_tiles * kPasses * kDigits) ||
                dalloc(&mpart, cap_tiles);
     for (ParityScratch& p : par)
-      bad = bad || dalloc(&p.work, cap_segs) || dalloc(&p.qown, cap_qt) ||
-            dalloc(&p.qkey, cap_qt) || dalloc(&p.qlim, cap_qt) || dalloc(&p.qfp, cap_qt) ||
+      bad = bad || dalloc(&p.work, cap_segs) || dalloc(&p.qt, cap_qt) ||
+            dalloc(&p.qfp, cap_qt) ||
             dalloc(&p.segs, cap_segs);
     if (bad) {
       free_scratch();
@@ -283,7 +282,7 @@ struct Engine {
           hipMemsetAsync(need, 0, cap_need, st);
     for (ParityScratch& p : par)
       bad = bad || hipMemsetAsync(p.work, 0, sizeof(SegWork) * cap_segs, st) ||
-            hipMemsetAsync(p.qown, 0xFF, 4 * cap_qt, st) ||
+            hipMemsetAsync(p.qt, 0xFF, sizeof(QRec) * cap_qt, st) ||
             hipMemsetAsync(p.qfp, 0, cap_qt, st);
     if (bad || hipStreamSynchronize(st))
       return fail(TC_EHIP, "clearing step scratch failed");
@@ -415,9 +414,7 @@ struct Engine {
     a.csum = csum;
     a.nchunk = (uint32_t)chunks;
     a.dir = dir;
-    a.qown = P.qown;
-    a.qkey = P.qkey;
-    a.qlim = P.qlim;
+    a.qt = P.qt;
     a.qfp = P.qfp;
     a.qt_slots = qt_n;
     a.j1 = J1;

@@ -95,12 +95,17 @@ struct DirSlot {
   uint32_t end;
 };
 
-// Step-3 query table (structure of arrays, one region per segment, linear
-// probing): slot s belongs to estimator qown[s] (kNone = free), which waits
-// for closing edge qkey[s] at a batch position >= qlim[s]; qfp[s] is a
-// nonzero 8-bit fingerprint of the key's hash (0 = free) and is what a
-// probe scans.  Every waiting estimator owns one slot (equal keys share a
-// probe cluster).  qown and qfp are reset at the start of every step.
+// Step-3 query table (one region per segment, linear probing): slot s is
+// the record qt[s] -- estimator `own` (kNone = free) waits for closing edge
+// `key` at a batch position >= `lim` -- plus qfp[s], a nonzero 8-bit
+// fingerprint of the key's hash (0 = free), which is what a probe scans.
+// Every waiting estimator owns one slot (equal keys share a probe cluster).
+// The records and fingerprints are reset at the start of every step.
+struct QRec {
+  uint64_t key;
+  uint32_t lim;
+  uint32_t own;
+};
 
 struct StepArgs {
   const SegDesc* segs;    // device copy of all segment descriptors
@@ -124,9 +129,7 @@ struct StepArgs {
   uint32_t* csum;         // per radix chunk: digit sums [chunk][pass][digit]
   uint32_t nchunk;        // total radix chunks over segments
   DirSlot* dir;
-  uint32_t* qown;         // query table: owning estimator per slot
-  uint64_t* qkey;         // query table: closing edge per slot
-  uint32_t* qlim;         // query table: first closing position per slot
+  QRec* qt;               // query table records
   uint8_t* qfp;           // query table: key fingerprint per slot
   uint64_t qt_slots;      // query-table slots over all segments
   uint32_t* j1;           // per estimator: Step-1 replacement (see kSideV)

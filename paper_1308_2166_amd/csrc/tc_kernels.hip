@@ -4,7 +4,8 @@
 // One step = k_hist -> k_fold_step1 -> k_scat<0> -> 3 x (k_cnt -> k_csum ->
 // k_scat) -> k_dir -> k_est -> k_post -> k_probe.
 //
-//  k_hist   per-tile digit counts of the 2w arcs (+ max id, self-loop check)
+//  k_hist   per-tile counts of digit 0 of the 2w arcs (+ max id, self-loop
+//           check)
 //  k_fold_step1
 //           per-segment digit histograms and chunk sums from the per-tile
 //           counts; Step 1 (which estimators take a new f1, from where)
@@ -166,7 +167,7 @@ __device__ __forceinline__ void hist_add(uint32_t* h, uint32_t dg, bool valid) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
-  __shared__ uint32_t h[kPasses][kDigits];
+  __shared__ uint32_t h[kDigits];
   __shared__ uint32_t s_max;
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
@@ -181,14 +182,13 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
     const uint32_t t = *a.tagp + 1u;
     *a.tagp = t ? t : 1u;
   }
-#pragma unroll
-  for (int d = 0; d < kPasses; ++d) h[d][tid] = 0;
+  h[tid] = 0;
   // empty the Step-3 query tables (first used by k_est of this step)
   {
     // (slot counts are multiples of 1024, so whole uint4s cover them)
-    uint4* o4 = reinterpret_cast<uint4*>(a.qown);
-    const uint4 none = make_uint4(kNone, kNone, kNone, kNone);
-    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.qt_slots / 4;
+    uint4* o4 = reinterpret_cast<uint4*>(a.qt);
+    const uint4 none = make_uint4(0, 0, 0, kNone);  // own = kNone
+    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.qt_slots;
          t += (uint64_t)a.nhblk * kBlock)
       o4[t] = none;
     uint4* f4 = reinterpret_cast<uint4*>(a.qfp);
@@ -244,29 +244,25 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
       loop |= x.z == x.w;
       vmax = max(vmax, max(x.z, x.w));
     }
-#pragma unroll
-    for (int d = 0; d < kPasses; ++d) {
-      hist_add(h[d], (x.x >> (8 * d)) & 255u, v01);
-      hist_add(h[d], (x.y >> (8 * d)) & 255u, v01);
-      hist_add(h[d], (x.z >> (8 * d)) & 255u, v23);
-      hist_add(h[d], (x.w >> (8 * d)) & 255u, v23);
-    }
+    // digit 0 only: the later passes count their own input order
+    hist_add(h, x.x & 255u, v01);
+    hist_add(h, x.y & 255u, v01);
+    hist_add(h, x.z & 255u, v23);
+    hist_add(h, x.w & 255u, v23);
   }
   if (loop) atomicOr(a.err, kErrSelfLoop);
   atomicMax(&s_max, vmax);
   __syncthreads();
-  // the block's counts go out with plain stores; k_fold sums them, so no
-  // global bin takes one atomic per block
-  uint32_t* hp = a.hpart + (size_t)hb * (kPasses * kDigits);
-#pragma unroll
-  for (int d = 0; d < kPasses; ++d) hp[d * kDigits + tid] = h[d][tid];
+  // the block's counts go out with plain stores; the fold sums them, so
+  // no global bin takes one atomic per block
+  a.hpart[(size_t)hb * (kPasses * kDigits) + tid] = h[tid];
   if (tid == 0) a.mpart[hb] = s_max;
 }
 
 // ---------------------------------------------------------------------------
-// k_fold (in the k_step1 launch): per radix chunk, the digit sums of its
-// tiles for every pass (the chunk sums of the first radix pass), added into
-// the segment's digit histograms; and the largest vertex id
+// k_fold (in the k_step1 launch): per radix chunk, the digit-0 sums of its
+// tiles (the chunk sums of the first radix pass), added into the segment's
+// digit-0 histogram; and the largest vertex id
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t seg_of_chunk(const StepArgs& a, uint32_t c) {
   if (a.nseg == 1) return 0;
@@ -294,49 +290,34 @@ __device__ void fold_chunk(const StepArgs& a, uint32_t c) {
   const SegDesc S = seg_desc(a, sidx);
   const uint32_t r0 = S.hblk_off + (c - S.chunk_off) * kChunk;
   const uint32_t r1 = min(r0 + kChunk, S.hblk_off + S.nhblk);
-  uint32_t acc[kPasses] = {};
-#pragma unroll 4
-  for (uint32_t rr = r0; rr < r1; ++rr) {
-    const uint32_t* row = a.hpart + (size_t)rr * (kPasses * kDigits);
-#pragma unroll
-    for (int d = 0; d < kPasses; ++d) acc[d] += row[d * kDigits + tid];
-  }
+  uint32_t acc = 0;
+#pragma unroll 8
+  for (uint32_t rr = r0; rr < r1; ++rr) acc += a.hpart[(size_t)rr * (kPasses * kDigits) + tid];
   if ((uint32_t)tid < r1 - r0) atomicMax(&s_max, a.mpart[r0 + tid]);
   __syncthreads();
   SegWork* wk = a.work + sidx;
-#pragma unroll
-  for (int d = 0; d < kPasses; ++d) {
-    csum_row(a, c, d)[tid] = acc[d];
-    if (acc[d]) atomicAdd(&wk->hist[d][tid], acc[d]);
-  }
+  csum_row(a, c, 0)[tid] = acc;
+  if (acc) atomicAdd(&wk->hist[0][tid], acc);
   if (tid == 0) atomicMax(&wk->maxid, s_max);
 }
 
 // ---------------------------------------------------------------------------
 // Radix passes.  Pass P orders the arcs stably by bits 8P..8P+7 of the
 // vertex id (LSD), by reduce-then-scan: k_cnt<P> counts the digits of every
-// tile, k_csum<P> sums the counts of every chunk of kChunk tiles, k_cpre<P>
-// turns those sums into exclusive prefixes per segment, and k_scat<P>
-// derives its tile's global offsets from them and moves its arcs.  No block
-// waits for another.  A digit that is constant over a chunk (every arc in
-// one bin) makes its pass a no-op, skipped on the device; the first pass
-// that is not skipped takes its counts from k_hist.
+// tile, k_csum<P> sums the counts of every chunk of kChunk tiles (and the
+// segment's digit histogram), and k_scat<P> adds up its tile's global
+// offsets from them and moves its arcs.  No block waits for another.
+// Passes above the largest vertex id's top digit are skipped on the device;
+// pass 0 takes its counts from k_hist and the fold.
 // ---------------------------------------------------------------------------
 
-// which passes up to P are skipped for a segment (one thread per digit
-// reads the histograms); returns the number of passes before P that run
-template <int P>
-__device__ __forceinline__ int pass_plan(const SegWork* wk, uint32_t n,
-                                         int* s_triv) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int d = 0; d <= P; ++d)
-    if (wk->hist[d][tid] == n) s_triv[d] = 1;
-  __syncthreads();
-  int k = 0;
-#pragma unroll
-  for (int d = 0; d < P; ++d) k += s_triv[d] ? 0 : 1;
-  return (int)uniform((uint32_t)k);
+// Pass P runs for a segment iff some vertex id has a nonzero digit at or
+// above P (max id >= 2^(8P)); otherwise digit P is zero for every arc and
+// the pass would leave the order unchanged.  Pass 0 always runs (an edge
+// has two distinct ids), so the passes that run are 0 .. K-1 and pass P
+// reads buffer (P+1)&1 (W for P = 0) and writes buffer P&1.
+__device__ __forceinline__ bool pass_runs(uint32_t maxid, int P) {
+  return P == 0 || (maxid >> (8 * P)) != 0u;
 }
 
 // row of tile t's digit counts (pass P) in the partial-count array
@@ -346,24 +327,21 @@ __device__ __forceinline__ uint32_t* cnt_row(const StepArgs& a, uint32_t t, int 
 
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
+  static_assert(P >= 1, "k_hist counts the first pass");
   __shared__ uint32_t s_h[kDigits];
   __shared__ uint32_t s_seg;
-  __shared__ int s_triv[kPasses];
   const int tid = threadIdx.x;
   if (tid == 0) s_seg = seg_of_tile(a, blockIdx.x);
-  if (tid < kPasses) s_triv[tid] = 0;
   s_h[tid] = 0;
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
   const uint32_t n = 2u * S.w;
-  const int k = pass_plan<P>(a.work + sidx, n, s_triv);
-  // skipped pass, or the first pass run (k_hist counted that order)
-  if (uniform((uint32_t)s_triv[P]) || k == 0) return;
+  if (!pass_runs(uniform(a.work[sidx].maxid), P)) return;
   const uint32_t base = (blockIdx.x - S.tile_off) * kTile;
   const uint32_t nv = min((uint32_t)kTile, n - base);
   // high words (vertex ids) of the pass input, read in order
-  const uint32_t* hi = reinterpret_cast<const uint32_t*>(a.arcs[(k + 1) & 1] + S.arc_off + base) + 1;
+  const uint32_t* hi = reinterpret_cast<const uint32_t*>(a.arcs[(P + 1) & 1] + S.arc_off + base) + 1;
   uint32_t v[kItems];
 #pragma unroll
   for (int i = 0; i < kItems; ++i) v[i] = hi[2u * min((uint32_t)(i * kBlock + tid), nv - 1)];
@@ -393,23 +371,23 @@ __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
 
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_csum(StepArgs a) {
+  static_assert(P >= 1, "the fold sums the first pass");
   __shared__ uint32_t s_seg;
-  __shared__ int s_triv[kPasses];
   const int tid = threadIdx.x;
   if (tid == 0) s_seg = seg_of_chunk(a, blockIdx.x);
-  if (tid < kPasses) s_triv[tid] = 0;
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
-  const int k = pass_plan<P>(a.work + sidx, 2u * S.w, s_triv);
-  // skipped pass, or the first pass run (k_fold summed that order)
-  if (uniform((uint32_t)s_triv[P]) || k == 0) return;
+  SegWork* wk = a.work + sidx;
+  if (!pass_runs(uniform(wk->maxid), P)) return;
   const uint32_t t0 = S.tile_off + (blockIdx.x - S.chunk_off) * kChunk;
   const uint32_t t1 = min(t0 + kChunk, S.tile_off + S.ntiles);
   uint32_t acc = 0;
 #pragma unroll 8
   for (uint32_t t = t0; t < t1; ++t) acc += cnt_row(a, t, P)[tid];
   csum_row(a, blockIdx.x, P)[tid] = acc;
+  // the segment's digit-P histogram (the bin starts of the pass)
+  if (acc) atomicAdd(&wk->hist[P][tid], acc);
 }
 
 template <int P>
@@ -420,28 +398,28 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
   __shared__ uint32_t s_dst[kDigits];
   __shared__ uint32_t s_tmp[kWaves];
   __shared__ uint32_t s_seg;
-  __shared__ int s_triv[kPasses];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) s_seg = seg_of_tile(a, blockIdx.x);
-  if (tid < kPasses) s_triv[tid] = 0;
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
   SegWork* wk = a.work + sidx;
   const uint32_t n = 2u * S.w;
-  const uint32_t hist_p = wk->hist[P][tid];
-  const int k = pass_plan<P>(wk, n, s_triv);
+  const uint32_t maxid = uniform(wk->maxid);
   if (P == kPasses - 1 && blockIdx.x == S.tile_off && tid == 0) {
-    const int K = k + (s_triv[P] ? 0 : 1);
+    int K = 0;  // passes run
+#pragma unroll
+    for (int d = 0; d < kPasses; ++d) K += pass_runs(maxid, d) ? 1 : 0;
     wk->final_buf = (uint32_t)((K + 1) & 1);  // (K - 1) & 1, K >= 1
-    const uint64_t span = (uint64_t)wk->maxid + 1;
+    const uint64_t span = (uint64_t)maxid + 1;
     wk->dense = span <= (1ull << S.dir_log2) ? 1u : 0u;
   }
-  if (uniform((uint32_t)s_triv[P])) return;
+  if (!pass_runs(maxid, P)) return;
+  const uint32_t hist_p = wk->hist[P][tid];
   const uint32_t ltile = blockIdx.x - S.tile_off;
-  const uint64_t* src = a.arcs[(k + 1) & 1] + S.arc_off;  // (k-1)&1
-  uint64_t* dst = a.arcs[k & 1] + S.arc_off;
+  const uint64_t* src = a.arcs[(P + 1) & 1] + S.arc_off;
+  uint64_t* dst = a.arcs[P & 1] + S.arc_off;
   const uint32_t base = ltile * kTile;
   const uint32_t nv = min((uint32_t)kTile, n - base);
 
@@ -451,7 +429,7 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
   // kItems loads are in flight together
   uint64_t el[kItems];
   uint32_t rk[kItems];
-  if (k == 0) {
+  if (P == 0) {
     // arcs straight from W: arc id = 2 pos + side, flagged when Step 1
     // takes some f1 from that position (read in order, so coalesced)
     const uint32_t* E = S.edges;
@@ -808,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   // stores one value lands whole); k_post checks which estimator won and
   // moves the others on, so the common case needs no atomic
   if (q != kEmpty)
-    a.qown[S.qt_off + q_home(mix64(q), (1u << S.qt_log2) - 1u)] = (uint32_t)e;
+    a.qt[S.qt_off + q_home(mix64(q), (1u << S.qt_log2) - 1u)].own = (uint32_t)e;
   a.qthr[e] = (p2 == kNone) ? 0u : p2 + 1;  // closes at a position >= this
   a.r2[e] = r2;
   a.cc[e] = (uint32_t)c | (closed ? kClosed : 0u);
@@ -832,20 +810,25 @@ __global__ __launch_bounds__(kBlock) void k_post(StepArgs a) {
   if (q == kEmpty) return;
   const uint32_t mask = (1u << S.qt_log2) - 1u;
   const uint64_t hq = mix64(q);
-  uint32_t* own = a.qown + S.qt_off;
+  QRec* qt = a.qt + S.qt_off;
   uint32_t s = q_home(hq, mask);
-  if (own[s] != (uint32_t)e) {
+  if (qt[s].own != (uint32_t)e) {
     uint32_t probe = 0;
     do {
       s = (s + 1) & mask;
-      if (++probe > mask) {  // cannot happen: at most half the slots are used
+      if (++probe > mask) {  // cannot happen: at most a quarter of the slots are used
         atomicOr(a.err, kErrProbe);
         return;
       }
-    } while (atomicCAS(&own[s], kNone, (uint32_t)e) != kNone);
+    } while (atomicCAS(&qt[s].own, kNone, (uint32_t)e) != kNone);
   }
-  a.qkey[S.qt_off + s] = q;
-  a.qlim[S.qt_off + s] = a.qthr[e];
+  // one 16-byte store (own is rewritten with its own value: no other
+  // thread touches an owned slot)
+  QRec rec;
+  rec.key = q;
+  rec.lim = a.qthr[e];
+  rec.own = (uint32_t)e;
+  qt[s] = rec;
   a.qfp[S.qt_off + s] = q_fp(hq);
 }
 
@@ -868,9 +851,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
     const uint2* W = reinterpret_cast<const uint2*>(S.edges);
     const uint32_t mask = (1u << S.qt_log2) - 1u;
     const uint8_t* fp = a.qfp + S.qt_off;
-    const uint64_t* key = a.qkey + S.qt_off;
-    const uint32_t* lim = a.qlim + S.qt_off;
-    const uint32_t* own = a.qown + S.qt_off;
+    const QRec* qt = a.qt + S.qt_off;
     constexpr uint64_t k01 = 0x0101010101010101ull, k80 = 0x8080808080808080ull;
     for (int k = 0; k < kProbeEdges; ++k) {
       const uint32_t j = ebase + k * kBlock + tid;
@@ -895,7 +876,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
         if (z) mt &= (z & (~z + 1)) - 1;          // only ever rechecked)
         while (mt) {
           const uint32_t at = b8 + ((uint32_t)__ffsll((long long)mt) - 1u) / 8u;
-          if (key[at] == q && j >= lim[at]) atomicOr(&a.cc[own[at]], kClosed);
+          const QRec rec = qt[at];
+          if (rec.key == q && j >= rec.lim) atomicOr(&a.cc[rec.own], kClosed);
           mt &= mt - 1;
         }
         if (z) break;
