@@ -113,7 +113,9 @@ def batched_comparison(tc, inputs, nstreams=256, ks=(4, 8, 16), replays=3):
             steps.append((ids, chunks))
         return steps
 
+    nv = max(st["n"] for st in streams)  # every stream's ids lie below this
     mb = tc.MultiBank(rs, seeds)
+    tc.tc_multi_set_vertex_bound(mb.h, nv)
 
     def run_batched(steps):
         tc.tc_multi_reset(mb.h, stream)
@@ -168,6 +170,7 @@ def batched_comparison(tc, inputs, nstreams=256, ks=(4, 8, 16), replays=3):
     banks = []
     for b in range(nstreams):
         bk = tc.Bank(rs[b], seeds[b])
+        tc.tc_set_vertex_bound(bk.h, streams[b]["n"])
         tc.tc_reserve(bk.h, (ms[b] + K - 1) // K)
         banks.append(bk)
 
@@ -307,6 +310,7 @@ def served_comparison(tc, inputs, nstreams=1024, ngraphs=64, r=1 << 16,
     log(f"[bench] serving: generating {ngraphs} graphs for {nstreams} streams")
     pool = inputs.many_streams(ngraphs, seed=505, device="cuda")
     graphs = [pool[s % ngraphs]["edges"] for s in range(nstreams)]
+    nv = max(p["n"] for p in pool)  # every stream's ids lie below this
     seeds = [(0x9E3779B97F4A7C15 * (s + 1)) & ((1 << 63) - 1) for s in range(nstreams)]
     chunks = serve.chunk_streams(graphs, seed=6)
     nchunks = sum(len(c) for c in chunks)
@@ -317,7 +321,8 @@ def served_comparison(tc, inputs, nstreams=1024, ngraphs=64, r=1 << 16,
     servers = {}
 
     def run(rate, nslots, seed):
-        srv = servers.get(nslots) or servers.setdefault(nslots, serve.Server(slots=nslots, r=r))
+        srv = servers.get(nslots) or servers.setdefault(
+            nslots, serve.Server(slots=nslots, r=r, vertex_bound=nv))
         lat, res, el, rw = srv.run(serve.poisson_arrivals(chunks, rate, seed), seeds)
         lat = np.array(lat) * 1e3
         return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
@@ -408,6 +413,7 @@ def main():
     log(f"[bench] generating {args.workload} on the GPU")
     G, r, w, seed = inputs.workload(args.workload, device="cuda")
     G = G.contiguous()
+    nv = inputs.vertex_count(args.workload)  # ids lie in [0, nv)
     m = G.shape[0]
     nb = (m + w - 1) // w
     batches = [G[j:j + w] for j in range(0, m, w)]
@@ -417,13 +423,17 @@ def main():
     # fresh banks: every timed step is batch (k mod nb) of a bank's stream
     nbanks = (steps + nb - 1) // nb
     log(f"[bench] m={m} r={r} w={w} batches/stream={nb} timed banks={nbanks}")
-    warm_bank = tc.Bank(r, seed)
-    tc.tc_reserve(warm_bank.h, w)
+    def new_bank():
+        b = tc.Bank(r, seed)
+        tc.tc_set_vertex_bound(b.h, nv)
+        tc.tc_reserve(b.h, w)
+        return b
+
+    warm_bank = new_bank()
     for k in range(warm):
         if k % nb == 0 and k:
             warm_bank.close()
-            warm_bank = tc.Bank(r, seed)
-            tc.tc_reserve(warm_bank.h, w)
+            warm_bank = new_bank()
         warm_bank.process(batches[k % nb], stream)
     warm_bank.sync()
     warm_bank.close()
@@ -432,8 +442,7 @@ def main():
         """timing: False, True (every kernel) or a list of kernel names."""
         out = []
         for _ in range(nbanks):
-            b = tc.Bank(r, seed)
-            tc.tc_reserve(b.h, w)
+            b = new_bank()
             if timing:
                 tc.tc_set_kernel_timing(b.h, timing)
             out.append(b)
@@ -537,7 +546,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
-                   "r": r, "w": w, "m_stream": m, "form": "plain"},
+                   "r": r, "w": w, "m_stream": m, "vertex_bound": nv, "form": "plain"},
         "edges_per_s": edges_done / dt,
         "ms_per_step_by_call_form": call_forms,
         "roofline": roofline,
@@ -561,7 +570,7 @@ def main():
             "sample": f"first {nbo} batch(es) of the same stream (r={r}, w={w}), "
                       f"paper-steps oracle variant, single thread, {odt:.1f} s"}
         # the same batches on the GPU must give the oracle's state
-        chk = tc.Bank(r, seed)
+        chk = new_bank()
         chk.process_stream(G[:min(m, nbo * w)], w, stream)
         same = all(np.array_equal(a, b_) for a, b_ in zip(chk.state(), ob.state()))
         out["bit_exact_vs_oracle"] = bool(same)

@@ -76,15 +76,24 @@ int tc_process_batch(tc_state *s, const uint32_t *edges, uint32_t w,
  * (uint32_t[2*m], 8-byte aligned) cut into ceil(m/w) consecutive batches of
  * w edges (the last one ragged), each one bulkUpdateAll in stream order.
  * The result is bit-identical to that many tc_process_batch calls on the
- * same cuts.  Inside the call, the closing-edge check (Step 3) of batch k
- * runs on an internal stream while batch k+1 is grouped on `stream`; the
- * call joins that stream back before it returns, so work enqueued on
- * `stream` afterwards sees every batch complete, and the call may be
- * captured into a HIP graph.  TC_EINVAL for a NULL state, NULL edges with
+ * same cuts.  Inside the call, for w <= 2^20, the closing-edge check
+ * (Step 3) of batch k runs on an internal stream while batch k+1 is grouped
+ * on `stream` (larger batches run one after the other); the call joins that
+ * stream back before it returns, so work enqueued on `stream` afterwards
+ * sees every batch complete, and the call may be captured into a HIP graph.  TC_EINVAL for a NULL state, NULL edges with
  * m > 0, w == 0 or w > TC_MAX_BATCH; on any error the batches before the
  * failing one stay enqueued. */
 int tc_process_stream(tc_state *s, const uint32_t *edges, uint64_t m,
                       uint32_t w, void *stream);
+
+/* Declare that every vertex id of this bank's stream is below n
+ * (2 <= n <= 2^32; the default is 2^32).  The grouping sort then runs only
+ * as many 8-bit radix passes as n - 1 has bytes, fewer kernel launches per
+ * batch.  An id >= n in a later batch is detected on the device: that step
+ * is abandoned and the next synchronising call returns TC_EINVAL (sticky;
+ * the bank is then unspecified).  Applies to batches enqueued afterwards.
+ * TC_EINVAL for n out of range. */
+int tc_set_vertex_bound(tc_state *s, uint64_t n);
 
 /* Pre-size the bank's step scratch for batches of up to max_w edges so that
  * later tc_process_batch calls with w <= max_w allocate nothing (needed
@@ -153,6 +162,9 @@ int tc_multi_reset(tc_multi *s, void *stream);
  * batch index 0; its size r stays).  Lets a serving loop hand a bank slot
  * to a new stream once the previous stream is finished and read out. */
 int tc_multi_assign(tc_multi *s, uint32_t bank, uint64_t seed, void *stream);
+
+/* As tc_set_vertex_bound, for every bank of the object. */
+int tc_multi_set_vertex_bound(tc_multi *s, uint64_t n);
 
 /* Prepare to capture up to nsteps tc_multi_process calls into a HIP graph:
  * each captured step gets its own pinned descriptor buffer, left unchanged

@@ -59,6 +59,8 @@ def lib():
         "tc_create": ([u32, u64], vp),
         "tc_process_batch": ([vp, vp, u32, vp], i32),
         "tc_process_stream": ([vp, vp, u64, u32, vp], i32),
+        "tc_set_vertex_bound": ([vp, u64], i32),
+        "tc_multi_set_vertex_bound": ([vp, u64], i32),
         "tc_estimate": ([vp], ctypes.c_double),
         "tc_estimate_ex": ([vp, P64, P64, ctypes.POINTER(ctypes.c_double)], i32),
         "tc_read_state": ([vp, vp, vp, vp, vp], i32),
@@ -103,7 +105,8 @@ EXPORTS = ("tc_create", "tc_process_batch", "tc_process_stream", "tc_estimate", 
            "tc_set_kernel_timing", "tc_kernel_times", "tc_multi_set_kernel_timing",
            "tc_multi_kernel_times", "tc_num_kernels", "tc_kernel_name",
            "tc_reserve", "tc_multi_reserve", "tc_reset", "tc_multi_reset",
-           "tc_multi_graph_reserve", "tc_multi_assign")
+           "tc_multi_graph_reserve", "tc_multi_assign", "tc_set_vertex_bound",
+           "tc_multi_set_vertex_bound")
 
 
 def _check(rc: int):
@@ -153,6 +156,14 @@ def tc_process_stream(state: int, edges, w: int, stream=None) -> None:
     else:
         ptr, m = _edge_ptr(edges)
     _check(lib().tc_process_stream(state, ptr or None, m, w, _stream_handle(stream)))
+
+
+def tc_set_vertex_bound(state: int, n: int) -> None:
+    _check(lib().tc_set_vertex_bound(state, n))
+
+
+def tc_multi_set_vertex_bound(multi: int, n: int) -> None:
+    _check(lib().tc_multi_set_vertex_bound(multi, n))
 
 
 def tc_reserve(state: int, max_w: int) -> None:

@@ -73,6 +73,15 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+// kernels (bit k = launch k of a step) that a step with npass radix passes
+// launches: the three kernels of each pass at or above npass are skipped
+uint32_t launched_kernels(uint32_t npass) {
+  uint32_t m = (1u << kNumKernels) - 1u;
+  for (uint32_t p = npass < 1 ? 1 : npass; p < (uint32_t)kPasses; ++p)
+    m &= ~(7u << (3 + 3 * (p - 1)));
+  return m;
+}
+
 // Per-parity scratch: the Step-3 phase of step s (on the engine's second
 // stream) overlaps the grouping phase of step s+1, so everything both
 // phases touch exists twice and step s uses copy s & 1.
@@ -138,12 +147,15 @@ struct Engine {
   std::vector<SegDesc*> graph_stage;
   size_t graph_next = 0;
   int sticky = TC_OK;
+  uint32_t id_limit = 0xFFFFFFFFu;  // declared vertex bound - 1
+  uint32_t npass = kPasses;
 
   // optional per-kernel timing: a start/end event pair per timed kernel
   // and step (bit k of timing_mask times kernel k)
   bool timing = false;
   uint32_t timing_mask = 0;
   std::vector<hipEvent_t*> ev_pending, ev_free;
+  std::vector<uint32_t> ev_launched;  // per pending step: kernels it launched
   double kernel_ms[kNumKernels] = {};
   uint64_t timed_steps = 0;
 
@@ -166,6 +178,7 @@ struct Engine {
   void release() {
     wait_all();
     (void)hipDeviceSynchronize();
+    ev_launched.clear();
     for (auto* v : {&ev_pending, &ev_free})
       for (hipEvent_t* e : *v) {
         for (int k = 0; k < 2 * kNumKernels; ++k)
@@ -424,6 +437,8 @@ struct Engine {
     a.need_bytes = need_n;
     a.inv = inv;
     a.err = err;
+    a.id_limit = id_limit;
+    a.npass = npass;
     if (a.nseg > 1) {
       rc = stage_descs(segs, P.segs, st, capturing);
       if (rc) return rc;
@@ -441,6 +456,7 @@ struct Engine {
               return fail(TC_EHIP, "hipEventCreate failed");
       }
       ev_pending.push_back(ev);
+      ev_launched.push_back(launched_kernels(npass));
     }
     // A: group the batch; B: Steps 1-2, after the previous step's Step 3;
     // C: Step 3, on st2 when it may overlap the next step's A
@@ -494,6 +510,16 @@ struct Engine {
     return TC_OK;
   }
 
+  // every vertex id is below n (2 <= n <= 2^32): the radix passes above
+  // the top byte of n - 1 are not launched
+  int set_bound(uint64_t n) {
+    if (n < 2 || n > (1ull << 32)) return fail(TC_EINVAL, "vertex bound must be in [2, 2^32]");
+    id_limit = (uint32_t)(n - 1);
+    npass = 1;
+    while (npass < kPasses && (id_limit >> (8 * npass)) != 0u) ++npass;
+    return TC_OK;
+  }
+
   int graph_reserve(uint32_t nsteps) {
     // outstanding eager work is finished, so a capture starts from a state
     // that depends on no event recorded outside it
@@ -517,9 +543,12 @@ struct Engine {
     if (hipMemcpy(h_err, err, 4, hipMemcpyDeviceToHost) != hipSuccess)
       return fail(TC_EHIP, "reading the device error word failed");
     const uint32_t e = *h_err;
-    if (e & kErrSelfLoop) sticky = TC_EBADEDGE;
+    if (e & kErrRange) sticky = TC_EINVAL;
+    else if (e & kErrSelfLoop) sticky = TC_EBADEDGE;
     else if (e & kErrOverflow) sticky = TC_EOVERFLOW;
     else if (e & (kErrProbe | kErrStall)) sticky = TC_EHIP;
+    if (sticky == TC_EINVAL)
+      return fail(sticky, "a batch contained a vertex id at or above the declared bound");
     if (sticky == TC_EBADEDGE) return fail(sticky, "a batch contained a self-loop");
     if (sticky == TC_EOVERFLOW) return fail(sticky, "an adjacency count reached 2^31");
     if (sticky != TC_OK) return fail(sticky, "a device table or wait ran past its bound");
@@ -528,9 +557,10 @@ struct Engine {
 
   // accumulate the elapsed time of every pending timed step
   int collect_times() {
-    for (hipEvent_t* e : ev_pending) {
+    for (size_t i = 0; i < ev_pending.size(); ++i) {
+      hipEvent_t* e = ev_pending[i];
       for (int k = 0; k < kNumKernels; ++k) {
-        if (!e[2 * k]) continue;
+        if (!e[2 * k] || !(ev_launched[i] >> k & 1u)) continue;
         float ms = 0;
         if (hipEventSynchronize(e[2 * k + 1]) ||
             hipEventElapsedTime(&ms, e[2 * k], e[2 * k + 1]))
@@ -541,6 +571,7 @@ struct Engine {
       ev_free.push_back(e);
     }
     ev_pending.clear();
+    ev_launched.clear();
     return TC_OK;
   }
 
@@ -628,7 +659,10 @@ int tc_process_stream(tc_state* s, const uint32_t* edges, uint64_t m,
   for (uint64_t j = 0; j < m; j += w) {
     const uint32_t wk = (uint32_t)std::min<uint64_t>(w, m - j);
     const uint32_t* ek = edges + 2 * j;
-    const bool more = j + w < m;
+    // Step 3 of a batch overlaps the grouping of the next only for batches
+    // of up to 2^20 edges: larger ones fill the device on their own, and
+    // the two phases then slow each other down more than they overlap
+    const bool more = j + w < m && w <= (1u << 20);
     int rc = s->e.step(1, &id, &ek, &wk, st, false, more);
     if (rc) {
       (void)s->e.join(st);
@@ -636,6 +670,11 @@ int tc_process_stream(tc_state* s, const uint32_t* edges, uint64_t m,
     }
   }
   return TC_OK;
+}
+
+int tc_set_vertex_bound(tc_state* s, uint64_t n) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  return s->e.set_bound(n);
 }
 
 int tc_reserve(tc_state* s, uint32_t max_w) {
@@ -792,6 +831,11 @@ int tc_multi_assign(tc_multi* s, uint32_t bank, uint64_t seed, void* stream) {
   if (!s) return fail(TC_EINVAL, "null object");
   if (bank >= s->e.nbanks) return fail(TC_EINVAL, "bank id out of range");
   return s->e.assign(bank, seed, static_cast<hipStream_t>(stream));
+}
+
+int tc_multi_set_vertex_bound(tc_multi* s, uint64_t n) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  return s->e.set_bound(n);
 }
 
 int tc_multi_graph_reserve(tc_multi* s, uint32_t nsteps) {

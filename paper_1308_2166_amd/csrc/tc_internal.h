@@ -48,8 +48,9 @@ constexpr uint32_t kErrSelfLoop = 1u;
 constexpr uint32_t kErrOverflow = 2u;
 constexpr uint32_t kErrProbe = 4u;  // a table probe ran past its bound
 constexpr uint32_t kErrStall = 8u;  // a bounded wait gave up
+constexpr uint32_t kErrRange = 16u;  // a vertex id above the declared bound
 // errors after which the rest of a step must not trust its scratch
-constexpr uint32_t kErrFatal = kErrSelfLoop | kErrStall;
+constexpr uint32_t kErrFatal = kErrSelfLoop | kErrStall | kErrRange;
 // bounded waits: a look-back or a busy table slot is given this many polls
 constexpr uint32_t kSpinLimit = 1u << 24;
 
@@ -141,6 +142,9 @@ struct StepArgs {
   uint32_t* inv;          // per arc slot: its index in the sorted arcs (only
                           // for arcs of needed positions)
   uint32_t* err;          // sticky error bits
+  uint32_t id_limit;      // largest vertex id allowed (declared bound - 1)
+  uint32_t npass;         // radix passes launched (1..kPasses): the bound's
+                          // byte count
 };
 
 }  // namespace tc

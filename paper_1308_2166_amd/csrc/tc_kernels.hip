@@ -251,6 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
     hist_add(h, x.w & 255u, v23);
   }
   if (loop) atomicOr(a.err, kErrSelfLoop);
+  if (vmax > a.id_limit) atomicOr(a.err, kErrRange);
   atomicMax(&s_max, vmax);
   __syncthreads();
   // the block's counts go out with plain stores; the fold sums them, so
@@ -407,10 +408,10 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
   SegWork* wk = a.work + sidx;
   const uint32_t n = 2u * S.w;
   const uint32_t maxid = uniform(wk->maxid);
-  if (P == kPasses - 1 && blockIdx.x == S.tile_off && tid == 0) {
-    int K = 0;  // passes run
+  if (P == 0 && blockIdx.x == S.tile_off && tid == 0) {
+    int K = 0;  // passes run (the launched ones that do not skip)
 #pragma unroll
-    for (int d = 0; d < kPasses; ++d) K += pass_runs(maxid, d) ? 1 : 0;
+    for (int d = 0; d < kPasses; ++d) K += (d < (int)a.npass && pass_runs(maxid, d)) ? 1 : 0;
     wk->final_buf = (uint32_t)((K + 1) & 1);  // (K - 1) & 1, K >= 1
     const uint64_t span = (uint64_t)maxid + 1;
     wk->dense = span <= (1ull << S.dir_log2) ? 1u : 0u;
@@ -556,8 +557,8 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
 
 // The body needs about 140 registers; passes whose build fits in 128
 // without spilling run with four waves per SIMD (one more block per CU),
-// the others (the first pass reads W and the need bytes; the last one sets
-// up the directory mode) with three.
+// the others (the first pass reads W and the need bytes and sets up the
+// directory mode; the last one) with three.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_scat(StepArgs a) {
   scat_body<P>(a);
@@ -951,16 +952,19 @@ hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st,
     });
     const dim3 chunks(a.nchunk);
     run(2, [&] { hipLaunchKernelGGL(k_scat<0>, tiles, blk, 0, st, a); });
-    int k = 3;
-    auto pass = [&](auto cntk, auto csumk, auto scatk) {
-      run(k++, [&] { hipLaunchKernelGGL(cntk, tiles, blk, 0, st, a); });
-      run(k++, [&] { hipLaunchKernelGGL(csumk, chunks, blk, 0, st, a); });
-      run(k++, [&] { hipLaunchKernelGGL(scatk, tiles, blk, 0, st, a); });
+    // launch k of pass P (P >= 1) is 3 + 3 (P - 1) + {0, 1, 2}
+    auto pass = [&](int P, auto cntk, auto csumk, auto scatk) {
+      const int k = 3 + 3 * (P - 1);
+      run(k, [&] { hipLaunchKernelGGL(cntk, tiles, blk, 0, st, a); });
+      run(k + 1, [&] { hipLaunchKernelGGL(csumk, chunks, blk, 0, st, a); });
+      run(k + 2, [&] { hipLaunchKernelGGL(scatk, tiles, blk, 0, st, a); });
     };
-    pass(k_cnt<1>, k_csum<1>, k_scat4<1>);
-    pass(k_cnt<2>, k_csum<2>, k_scat4<2>);
-    pass(k_cnt<3>, k_csum<3>, k_scat<3>);
-    run(k++, [&] { hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a); });
+    // passes above the declared vertex bound are not launched (k_hist
+    // reports an id above it)
+    if (a.npass > 1) pass(1, k_cnt<1>, k_csum<1>, k_scat4<1>);
+    if (a.npass > 2) pass(2, k_cnt<2>, k_csum<2>, k_scat4<2>);
+    if (a.npass > 3) pass(3, k_cnt<3>, k_csum<3>, k_scat<3>);
+    run(kNumKernels - 4, [&] { hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a); });
   } else if (phase == 1) {
     run(kNumKernels - 3, [&] { hipLaunchKernelGGL(k_est, ests, blk, 0, st, a); });
   } else {

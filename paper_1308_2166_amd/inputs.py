@@ -224,6 +224,11 @@ def workload(name: str, device="cpu"):
     raise KeyError(name)
 
 
+def vertex_count(name: str) -> int:
+    """Vertex ids of a named workload lie in [0, vertex_count)."""
+    return {"gnm-2k": 2000, "rmat20": 1 << 20, "rmat24": 1 << 24}[name]
+
+
 def lognormal_sizes(k: int, seed: int, median: float = 3e5, sigma: float = 1.2,
                     lo: float = 1e4, hi: float = 1e7):
     """k stream lengths, ln m ~ N(ln median, sigma^2), clipped to [lo, hi]."""
@@ -246,7 +251,8 @@ def many_streams(nstreams: int = 256, seed: int = 404, device="cpu",
     """Independent streams of uneven length for the batched form.
 
     Stream lengths are lognormal (median 3e5, sigma 1.2, clipped to
-    [1e4, 1e7]; `size_scale` shrinks them for tests).  Even-indexed streams
+    [1e4, 1e7]; `size_scale` shrinks them for tests).  Each entry also
+    gives n, a bound on its vertex ids.  Even-indexed streams
     are R-MAT with scale ~ U{16..22} (raised until m/n <= 16), odd-indexed
     ones Chung-Lu with n = m/8 and degree exponent 2.1.  Each stream has its
     own bank of r = 2^U{14..18} estimators and its own seed.
@@ -264,12 +270,14 @@ def many_streams(nstreams: int = 256, seed: int = 404, device="cpu",
                 sc += 1
             e = rmat(sc, m, seed=gseed, device=device)
             kind = f"rmat{sc}"
+            nv = 1 << sc
         else:
             n = max(64, m // 8)
             e = chung_lu(n, m, seed=gseed, device=device)
             kind = f"chunglu{n}"
+            nv = n
         r = 1 << rlog[s]
         if size_scale < 1.0:
             r = max(16, int(r * size_scale))
-        out.append({"edges": e, "r": r, "seed": gseed ^ 0x5A5A, "kind": kind})
+        out.append({"edges": e, "r": r, "seed": gseed ^ 0x5A5A, "kind": kind, "n": nv})
     return out

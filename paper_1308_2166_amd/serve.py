@@ -26,7 +26,8 @@ import time
 
 import torch
 
-from . import MultiBank, tc_multi_assign, tc_multi_estimate, tc_multi_reserve
+from . import (MultiBank, tc_multi_assign, tc_multi_estimate, tc_multi_reserve,
+               tc_multi_set_vertex_bound)
 
 
 @dataclasses.dataclass
@@ -85,14 +86,19 @@ class Server:
     """Admission, continuous batching and latency bookkeeping."""
 
     def __init__(self, slots: int, r: int, depth: int = 2,
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None,
+                 vertex_bound: int | None = None):
         """`slots` resident banks of r estimators.  Step scratch grows to
         the largest step seen (the first run is a warm-up) and is reused;
-        every run reassigns the slots it uses, so a Server serves many runs."""
+        every run reassigns the slots it uses, so a Server serves many runs.
+        vertex_bound: every vertex id of every stream is below it (fewer
+        radix passes; an id at or above it fails the run)."""
         if slots < 1:
             raise ValueError("the memory budget leaves no bank slot")
         self.slots, self.r, self.depth = slots, r, depth
         self.bank = MultiBank([r] * slots, [0] * slots)
+        if vertex_bound is not None:
+            tc_multi_set_vertex_bound(self.bank.h, vertex_bound)
         self.stream = stream or torch.cuda.current_stream()
 
     def reserve(self, chunk_sizes) -> None:

@@ -456,3 +456,74 @@ def test_process_stream_arguments(tc):
         assert ei.value.code == tc.TC_EINVAL
     g.process_stream(dev[:0], 10)  # empty stream: nothing happens
     assert g.m == 0 and g.batch == 0
+
+
+# -- declared vertex bound: fewer radix passes, same results ----------------------
+
+@pytest.mark.parametrize("n,m,w,bound", [(200, 3000, 700, 200), (2000, 20000, 2048, 2000),
+                                         (3000, 30000, 9001, 1 << 16), (250, 2000, 500, 256)])
+def test_vertex_bound_same_results(tc, n, m, w, bound):
+    E = np_edges(inputs.gnm(n, m, seed=n + w))
+    dev = to_dev(E)
+    g = tc.Bank(3000, 21)
+    tc.tc_set_vertex_bound(g.h, bound)
+    g.process_stream(dev, w)
+    o = O.run_stream(E, 3000, 21, w)
+    assert_same(g.state(), o.state(), f"bound {bound}")
+
+
+def test_vertex_bound_rmat20(tc):
+    G, r, w, seed = inputs.workload("rmat20", device="cuda")
+    sub = G[:2 * w]
+    g = tc.Bank(r, seed)
+    tc.tc_set_vertex_bound(g.h, inputs.vertex_count("rmat20"))
+    for k in range(2):
+        g.process(sub[k * w:(k + 1) * w])
+    o = O.run_stream(np_edges(sub), r, seed, w)
+    assert_same(g.state(), o.state(), "rmat20 with bound")
+
+
+def test_vertex_bound_violation_is_reported(tc):
+    E = np_edges(inputs.gnm(100, 800, seed=2))
+    g = tc.Bank(500, 3)
+    tc.tc_set_vertex_bound(g.h, 100)
+    g.process(to_dev(E))
+    g.sync()
+    bad = E[:50].copy()
+    bad[7] = (5, 150)
+    g.process(to_dev(bad))
+    with pytest.raises(tc.TcError) as ei:
+        g.sync()
+    assert ei.value.code == tc.TC_EINVAL
+    with pytest.raises(tc.TcError):  # sticky
+        g.process(to_dev(E[:10]))
+    for n in (0, 1, (1 << 32) + 1):
+        with pytest.raises(tc.TcError):
+            tc.tc_set_vertex_bound(tc.Bank(10, 1).h, n)
+
+
+def test_multi_vertex_bound(tc):
+    rs, seeds = [700, 1500, 900], [1, 2, 3]
+    Es = [np_edges(inputs.gnm(300 + 100 * b, 4000, seed=40 + b)) for b in range(3)]
+    mb = tc.MultiBank(rs, seeds)
+    tc.tc_multi_set_vertex_bound(mb.h, 600)
+    w = 1000
+    for k in range(4):
+        mb.process([0, 1, 2], [to_dev(E[k * w:(k + 1) * w]) for E in Es])
+    for b in range(3):
+        assert_same(mb.state(b), O.run_stream(Es[b], rs[b], seeds[b], w).state(), f"bank {b}")
+
+
+def test_kernel_timing_with_bound(tc):
+    # passes above the bound are not launched: their times stay zero
+    E = to_dev(np_edges(inputs.gnm(200, 3000, seed=9)))
+    g = tc.Bank(1000, 2)
+    tc.tc_set_vertex_bound(g.h, 200)
+    tc.tc_set_kernel_timing(g.h, True)
+    g.process(E[:1500])
+    g.process(E[1500:])
+    times, steps = tc.tc_kernel_times(g.h)
+    assert steps == 2
+    assert times["k_scat<0>"] > 0 and times["k_est"] > 0
+    for p in (1, 2, 3):
+        assert times[f"k_scat<{p}>"] == 0.0 and times[f"k_cnt<{p}>"] == 0.0
