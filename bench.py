@@ -538,6 +538,12 @@ def main():
         step_alg = sum(alg_bytes(k_, w, r, nontrivial) for k_ in per_kernel)
         roofline["step_alg_bytes"] = step_alg
         roofline["step_alg_GBs"] = round(step_alg / (dt / steps) / 1e9, 1)
+        # the method's own bytes per step: read W, write and read the 2w
+        # 8-byte arcs once, read and write 24 bytes of state per estimator
+        b_alg = 8.0 * w + 32.0 * w + 48.0 * r
+        roofline["method_bytes_per_step"] = b_alg
+        roofline["method_GBs"] = round(b_alg / (dt / steps) / 1e9, 1)
+        roofline["method_frac"] = round(b_alg / (dt / steps) / 1e9 / HBM_PEAK_GBS, 4)
 
     out = {
         "metric": METRIC, "value": value, "unit": "estimator-edge updates/s",
