@@ -217,9 +217,11 @@ def kernel_source_hash() -> str:
 
 
 def _short(name: str) -> str:
+    """Kernel name as tc_kernel_name gives it (the four-wave build of a
+    radix pass, k_scat4<P>, is the launch k_scat<P>)."""
     import re
     n = re.sub(r"\(.*", "", name).replace("void ", "").replace("tc::", "")
-    return n.strip()
+    return n.strip().replace("k_scat4<", "k_scat<")
 
 
 def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command, timed=0):
@@ -533,6 +535,14 @@ def main():
                     and rec["kernel_source_sha256_16"] == kernel_source_hash()
                     and rec["per_kernel"].get(dom, {}).get("hbm_bytes")):
                 roofline["traffic"] = rec["per_kernel"][dom]["hbm_bytes"]
+                # the whole step: measured HBM bytes of every kernel it
+                # launches, over the timed step time
+                step_bytes = sum(v["hbm_bytes"] for k_, v in rec["per_kernel"].items()
+                                 if k_ in per_kernel and per_kernel[k_] > 0 and v["hbm_bytes"])
+                roofline["step_traffic_bytes"] = step_bytes
+                roofline["step_traffic_GBs"] = round(step_bytes / (dt / steps) / 1e9, 1)
+                roofline["step_traffic_frac"] = round(
+                    step_bytes / (dt / steps) / 1e9 / HBM_PEAK_GBS, 4)
         except (OSError, KeyError, ValueError):
             pass
         step_alg = sum(alg_bytes(k_, w, r, nontrivial) for k_ in per_kernel)
