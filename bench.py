@@ -206,6 +206,62 @@ def batched_comparison(tc, inputs, nstreams=256, ks=(4, 8, 16), replays=3):
     }
 
 
+def host_fed(tc, G, r, seed, w, nv, reps=2):
+    """The same stream fed from pinned host memory: each batch is copied to
+    one of two device buffers on a copy stream while the previous batch is
+    processed.  Returns the PCIe-inclusive rate (never the headline value)
+    and the copy rate alone."""
+    import torch
+    m = G.shape[0]
+    nb = (m + w - 1) // w
+    host = torch.empty(G.shape, dtype=G.dtype, pin_memory=True)
+    host.copy_(G)
+    bufs = [torch.empty((w, 2), dtype=G.dtype, device="cuda") for _ in range(2)]
+    main = torch.cuda.current_stream()
+    cp = torch.cuda.Stream()
+    ready = [torch.cuda.Event() for _ in range(2)]
+    free = [torch.cuda.Event() for _ in range(2)]
+    best = None
+    for _ in range(reps):
+        b = tc.Bank(r, seed)
+        tc.tc_set_vertex_bound(b.h, nv)
+        tc.tc_reserve(b.h, w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(nb):
+            j = k % 2
+            wk = min(w, m - k * w)
+            with torch.cuda.stream(cp):
+                if k >= 2:
+                    cp.wait_event(free[j])
+                bufs[j][:wk].copy_(host[k * w:k * w + wk], non_blocking=True)
+                ready[j].record(cp)
+            main.wait_event(ready[j])
+            b.process(bufs[j][:wk], main)
+            free[j].record(main)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s_fed = tc.tc_estimate_ex(b.h)[0]
+        b.close()
+        best = dt if best is None else min(best, dt)
+    ref = tc.Bank(r, seed)
+    ref.process_stream(G, w)
+    same = tc.tc_estimate_ex(ref.h)[0] == s_fed
+    ref.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(nb):
+        wk = min(w, m - k * w)
+        bufs[k % 2][:wk].copy_(host[k * w:k * w + wk], non_blocking=True)
+    torch.cuda.synchronize()
+    t_copy = time.perf_counter() - t0
+    return {"ms_per_step": best * 1e3 / nb, "value": r * m / best,
+            "edges_per_s": m / best, "unit": "estimator-edge updates/s",
+            "h2d_GBs": 8.0 * m / t_copy / 1e9, "same_S_as_resident": bool(same),
+            "note": "batches copied from pinned host memory (double-buffered, "
+                    "overlapped with the steps); PCIe-inclusive, not the headline"}
+
+
 KERNEL_SRC = os.path.join(ROOT, "paper_1308_2166_amd", "csrc", "tc_kernels.hip")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_rmat20.json")
 
@@ -376,6 +432,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the plain vs batched comparison on many streams")
     ap.add_argument("--streams", type=int, default=256)
+    ap.add_argument("--no-host-fed", action="store_true",
+                    help="skip the run fed from pinned host memory")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the continuous-batching serving run")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -569,6 +627,10 @@ def main():
         "kernel_ms_per_step_alone": {k_: round(v / timed, 4)
                                      for k_, v in per_kernel.items()} if timed else None,
     }
+
+    if not args.no_host_fed:
+        log("[bench] host-fed stream")
+        out["host_fed"] = host_fed(tc, G, r, seed, w, nv)
 
     if not args.no_batched:
         out["batched"] = batched_comparison(tc, inputs, nstreams=args.streams)
