@@ -321,6 +321,14 @@ __device__ __forceinline__ bool pass_runs(uint32_t maxid, int P) {
   return P == 0 || (maxid >> (8 * P)) != 0u;
 }
 
+// bits of digit P that can be nonzero (the match needs only those; used
+// from pass 2 on, where ids often stop short of the digit's top -- on the
+// lower passes the early exit costs more than it saves)
+__device__ __forceinline__ int digit_bits(uint32_t maxid, int P) {
+  const uint32_t top = maxid >> (8 * P);
+  return top == 0u ? 1 : min(8, 32 - __clz(top));
+}
+
 // row of tile t's digit counts (pass P) in the partial-count array
 __device__ __forceinline__ uint32_t* cnt_row(const StepArgs& a, uint32_t t, int P) {
   return a.hpart + (size_t)t * (kPasses * kDigits) + (size_t)P * kDigits;
@@ -338,7 +346,9 @@ __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
   const uint32_t n = 2u * S.w;
-  if (!pass_runs(uniform(a.work[sidx].maxid), P)) return;
+  const uint32_t maxid = uniform(a.work[sidx].maxid);
+  if (!pass_runs(maxid, P)) return;
+  const int nbits = digit_bits(maxid, P);
   const uint32_t base = (blockIdx.x - S.tile_off) * kTile;
   const uint32_t nv = min((uint32_t)kTile, n - base);
   // high words (vertex ids) of the pass input, read in order
@@ -357,6 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
     uint32_t lo = (uint32_t)vm, hi2 = (uint32_t)(vm >> 32);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
+      if (P >= 2 && b >= nbits) break;  // higher digit bits are zero in every arc
       const uint32_t t = (uint32_t)((int32_t)(dg << (31 - b)) >> 31);
       const uint64_t bb = __ballot(t != 0u);
       lo = __builtin_amdgcn_bitop3_b32(lo, t, (uint32_t)bb, 0x90);
@@ -417,6 +428,7 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
     wk->dense = span <= (1ull << S.dir_log2) ? 1u : 0u;
   }
   if (!pass_runs(maxid, P)) return;
+  const int nbits = digit_bits(maxid, P);
   const uint32_t hist_p = wk->hist[P][tid];
   const uint32_t ltile = blockIdx.x - S.tile_off;
   const uint64_t* src = a.arcs[(P + 1) & 1] + S.arc_off;
@@ -507,6 +519,7 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
     uint32_t lo = (uint32_t)vm, hi = (uint32_t)(vm >> 32);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
+      if (P >= 2 && b >= nbits) break;  // higher digit bits are zero in every arc
       const uint32_t t = (uint32_t)((int32_t)(dg << (31 - b)) >> 31);  // 0 or ~0
       const uint64_t bb = __ballot(t != 0u);
       lo = __builtin_amdgcn_bitop3_b32(lo, t, (uint32_t)bb, 0x90);
@@ -671,15 +684,21 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
     const bool head = i == 0 || (uint32_t)(arc[i - 1] >> 32) != x;
     const bool tail = i + 1 == n || (uint32_t)(arc[i + 1] >> 32) != x;
     if (!head && !tail) continue;
-    uint32_t slot;
     if (dense) {
       if (x > mask) continue;  // cannot happen: x <= max id < 2^dir_log2
-      slot = x;
-      *reinterpret_cast<uint2*>(&dir[x]) = make_uint2(x, tag);
-    } else {
-      slot = dir_claim(dir, mask, x, tag, a.err);
-      if (slot == kNone) continue;
+      // the head writes key, tag and start (and end too for a one-arc
+      // segment) in one store; a separate tail writes end
+      if (head && tail) {
+        *reinterpret_cast<uint4*>(&dir[x]) = make_uint4(x, tag, i, i + 1);
+      } else if (head) {
+        *reinterpret_cast<uint3*>(&dir[x]) = make_uint3(x, tag, i);
+      } else {
+        dir[x].end = i + 1;
+      }
+      continue;
     }
+    const uint32_t slot = dir_claim(dir, mask, x, tag, a.err);
+    if (slot == kNone) continue;
     if (head) dir[slot].start = i;
     if (tail) dir[slot].end = i + 1;
   }
@@ -688,9 +707,6 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
 // ---------------------------------------------------------------------------
 // k_est: Steps 1 and 2 per estimator, Step-3 query posted
 // ---------------------------------------------------------------------------
-// register estimator `est` as waiting for closing edge q at a position
-// >= thr: claim an empty slot of q's probe sequence with one CAS (relaxed:
-// the slot's other fields are read only by the next kernel)
 // query-table home slot and fingerprint of a closing edge (independent
 // bits of one hash)
 __device__ __forceinline__ uint32_t q_home(uint64_t hq, uint32_t mask) {
