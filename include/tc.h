@@ -115,6 +115,26 @@ double tc_estimate(tc_state *s);
  * NULL.  Returns TC_OK or a sticky device error. */
 int tc_estimate_ex(tc_state *s, uint64_t *S, uint64_t *m, double *tau);
 
+/* Blocking; the median-of-means aggregate the paper applies to its
+ * estimators (Sec. 3.1, before Theorem 2; Sec. 5): the r estimators are cut
+ * into `groups` contiguous groups, group k = [floor(k r/g), floor((k+1) r/g)),
+ * each group's mean of Lemma 1's X is (|E| / size_k) * S_k with S_k the
+ * exact sum of chi * closed over the group, and *tau receives the median
+ * of the g means (the mean of the two middle ones for even g).  group_sums
+ * (a HOST array of length g, may be NULL) receives the S_k.  tau may be
+ * NULL.  TC_EINVAL unless 1 <= groups <= r. */
+int tc_estimate_mom(tc_state *s, uint32_t groups, double *tau,
+                    uint64_t *group_sums);
+
+/* Theorem 2: the number of estimators that suffices for an
+ * (eps, delta)-approximation of the triangle count of a graph with m edges,
+ * maximum degree maxdeg and tau triangles:
+ * ceil(96 / eps^2 * m * maxdeg / tau * ln(1 / delta)) (the logarithm read as
+ * natural).  0 unless eps > 0, 0 < delta < 1 and tau > 0.  Pure host
+ * function. */
+uint64_t tc_estimators_needed(double eps, double delta, uint64_t m,
+                              uint64_t maxdeg, double tau);
+
 /* Blocking; copies the bank into caller-owned HOST arrays of length r:
  * f1, f2 (canonical codes), chi and closed (0/1).  Any pointer may be NULL. */
 int tc_read_state(tc_state *s, uint64_t *r1, uint64_t *r2, uint32_t *c,
@@ -179,6 +199,10 @@ int tc_multi_graph_reserve(tc_multi *s, uint32_t nsteps);
 /* Blocking; per-bank S, |E| and tau_hat into HOST arrays of length nbanks
  * (any may be NULL). */
 int tc_multi_estimate(tc_multi *s, uint64_t *S, uint64_t *m, double *tau);
+
+/* Blocking; tc_estimate_mom for bank `bank`. */
+int tc_multi_estimate_mom(tc_multi *s, uint32_t bank, uint32_t groups,
+                          double *tau, uint64_t *group_sums);
 
 /* Blocking; like tc_read_state for bank `bank`. */
 int tc_multi_read_state(tc_multi *s, uint32_t bank, uint64_t *r1, uint64_t *r2,

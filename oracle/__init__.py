@@ -66,6 +66,10 @@ def lib():
             f.restype = ctypes.c_int
         L.orc_sum.argtypes, L.orc_sum.restype = [P], u64
         L.orc_estimate.argtypes, L.orc_estimate.restype = [P], ctypes.c_double
+        L.orc_mom.argtypes, L.orc_mom.restype = [P, u32, vp], ctypes.c_double
+        L.orc_estimators_needed.argtypes = [ctypes.c_double, ctypes.c_double, u64, u64,
+                                            ctypes.c_double]
+        L.orc_estimators_needed.restype = u64
         L.orc_rank.argtypes, L.orc_rank.restype = [vp, u32, u32, u32], u32
         L.orc_rank_all.argtypes = [vp, u32, vp, vp, vp, vp]
         L.orc_rank_all.restype = None
@@ -141,6 +145,17 @@ class Bank:
 
     def estimate(self) -> float:
         return lib().orc_estimate(self._p)
+
+    def mom(self, g: int):
+        """(median-of-means estimate, exact group sums S_k)."""
+        sums = np.zeros(max(g, 1), np.uint64)
+        tau = lib().orc_mom(self._p, g, sums.ctypes.data)
+        return tau, sums[:g]
+
+
+def estimators_needed(eps: float, delta: float, m: int, maxdeg: int, tau: float) -> int:
+    """Theorem 2's r for an (eps, delta)-approximation (0 if out of range)."""
+    return lib().orc_estimators_needed(eps, delta, m, maxdeg, tau)
 
 
 def rank(W, x: int, y: int) -> int:

@@ -9,7 +9,7 @@ def build(verbose: bool = False) -> str:
     out = os.path.join(_HERE, "liboracle.so")
     tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-           os.path.join(_HERE, "oracle.c"), "-o", tmp]
+           os.path.join(_HERE, "oracle.c"), "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -8,6 +8,7 @@
  */
 #include "oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -133,6 +134,38 @@ uint64_t orc_sum(const orc_state *s) {
 
 double orc_estimate(const orc_state *s) {
   return (double)orc_sum(s) * (double)s->m / (double)s->r;
+}
+
+static int cmp_double(const void *a, const void *b) {
+  const double x = *(const double *)a, y = *(const double *)b;
+  return (x > y) - (x < y);
+}
+
+double orc_mom(const orc_state *s, uint32_t g, uint64_t *group_sums) {
+  if (g == 0 || g > s->r) return NAN;
+  double *mean = (double *)malloc(sizeof(double) * g);
+  if (!mean) return NAN;
+  for (uint32_t k = 0; k < g; ++k) {
+    /* group k: estimators floor(k r / g) .. floor((k+1) r / g) - 1 */
+    const uint64_t lo = (uint64_t)k * s->r / g;
+    const uint64_t hi = (uint64_t)(k + 1) * s->r / g;
+    uint64_t S = 0;
+    for (uint64_t i = lo; i < hi; ++i)
+      if (s->closed[i]) S += s->c[i];
+    if (group_sums) group_sums[k] = S;
+    mean[k] = (double)S * (double)s->m / (double)(hi - lo);
+  }
+  qsort(mean, g, sizeof(double), cmp_double);
+  const double med = (g & 1u) ? mean[g / 2] : 0.5 * (mean[g / 2 - 1] + mean[g / 2]);
+  free(mean);
+  return med;
+}
+
+uint64_t orc_estimators_needed(double eps, double delta, uint64_t m,
+                               uint64_t maxdeg, double tau) {
+  if (!(eps > 0.0) || !(delta > 0.0 && delta < 1.0) || !(tau > 0.0)) return 0;
+  const double r = 96.0 / (eps * eps) * (double)m * (double)maxdeg / tau * log(1.0 / delta);
+  return (uint64_t)ceil(r);
 }
 
 static int check_batch(const uint32_t *W, uint32_t w) {

@@ -86,6 +86,21 @@ uint64_t orc_sum(const orc_state *s);
 /* Lemma 1 averaged over the bank: (m / r) * S. */
 double orc_estimate(const orc_state *s);
 
+/* Median-of-means (Sec. 3.1, the aggregate named before Theorem 2; group
+ * layout is this build's reading): the r estimators are cut into g
+ * contiguous groups, group k = [floor(k r / g), floor((k+1) r / g)); each
+ * group's mean of Lemma 1's X is (m / size_k) * S_k with S_k the exact sum
+ * of c_i * closed_i over the group; the result is the median of the g
+ * means (the mean of the two middle ones when g is even).  group_sums
+ * (length g, may be NULL) receives S_k.  Returns NaN for g == 0 or g > r. */
+double orc_mom(const orc_state *s, uint32_t g, uint64_t *group_sums);
+
+/* Theorem 2: estimators that suffice for an (eps, delta)-approximation,
+ * ceil(96 / eps^2 * m * maxdeg / tau * ln(1 / delta)) (log read as the
+ * natural logarithm).  0 for arguments out of range. */
+uint64_t orc_estimators_needed(double eps, double delta, uint64_t m,
+                               uint64_t maxdeg, double tau);
+
 /* --- pieces of Sec. 4.3 exposed for the worked-example pins ------------- */
 /* Definition (Rank): rank(x -> y) over batch W. */
 uint32_t orc_rank(const uint32_t *W, uint32_t w, uint32_t x, uint32_t y);

@@ -60,6 +60,10 @@ def lib():
         "tc_process_batch": ([vp, vp, u32, vp], i32),
         "tc_process_stream": ([vp, vp, u64, u32, vp], i32),
         "tc_set_vertex_bound": ([vp, u64], i32),
+        "tc_estimate_mom": ([vp, u32, ctypes.POINTER(ctypes.c_double), P64], i32),
+        "tc_multi_estimate_mom": ([vp, u32, u32, ctypes.POINTER(ctypes.c_double), P64], i32),
+        "tc_estimators_needed": ([ctypes.c_double, ctypes.c_double, u64, u64, ctypes.c_double],
+                                 u64),
         "tc_multi_set_vertex_bound": ([vp, u64], i32),
         "tc_estimate": ([vp], ctypes.c_double),
         "tc_estimate_ex": ([vp, P64, P64, ctypes.POINTER(ctypes.c_double)], i32),
@@ -106,7 +110,8 @@ EXPORTS = ("tc_create", "tc_process_batch", "tc_process_stream", "tc_estimate", 
            "tc_multi_kernel_times", "tc_num_kernels", "tc_kernel_name",
            "tc_reserve", "tc_multi_reserve", "tc_reset", "tc_multi_reset",
            "tc_multi_graph_reserve", "tc_multi_assign", "tc_set_vertex_bound",
-           "tc_multi_set_vertex_bound")
+           "tc_multi_set_vertex_bound", "tc_estimate_mom", "tc_multi_estimate_mom",
+           "tc_estimators_needed")
 
 
 def _check(rc: int):
@@ -156,6 +161,27 @@ def tc_process_stream(state: int, edges, w: int, stream=None) -> None:
     else:
         ptr, m = _edge_ptr(edges)
     _check(lib().tc_process_stream(state, ptr or None, m, w, _stream_handle(stream)))
+
+
+def tc_estimate_mom(state: int, groups: int):
+    """(median-of-means estimate, group sums S_k as a uint64 array)."""
+    tau = ctypes.c_double()
+    sums = np.zeros(max(groups, 1), np.uint64)
+    _check(lib().tc_estimate_mom(state, groups, ctypes.byref(tau),
+                                 sums.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    return tau.value, sums[:groups]
+
+
+def tc_multi_estimate_mom(multi: int, bank: int, groups: int):
+    tau = ctypes.c_double()
+    sums = np.zeros(max(groups, 1), np.uint64)
+    _check(lib().tc_multi_estimate_mom(multi, bank, groups, ctypes.byref(tau),
+                                       sums.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    return tau.value, sums[:groups]
+
+
+def tc_estimators_needed(eps: float, delta: float, m: int, maxdeg: int, tau: float) -> int:
+    return lib().tc_estimators_needed(eps, delta, m, maxdeg, tau)
 
 
 def tc_set_vertex_bound(state: int, n: int) -> None:

@@ -19,9 +19,9 @@
 
 namespace tc {
 hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st, hipEvent_t* ev);
-hipError_t launch_sum(const uint32_t* cc, const uint64_t* bank_off,
-                      uint32_t nbanks, uint64_t total,
-                      unsigned long long* sums, hipStream_t st);
+hipError_t launch_gsum(const uint32_t* cc, uint64_t e0, uint64_t n,
+                       const uint64_t* bank_off, uint32_t nbanks, uint32_t g,
+                       unsigned long long* sums, hipStream_t st);
 hipError_t launch_fill64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
 hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 }  // namespace tc
@@ -108,6 +108,9 @@ struct Engine {
   uint32_t* QT = nullptr;  // its first closing batch position
   uint64_t* bank_off = nullptr;  // device copy of est_off
   unsigned long long* sums = nullptr;
+  unsigned long long* gsums = nullptr;  // median-of-means group sums
+  uint64_t* h_gsums = nullptr;          // pinned
+  uint32_t cap_groups = 0;
   uint32_t* err = nullptr;
   uint32_t* tagp = nullptr;  // directory tag (advanced by every step)
   unsigned long long* h_sums = nullptr;  // pinned
@@ -188,7 +191,10 @@ struct Engine {
     ev_pending.clear();
     ev_free.clear();
     dfree(R1), dfree(R2), dfree(CC), dfree(J1), dfree(QQ), dfree(QT), dfree(bank_off);
-    dfree(sums), dfree(err), dfree(tagp);
+    dfree(sums), dfree(err), dfree(tagp), dfree(gsums);
+    if (h_gsums) (void)hipHostFree(h_gsums);
+    h_gsums = nullptr;
+    cap_groups = 0;
     for (SegDesc* g : graph_stage) (void)hipHostFree(g);
     graph_stage.clear();
     if (h_sums) (void)hipHostFree(h_sums);
@@ -579,12 +585,45 @@ struct Engine {
     int rc = sync();
     if (rc) return rc;
     hipStream_t st = last;
-    if (launch_sum(CC, bank_off, nbanks, total, sums, st) != hipSuccess ||
+    if (launch_gsum(CC, 0, total, bank_off, nbanks, 0, sums, st) != hipSuccess ||
         hipMemcpyAsync(h_sums, sums, sizeof(uint64_t) * nbanks,
                        hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return fail(TC_EHIP, "estimate reduction failed");
     for (uint32_t b = 0; b < nbanks; ++b) S[b] = h_sums[b];
+    return TC_OK;
+  }
+
+  // median-of-means over g contiguous groups of bank b (group sums on the
+  // device, the g means and their median on the host, in double)
+  int mom(uint32_t b, uint32_t g, double* tau, uint64_t* group_sums) {
+    if (g == 0 || g > r[b]) return fail(TC_EINVAL, "groups must be in [1, r]");
+    int rc = sync();
+    if (rc) return rc;
+    if (g > cap_groups) {
+      dfree(gsums);
+      if (h_gsums) (void)hipHostFree(h_gsums);
+      h_gsums = nullptr;
+      cap_groups = 0;
+      if (dalloc(&gsums, g) ||
+          hipHostMalloc(reinterpret_cast<void**>(&h_gsums), sizeof(uint64_t) * g))
+        return fail(TC_ENOMEM, "group-sum buffers");
+      cap_groups = g;
+    }
+    hipStream_t st = last;
+    if (launch_gsum(CC, est_off[b], r[b], nullptr, 0, g, gsums, st) != hipSuccess ||
+        hipMemcpyAsync(h_gsums, gsums, sizeof(uint64_t) * g, hipMemcpyDeviceToHost,
+                       st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(TC_EHIP, "group-sum reduction failed");
+    std::vector<double> mean(g);
+    for (uint32_t k = 0; k < g; ++k) {
+      const uint64_t lo = (uint64_t)k * r[b] / g, hi = (uint64_t)(k + 1) * r[b] / g;
+      mean[k] = (double)h_gsums[k] * (double)m[b] / (double)(hi - lo);
+      if (group_sums) group_sums[k] = h_gsums[k];
+    }
+    std::sort(mean.begin(), mean.end());
+    if (tau) *tau = (g & 1u) ? mean[g / 2] : 0.5 * (mean[g / 2 - 1] + mean[g / 2]);
     return TC_OK;
   }
 
@@ -675,6 +714,18 @@ int tc_process_stream(tc_state* s, const uint32_t* edges, uint64_t m,
 int tc_set_vertex_bound(tc_state* s, uint64_t n) {
   if (!s) return fail(TC_EINVAL, "null state");
   return s->e.set_bound(n);
+}
+
+int tc_estimate_mom(tc_state* s, uint32_t groups, double* tau, uint64_t* group_sums) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  return s->e.mom(0, groups, tau, group_sums);
+}
+
+uint64_t tc_estimators_needed(double eps, double delta, uint64_t m, uint64_t maxdeg,
+                              double tau) {
+  if (!(eps > 0.0) || !(delta > 0.0 && delta < 1.0) || !(tau > 0.0)) return 0;
+  const double r = 96.0 / (eps * eps) * (double)m * (double)maxdeg / tau * std::log(1.0 / delta);
+  return (uint64_t)std::ceil(r);
 }
 
 int tc_reserve(tc_state* s, uint32_t max_w) {
@@ -831,6 +882,13 @@ int tc_multi_assign(tc_multi* s, uint32_t bank, uint64_t seed, void* stream) {
   if (!s) return fail(TC_EINVAL, "null object");
   if (bank >= s->e.nbanks) return fail(TC_EINVAL, "bank id out of range");
   return s->e.assign(bank, seed, static_cast<hipStream_t>(stream));
+}
+
+int tc_multi_estimate_mom(tc_multi* s, uint32_t bank, uint32_t groups, double* tau,
+                          uint64_t* group_sums) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  if (bank >= s->e.nbanks) return fail(TC_EINVAL, "bank id out of range");
+  return s->e.mom(bank, groups, tau, group_sums);
 }
 
 int tc_multi_set_vertex_bound(tc_multi* s, uint64_t n) {

@@ -912,20 +912,47 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
 // ---------------------------------------------------------------------------
 // estimate and small utilities
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_sum(const uint32_t* cc,
-                                                const uint64_t* bank_off,
-                                                uint32_t nbanks, uint64_t total,
-                                                unsigned long long* sums) {
-  const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (gid >= total) return;
-  const uint32_t w = cc[gid];
-  if (!(w & kClosed)) return;
-  uint32_t lo = 0, hi = nbanks - 1;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1) >> 1;
-    if (bank_off[mid] <= gid) lo = mid; else hi = mid - 1;
+// group of local estimator i of n: with bank offsets, its bank; otherwise
+// its median-of-means group k = floor(((i+1) g - 1) / n), i.e. the groups
+// [floor(k n / g), floor((k+1) n / g)), k < g <= n
+__device__ __forceinline__ uint32_t group_of(uint64_t i, const uint64_t* bank_off,
+                                             uint32_t nbanks, uint64_t n, uint32_t g) {
+  if (bank_off) {
+    uint32_t lo = 0, hi = nbanks - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (bank_off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
   }
-  atomicAdd(&sums[lo], (unsigned long long)(w & kChiMax));
+  return (uint32_t)(((i + 1) * (uint64_t)g - 1) / n);
+}
+
+// S_k = sum of chi * closed over the estimators of each group k, for the
+// estimators e0 .. e0 + n - 1 (groups are consecutive, so a block's
+// kGsumChunk estimators fall in at most kGsumChunk groups: summed in LDS
+// first, then one global atomic per group the block touches)
+constexpr uint32_t kGsumChunk = kBlock * 16;
+__global__ __launch_bounds__(kBlock) void k_gsum(const uint32_t* cc, uint64_t e0, uint64_t n,
+                                                 const uint64_t* bank_off, uint32_t nbanks,
+                                                 uint32_t g, unsigned long long* sums) {
+  __shared__ unsigned long long acc[kGsumChunk];
+  const int tid = threadIdx.x;
+  const uint64_t b0 = (uint64_t)blockIdx.x * kGsumChunk;
+  for (uint32_t t = tid; t < kGsumChunk; t += kBlock) acc[t] = 0;
+  const uint32_t k0 = group_of(b0, bank_off, nbanks, n, g);
+  __syncthreads();
+  for (uint32_t t = tid; t < kGsumChunk; t += kBlock) {
+    const uint64_t i = b0 + t;
+    if (i >= n) break;
+    const uint32_t w = cc[e0 + i];
+    if (w & kClosed)
+      atomicAdd(&acc[group_of(i, bank_off, nbanks, n, g) - k0],
+                (unsigned long long)(w & kChiMax));
+  }
+  __syncthreads();
+  for (uint32_t t = tid; t < kGsumChunk; t += kBlock)
+    if (acc[t]) atomicAdd(&sums[k0 + t], acc[t]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill64(uint64_t* p, uint64_t n,
@@ -990,14 +1017,16 @@ hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st,
   return hipGetLastError();
 }
 
-hipError_t launch_sum(const uint32_t* cc, const uint64_t* bank_off,
-                      uint32_t nbanks, uint64_t total,
-                      unsigned long long* sums, hipStream_t st) {
+hipError_t launch_gsum(const uint32_t* cc, uint64_t e0, uint64_t n,
+                       const uint64_t* bank_off, uint32_t nbanks, uint32_t g,
+                       unsigned long long* sums, hipStream_t st) {
+  const uint32_t ngroups = bank_off ? nbanks : g;
   hipLaunchKernelGGL(k_fill64, dim3(1), dim3(kBlock), 0, st,
-                     reinterpret_cast<uint64_t*>(sums), (uint64_t)nbanks, 0ull);
-  const uint64_t nb = (total + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_sum, dim3((uint32_t)nb), dim3(kBlock), 0, st, cc,
-                     bank_off, nbanks, total, sums);
+                     reinterpret_cast<uint64_t*>(sums), (uint64_t)ngroups, 0ull);
+  if (n == 0) return hipGetLastError();
+  const uint64_t nb = (n + kGsumChunk - 1) / kGsumChunk;
+  hipLaunchKernelGGL(k_gsum, dim3((uint32_t)nb), dim3(kBlock), 0, st, cc, e0, n,
+                     bank_off, nbanks, g, sums);
   return hipGetLastError();
 }
 

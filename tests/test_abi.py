@@ -69,3 +69,19 @@ def test_kernels_are_plain_hip_for_gfx950():
     for f in build.SOURCES:
         text = open(os.path.join(PKG, "csrc", f)).read()
         assert "__CUDA" not in text and "__HIP_PLATFORM" not in text
+
+
+def test_estimators_needed_matches_oracle():
+    # Theorem 2's sizing is a pure host function of the library: no GPU
+    import numpy as np
+    import oracle as O
+    import paper_1308_2166_amd as tc
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        eps, delta = float(rng.uniform(0.01, 1.0)), float(rng.uniform(0.001, 0.99))
+        m, deg = int(rng.integers(1, 10**9)), int(rng.integers(1, 10**5))
+        tau = float(rng.uniform(1.0, 1e12))
+        assert tc.tc_estimators_needed(eps, delta, m, deg, tau) == \
+            O.estimators_needed(eps, delta, m, deg, tau)
+    assert tc.tc_estimators_needed(0.5, 0.1, 30, 6, 10.0) == 15916
+    assert tc.tc_estimators_needed(0.5, 1.5, 30, 6, 10.0) == 0

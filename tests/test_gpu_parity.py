@@ -527,3 +527,51 @@ def test_kernel_timing_with_bound(tc):
     assert times["k_scat<0>"] > 0 and times["k_est"] > 0
     for p in (1, 2, 3):
         assert times[f"k_scat<{p}>"] == 0.0 and times[f"k_cnt<{p}>"] == 0.0
+
+
+# -- median-of-means aggregate -----------------------------------------------------
+
+def _assert_mom(got, want):
+    (tg, sg), (to, so) = got, want
+    assert list(map(int, sg)) == list(map(int, so))
+    assert abs(tg - to) <= REL_TOL * max(1.0, abs(to))
+
+
+@pytest.mark.parametrize("groups", [1, 2, 7, 64, 4095, 4096])
+def test_mom_matches_oracle_gnm2k(tc, groups):
+    G, r, w, seed = inputs.workload("gnm-2k")
+    E = np_edges(G)
+    g = tc.Bank(r, seed)
+    g.process_stream(to_dev(E), w)
+    o = O.run_stream(E, r, seed, w)
+    _assert_mom(tc.tc_estimate_mom(g.h, groups), o.mom(groups))
+
+
+def test_mom_matches_oracle_rmat20(tc):
+    G, r, w, seed = inputs.workload("rmat20", device="cuda")
+    sub = G[:2 * w]
+    g = tc.Bank(r, seed)
+    g.process_stream(sub, w)
+    o = O.run_stream(np_edges(sub), r, seed, w)
+    for groups in (1, 9, 1024, r):
+        _assert_mom(tc.tc_estimate_mom(g.h, groups), o.mom(groups))
+    # the plain estimate through the same group-sum kernel
+    S, m, tau = tc.tc_estimate_ex(g.h)
+    assert S == o.sum() and abs(tau - o.estimate()) <= REL_TOL * o.estimate()
+
+
+def test_multi_mom_and_arguments(tc):
+    rs, seeds = [700, 1500, 333], [1, 2, 3]
+    Es = [np_edges(inputs.gnm(300 + 100 * b, 4000, seed=60 + b)) for b in range(3)]
+    mb = tc.MultiBank(rs, seeds)
+    w = 1000
+    for k in range(4):
+        mb.process([0, 1, 2], [to_dev(E[k * w:(k + 1) * w]) for E in Es])
+    for b in range(3):
+        o = O.run_stream(Es[b], rs[b], seeds[b], w)
+        for groups in (1, 5, rs[b]):
+            _assert_mom(tc.tc_multi_estimate_mom(mb.h, b, groups), o.mom(groups))
+    for bad in (0, rs[0] + 1):
+        with pytest.raises(tc.TcError) as ei:
+            tc.tc_multi_estimate_mom(mb.h, 0, bad)
+        assert ei.value.code == tc.TC_EINVAL

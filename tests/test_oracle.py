@@ -270,3 +270,76 @@ def test_duplicate_edges_are_deterministic():
     b = O.run_stream(G, r=100, seed=2, w=13, variant="bulk")
     for x, y in zip(a.state(), b.state()):
         np.testing.assert_array_equal(x, y)
+
+
+# -- median-of-means aggregate and Theorem 2 sizing -----------------------------------
+
+def _bank_with(c, closed, m):
+    """An oracle bank whose (c, closed, |E|) are set directly (test only)."""
+    bank = O.Bank(len(c), seed=1)
+    st = bank._p.contents
+    np.ctypeslib.as_array(st.c, shape=(len(c),))[:] = np.asarray(c, np.uint32)
+    np.ctypeslib.as_array(st.closed, shape=(len(c),))[:] = np.asarray(closed, np.uint8)
+    st.m = m
+    return bank
+
+
+def test_mom_hand_example():
+    # X_i = c_i * closed_i * m = 30, 0, 40, 10, 0, 90 (m = 10)
+    bank = _bank_with([3, 1, 4, 1, 5, 9], [1, 0, 1, 1, 0, 1], m=10)
+    # g = 3: groups {0,1} {2,3} {4,5}: S = 3, 5, 9; means 15, 25, 45
+    tau, sums = bank.mom(3)
+    assert list(sums) == [3, 5, 9] and tau == 25.0
+    # g = 4: groups {0} {1,2} {3} {4,5}: means 30, 20, 10, 45 -> (20 + 30) / 2
+    tau, sums = bank.mom(4)
+    assert list(sums) == [3, 4, 1, 9] and tau == 25.0
+    # g = r: the median of the single estimators, (10 + 30) / 2
+    assert bank.mom(6)[0] == 20.0
+    # g = 1 is Lemma 1's mean: 17 * 10 / 6
+    assert abs(bank.mom(1)[0] - 170.0 / 6.0) < 1e-12 and bank.mom(1)[0] == bank.estimate()
+    for g in (0, 7):
+        assert np.isnan(bank.mom(g)[0])
+
+
+def test_mom_groups_partition_the_bank():
+    G = _random_graph(30, 120, seed=4)
+    bank = O.run_stream(G, r=1001, seed=8, w=17)
+    S = bank.sum()
+    _, _, c, closed = bank.state()
+    x = c.astype(np.uint64) * closed
+    for g in (1, 2, 7, 13, 1000, 1001):
+        tau, sums = bank.mom(g)
+        assert int(sums.sum()) == S
+        bounds = [k * 1001 // g for k in range(g + 1)]
+        assert [int(x[bounds[k]:bounds[k + 1]].sum()) for k in range(g)] == [int(v) for v in sums]
+        means = sorted(int(s) * bank.m / (bounds[k + 1] - bounds[k]) for k, s in enumerate(sums))
+        want = means[g // 2] if g % 2 else 0.5 * (means[g // 2 - 1] + means[g // 2])
+        assert abs(tau - want) <= 1e-12 * max(1.0, abs(want))
+
+
+def test_estimators_needed_is_theorem_2():
+    # 96 / 0.25 * 30 * 6 / 10 * ln 10 = 15915.47...
+    assert O.estimators_needed(0.5, 0.1, 30, 6, 10.0) == 15916
+    assert O.estimators_needed(0.1, 0.01, 1000, 50, 2000.0) == int(np.ceil(
+        96 / 0.01 * 1000 * 50 / 2000.0 * np.log(100.0)))
+    for bad in ((0.0, 0.1, 30, 6, 10.0), (0.5, 0.0, 30, 6, 10.0), (0.5, 1.0, 30, 6, 10.0),
+                (0.5, 0.1, 30, 6, 0.0)):
+        assert O.estimators_needed(*bad) == 0
+
+
+def test_theorem_2_guarantee_holds():
+    # with Theorem 2's r, the median-of-means estimate is within eps * tau
+    # in (well over) a 1 - delta fraction of independent runs
+    G = _random_graph(14, 48, seed=6)
+    codes = brute.stream_codes(G)
+    tau = len(brute.triangles(codes))
+    deg = np.bincount(G.ravel().astype(np.int64))
+    eps, delta = 0.5, 0.2
+    r = O.estimators_needed(eps, delta, len(G), int(deg.max()), float(tau))
+    assert 1000 < r < 200000
+    ok = 0
+    for s in range(10):
+        bank = O.run_stream(G, r=r, seed=700 + s, w=8)
+        est, _ = bank.mom(9)
+        ok += abs(est - tau) <= eps * tau
+    assert ok >= 8
