@@ -262,6 +262,38 @@ def host_fed(tc, G, r, seed, w, nv, reps=2):
                     "overlapped with the steps); PCIe-inclusive, not the headline"}
 
 
+def naive_vs_bulk(tc, inputs, shapes=((4096, 2048), (4096, 16384), (65536, 16384),
+                                       (16384, 131072), (262144, 65536))):
+    """Per-batch time of the per-estimator form (every estimator scans the
+    batch, O(r w)) against the bulk step at small r * w, on R-MAT scale-16
+    batches, with a check that both leave the same state."""
+    import numpy as np
+    import torch
+    G = inputs.rmat(16, 16 << 16, seed=33, device="cuda")
+    out = []
+    for r, w in shapes:
+        batches = [G[j:j + w] for j in range(0, 4 * w, w)]
+        times, states = {}, {}
+        for form in ("naive", "bulk"):
+            b = tc.Bank(r, 9)
+            tc.tc_set_vertex_bound(b.h, 1 << 16)
+            tc.tc_reserve(b.h, w)
+            (b.process_naive if form == "naive" else b.process)(batches[0])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c in batches[1:]:
+                (b.process_naive if form == "naive" else b.process)(c)
+            torch.cuda.synchronize()
+            times[form] = (time.perf_counter() - t0) * 1e6 / (len(batches) - 1)
+            states[form] = b.state()
+            b.close()
+        same = all(np.array_equal(x, y) for x, y in zip(states["naive"], states["bulk"]))
+        out.append({"r": r, "w": w, "naive_us": round(times["naive"], 1),
+                    "bulk_us": round(times["bulk"], 1), "identical": bool(same)})
+        log(f"[bench]   r={r} w={w}: naive {times['naive']:.1f} us, bulk {times['bulk']:.1f} us")
+    return out
+
+
 KERNEL_SRC = os.path.join(ROOT, "paper_1308_2166_amd", "csrc", "tc_kernels.hip")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_rmat20.json")
 
@@ -432,6 +464,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the plain vs batched comparison on many streams")
     ap.add_argument("--streams", type=int, default=256)
+    ap.add_argument("--no-naive", action="store_true",
+                    help="skip the per-estimator form comparison")
     ap.add_argument("--no-host-fed", action="store_true",
                     help="skip the run fed from pinned host memory")
     ap.add_argument("--no-served", action="store_true",
@@ -627,6 +661,10 @@ def main():
         "kernel_ms_per_step_alone": {k_: round(v / timed, 4)
                                      for k_, v in per_kernel.items()} if timed else None,
     }
+
+    if not args.no_naive:
+        log("[bench] per-estimator form vs bulk at small r*w")
+        out["naive_vs_bulk"] = naive_vs_bulk(tc, inputs)
 
     if not args.no_host_fed:
         log("[bench] host-fed stream")

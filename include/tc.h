@@ -72,6 +72,16 @@ tc_state *tc_create(uint32_t r, uint64_t seed);
 int tc_process_batch(tc_state *s, const uint32_t *edges, uint32_t w,
                      void *stream);
 
+/* Enqueue one batch by the per-estimator form that the bulk algorithm
+ * improves on (Sec. 4, opening): every estimator scans the whole batch
+ * itself, O(r * w) work, from the definitions of Steps 1-3.  It makes the
+ * same random draws and the same state transitions as tc_process_batch, so
+ * the two may be mixed on one bank and give bit-identical states; it is
+ * meant for checking and for small r * w.  Same arguments, lifetime and
+ * errors as tc_process_batch. */
+int tc_process_batch_naive(tc_state *s, const uint32_t *edges, uint32_t w,
+                           void *stream);
+
 /* Enqueue a whole resident stream: the m edges at DEVICE address edges
  * (uint32_t[2*m], 8-byte aligned) cut into ceil(m/w) consecutive batches of
  * w edges (the last one ragged), each one bulkUpdateAll in stream order.

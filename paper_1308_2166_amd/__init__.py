@@ -59,6 +59,7 @@ def lib():
         "tc_create": ([u32, u64], vp),
         "tc_process_batch": ([vp, vp, u32, vp], i32),
         "tc_process_stream": ([vp, vp, u64, u32, vp], i32),
+        "tc_process_batch_naive": ([vp, vp, u32, vp], i32),
         "tc_set_vertex_bound": ([vp, u64], i32),
         "tc_estimate_mom": ([vp, u32, ctypes.POINTER(ctypes.c_double), P64], i32),
         "tc_multi_estimate_mom": ([vp, u32, u32, ctypes.POINTER(ctypes.c_double), P64], i32),
@@ -111,7 +112,7 @@ EXPORTS = ("tc_create", "tc_process_batch", "tc_process_stream", "tc_estimate", 
            "tc_reserve", "tc_multi_reserve", "tc_reset", "tc_multi_reset",
            "tc_multi_graph_reserve", "tc_multi_assign", "tc_set_vertex_bound",
            "tc_multi_set_vertex_bound", "tc_estimate_mom", "tc_multi_estimate_mom",
-           "tc_estimators_needed")
+           "tc_estimators_needed", "tc_process_batch_naive")
 
 
 def _check(rc: int):
@@ -152,6 +153,12 @@ def tc_process_batch(state: int, edges, w: int | None = None, stream=None) -> No
     ptr, n = _edge_ptr(edges) if edges is not None else (0, 0)
     _check(lib().tc_process_batch(state, ptr or None, n if w is None else w,
                                   _stream_handle(stream)))
+
+
+def tc_process_batch_naive(state: int, edges, w: int | None = None, stream=None) -> None:
+    ptr, n = _edge_ptr(edges) if edges is not None else (0, 0)
+    _check(lib().tc_process_batch_naive(state, ptr or None, n if w is None else w,
+                                        _stream_handle(stream)))
 
 
 def tc_process_stream(state: int, edges, w: int, stream=None) -> None:
@@ -368,6 +375,9 @@ class Bank:
 
     def process(self, edges, stream=None):
         tc_process_batch(self.h, edges, stream=stream)
+
+    def process_naive(self, edges, stream=None):
+        tc_process_batch_naive(self.h, edges, stream=stream)
 
     def process_stream(self, edges, w: int, stream=None):
         tc_process_stream(self.h, edges, w, stream=stream)

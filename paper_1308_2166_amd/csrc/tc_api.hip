@@ -23,6 +23,7 @@ hipError_t launch_gsum(const uint32_t* cc, uint64_t e0, uint64_t n,
                        const uint64_t* bank_off, uint32_t nbanks, uint32_t g,
                        unsigned long long* sums, hipStream_t st);
 hipError_t launch_fill64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
+hipError_t launch_naive(const NaiveArgs& a, hipStream_t st);
 hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 }  // namespace tc
 
@@ -490,6 +491,31 @@ struct Engine {
     return TC_OK;
   }
 
+  // one batch for bank b by the per-estimator kernel (same state, same draws)
+  int step_naive(uint32_t b, const uint32_t* edges, uint32_t w, hipStream_t st) {
+    if (sticky != TC_OK) return fail(sticky, "an earlier batch failed on the device");
+    if (w > TC_MAX_BATCH) return fail(TC_EINVAL, "batch larger than TC_MAX_BATCH");
+    if (w == 0) return TC_OK;
+    if (!edges) return fail(TC_EINVAL, "null edge pointer with w > 0");
+    if (reinterpret_cast<uintptr_t>(edges) & 7u)
+      return fail(TC_EINVAL, "edge buffer must be 8-byte aligned");
+    NaiveArgs a{};
+    a.edges = edges;
+    a.w = w;
+    a.r = r[b];
+    a.m = m[b];
+    a.batch = batch[b];
+    a.key0 = key0[b];
+    a.est_off = est_off[b];
+    a.r1 = R1, a.r2 = R2, a.cc = CC, a.err = err;
+    if (join(st) || launch_naive(a, st) != hipSuccess)
+      return fail(TC_EHIP, "kernel launch failed");
+    m[b] += w;
+    batch[b] += 1;
+    last = st;
+    return TC_OK;
+  }
+
   // every bank back to empty, |E| = 0, batch 0 (fill kernels only, so a
   // reset can be captured into a graph ahead of captured steps)
   int reset(hipStream_t st) {
@@ -685,6 +711,12 @@ int tc_process_batch(tc_state* s, const uint32_t* edges, uint32_t w,
   if (!s) return fail(TC_EINVAL, "null state");
   const uint32_t id = 0;
   return s->e.step(1, &id, &edges, &w, static_cast<hipStream_t>(stream));
+}
+
+int tc_process_batch_naive(tc_state* s, const uint32_t* edges, uint32_t w,
+                           void* stream) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  return s->e.step_naive(0, edges, w, static_cast<hipStream_t>(stream));
 }
 
 int tc_process_stream(tc_state* s, const uint32_t* edges, uint64_t m,

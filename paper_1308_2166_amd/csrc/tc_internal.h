@@ -147,4 +147,19 @@ struct StepArgs {
                           // byte count
 };
 
+// arguments of the per-estimator (naive) step: one bank, one batch
+struct NaiveArgs {
+  const uint32_t* edges;  // W: uint32[2w], device
+  uint32_t w;
+  uint32_t r;
+  uint64_t m;             // |E| before the batch
+  uint64_t batch;
+  uint64_t key0;
+  uint64_t est_off;
+  uint64_t* r1;
+  uint64_t* r2;
+  uint32_t* cc;
+  uint32_t* err;
+};
+
 }  // namespace tc

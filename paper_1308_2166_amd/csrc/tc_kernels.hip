@@ -910,6 +910,215 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// k_naive: the per-estimator form the bulk algorithm improves on (Sec. 4):
+// every estimator reads the whole batch itself, O(r w) work.  It makes the
+// same random draws and state transitions as the bulk step, written from
+// the definitions: Step 1 takes W[x - |E|] when x = U(|E|+|W|) >= |E|;
+// Step 2 counts the batch edges on each endpoint of f1 after f1's position
+// (ld, rd), keeps f2 when y = U(chi + ld + rd) < chi and otherwise takes the
+// edge with phi = y - chi later edges on u (phi < ld) or phi - ld later
+// edges on v; Step 3 closes when the closing edge occurs in W after f2's
+// position (anywhere, for an f2 from an earlier batch).
+// ---------------------------------------------------------------------------
+// The batch is read in tiles of kNaiveTile edges staged in LDS and shared by
+// the block (every estimator reads every edge: broadcast LDS reads); the
+// three scans (later edges on f1's endpoints, the phi-th edge, the closing
+// edge's latest position) each sweep the tiles, forward or backward.
+constexpr uint32_t kNaiveTile = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_naive(NaiveArgs a) {
+  __shared__ uint2 s_w[kNaiveTile];
+  __shared__ uint32_t s_err;
+  const uint2* W = reinterpret_cast<const uint2*>(a.edges);
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0) {  // a self-loop invalidates the batch
+    bool loop = false;
+    for (uint32_t j = tid; j < a.w; j += kBlock) {
+      const uint2 ed = W[j];
+      loop |= ed.x == ed.y;
+    }
+    if (loop) atomicOr(a.err, kErrSelfLoop);
+  }
+  if (tid == 0) s_err = *a.err;  // one read, so the exit is block-uniform
+  __syncthreads();
+  if (s_err & kErrFatal) return;
+  const uint32_t i = blockIdx.x * kBlock + tid;
+  const bool live = i < a.r;  // threads past r still help load the tiles
+  const uint64_t e = a.est_off + (live ? i : 0u);
+  uint64_t r1 = kEmpty, r2 = kEmpty, c = 0;
+  bool closed = false;
+  uint64_t kb = 0;
+  uint32_t j1 = kNone;
+  if (live) {
+    r1 = a.r1[e];
+    r2 = a.r2[e];
+    const uint32_t ccw = a.cc[e];
+    c = ccw & kChiMax;
+    closed = (ccw & kClosed) != 0;
+    kb = mix64(mix64(a.key0 ^ (uint64_t)i) ^ a.batch);
+    // Step 1
+    const uint64_t x = bounded(kb, 1, a.m + a.w);
+    if (x >= a.m) {
+      j1 = (uint32_t)(x - a.m);
+      const uint2 ed = W[j1];
+      r1 = canon(ed.x, ed.y);
+      c = 0;
+      r2 = kEmpty;
+      closed = false;
+    }
+  }
+  const uint32_t ntile = (a.w + kNaiveTile - 1) / kNaiveTile;
+  auto load_tile = [&](uint32_t t) {
+    __syncthreads();
+    const uint32_t j0 = t * kNaiveTile, n = min(kNaiveTile, a.w - j0);
+    for (uint32_t k = tid; k < n; k += kBlock) s_w[k] = W[j0 + k];
+    __syncthreads();
+  };
+
+  // Step 2: ld, rd = edges on u, v after f1's position (all of W for an
+  // f1 from an earlier batch)
+  const uint32_t u = (uint32_t)(r1 >> 32), v = (uint32_t)r1;
+  uint32_t ld = 0, rd = 0;
+  const uint32_t jstart = j1 == kNone ? 0u : j1 + 1;
+  for (uint32_t t = 0; t < ntile; ++t) {
+    load_tile(t);
+    const uint32_t j0 = t * kNaiveTile, n = min(kNaiveTile, a.w - j0);
+    if (!live || jstart >= j0 + n) continue;
+    uint32_t k = jstart > j0 ? jstart - j0 : 0u;
+    for (; k + 8 <= n; k += 8) {  // eight independent LDS reads per round
+      uint2 ed[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ed[q] = s_w[k + q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        ld += (ed[q].x == u || ed[q].y == u) ? 1u : 0u;
+        rd += (ed[q].x == v || ed[q].y == v) ? 1u : 0u;
+      }
+    }
+    for (; k < n; ++k) {
+      const uint2 ed = s_w[k];
+      ld += (ed.x == u || ed.y == u) ? 1u : 0u;
+      rd += (ed.x == v || ed.y == v) ? 1u : 0u;
+    }
+  }
+  const uint64_t cplus = (uint64_t)ld + rd;
+  uint32_t p2 = kNone;
+  bool pick = false;  // a new f2 is taken: find the edge with k later
+  uint32_t src = 0, kk = 0;  // edges on src
+  if (live && cplus != 0) {
+    const uint64_t y = bounded(kb, 2, c + cplus);
+    if (y >= c) {
+      const uint64_t phi = y - c;
+      src = phi < ld ? u : v;
+      kk = (uint32_t)(phi < ld ? phi : phi - ld);
+      pick = true;
+    }
+    const uint64_t tot = c + cplus;
+    if (tot > kChiMax) {
+      atomicOr(a.err, kErrOverflow);
+      c = kChiMax;
+    } else {
+      c = tot;
+    }
+  }
+  if (__syncthreads_or(pick)) {
+    uint32_t seen = 0;
+    for (uint32_t t = ntile; t-- > 0;) {
+      load_tile(t);
+      if (!pick || p2 != kNone) continue;
+      const uint32_t j0 = t * kNaiveTile, n = min(kNaiveTile, a.w - j0);
+      uint32_t k = n;
+      for (; k >= 8; k -= 8) {  // edges k-8 .. k-1, eight reads per round
+        uint32_t hit = 0;  // bit q: edge k-8+q is on src
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint2 ed = s_w[k - 8 + q];
+          hit |= (ed.x == src || ed.y == src) ? (1u << q) : 0u;
+        }
+        const uint32_t cnt = __popc(hit);
+        if (seen + cnt <= kk) {
+          seen += cnt;
+          continue;
+        }
+        // the (kk - seen)-th set bit counted from the top
+        uint32_t need = kk - seen;
+        for (int q = 7; q >= 0; --q) {
+          if (!((hit >> q) & 1u)) continue;
+          if (need == 0) {
+            p2 = j0 + k - 8 + q;
+            break;
+          }
+          --need;
+        }
+        break;
+      }
+      if (p2 == kNone) {
+        for (; k-- > 0;) {
+          const uint2 ed = s_w[k];
+          if (ed.x != src && ed.y != src) continue;
+          if (seen == kk) {
+            p2 = j0 + k;
+            break;
+          }
+          ++seen;
+        }
+      }
+    }
+    if (pick) {
+      if (p2 == kNone) {  // cannot happen: kk < the count just taken
+        atomicOr(a.err, kErrStall);
+        pick = false;
+      } else {
+        const uint2 ed = W[p2];
+        r2 = canon(ed.x, ed.y);
+        closed = false;
+      }
+    }
+  }
+
+  // Step 3: the latest occurrence of the closing edge decides
+  uint64_t q = kEmpty;
+  if (live && r2 != kEmpty && !closed) q = closing(r1, r2);
+  if (__syncthreads_or(q != kEmpty)) {
+    bool found = false;
+    for (uint32_t t = ntile; t-- > 0;) {
+      load_tile(t);
+      if (q == kEmpty || found) continue;
+      const uint32_t j0 = t * kNaiveTile, n = min(kNaiveTile, a.w - j0);
+      uint32_t k = n;
+      for (; k >= 8 && !found; k -= 8) {
+        uint32_t hit = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const uint2 ed = s_w[k - 8 + b];
+          hit |= canon(ed.x, ed.y) == q ? (1u << b) : 0u;
+        }
+        if (hit) {  // the latest of them
+          const uint32_t jl = j0 + k - 8 + (31u - __clz(hit));
+          closed = p2 == kNone || jl > p2;
+          found = true;
+        }
+      }
+      for (; k-- > 0 && !found;) {
+        const uint2 ed = s_w[k];
+        if (canon(ed.x, ed.y) != q) continue;
+        closed = p2 == kNone || j0 + k > p2;
+        found = true;
+      }
+    }
+  }
+  if (!live) return;
+  a.r1[e] = r1;
+  a.r2[e] = r2;
+  a.cc[e] = (uint32_t)c | (closed ? kClosed : 0u);
+}
+
+hipError_t launch_naive(const NaiveArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_naive, dim3((a.r + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // estimate and small utilities
 // ---------------------------------------------------------------------------
 // group of local estimator i of n: with bank offsets, its bank; otherwise

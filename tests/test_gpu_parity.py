@@ -575,3 +575,49 @@ def test_multi_mom_and_arguments(tc):
         with pytest.raises(tc.TcError) as ei:
             tc.tc_multi_estimate_mom(mb.h, 0, bad)
         assert ei.value.code == tc.TC_EINVAL
+
+
+# -- the per-estimator (naive) form: an independent path to the same state ---------
+
+@pytest.mark.parametrize("n,m,r,w", [(30, 120, 7, 2), (60, 500, 100, 7), (200, 3000, 1000, 4096),
+                                     (1000, 9000, 257, 2049), (2000, 20000, 4096, 2048)])
+def test_naive_equals_oracle(tc, n, m, r, w):
+    E = np_edges(inputs.gnm(n, m, seed=n + m))
+    dev = to_dev(E)
+    g = tc.Bank(r, r + w)
+    o = O.Bank(r, r + w)
+    for k, j in enumerate(range(0, len(E), w)):
+        g.process_naive(dev[j:j + w])
+        assert o.process(E[j:j + w], "def") == O.OK
+        assert_same(g.state(), o.state(), f"batch {k}")
+    assert tc.tc_estimate_ex(g.h)[0] == o.sum()
+
+
+def test_naive_and_bulk_interleave(tc):
+    E = np_edges(inputs.rmat(13, 30000, seed=17))
+    dev = to_dev(E)
+    w, r = 3000, 5000
+    banks = [tc.Bank(r, 44) for _ in range(3)]  # naive, alternating, bulk
+    for k, j in enumerate(range(0, len(E), w)):
+        c = dev[j:j + w]
+        banks[0].process_naive(c)
+        (banks[1].process_naive if k % 2 else banks[1].process)(c)
+        banks[2].process(c)
+        ref = banks[2].state()
+        assert_same(banks[0].state(), ref, f"naive, batch {k}")
+        assert_same(banks[1].state(), ref, f"alternating, batch {k}")
+
+
+def test_naive_boundary(tc):
+    g = tc.Bank(50, 1)
+    E = to_dev(np_edges(inputs.gnm(40, 200, seed=3)))
+    g.process_naive(E[:0])
+    assert g.m == 0 and g.batch == 0
+    g.process_naive(E[:100])
+    assert g.m == 100 and g.batch == 1
+    bad = np_edges(inputs.gnm(40, 50, seed=4)).copy()
+    bad[3] = (9, 9)
+    g.process_naive(to_dev(bad))
+    with pytest.raises(tc.TcError) as ei:
+        g.sync()
+    assert ei.value.code == tc.TC_EBADEDGE
