@@ -294,6 +294,26 @@ def naive_vs_bulk(tc, inputs, shapes=((4096, 2048), (4096, 16384), (65536, 16384
     return out
 
 
+def parse_rate(tc, inputs, G, reps=3):
+    """The stream as a text edge list in device memory, parsed on the device
+    (tc_parse_edges, blocking, including its scratch allocation)."""
+    import torch
+    txt = inputs.edge_list_text(G, header="# synthetic R-MAT edge list\n")
+    out = tc.tc_parse_edges(txt)
+    same = bool(torch.equal(out, G))
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tc.tc_parse_edges(txt)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return {"bytes": int(txt.numel()), "ms": round(best * 1e3, 3),
+            "GB_per_s": round(txt.numel() / best / 1e9, 2),
+            "edges_per_s": G.shape[0] / best, "round_trip_identical": same}
+
+
 KERNEL_SRC = os.path.join(ROOT, "paper_1308_2166_amd", "csrc", "tc_kernels.hip")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_rmat20.json")
 
@@ -669,6 +689,8 @@ def main():
     if not args.no_host_fed:
         log("[bench] host-fed stream")
         out["host_fed"] = host_fed(tc, G, r, seed, w, nv)
+        log("[bench] text edge list parsed on the device")
+        out["text_parse"] = parse_rate(tc, inputs, G)
 
     if not args.no_batched:
         out["batched"] = batched_comparison(tc, inputs, nstreams=args.streams)

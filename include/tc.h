@@ -222,6 +222,20 @@ int tc_multi_sync(tc_multi *s);
 uint32_t tc_multi_num_banks(const tc_multi *s);
 void tc_multi_destroy(tc_multi *s);
 
+/* ---- input: text edge lists ------------------------------------------------
+ * Parse a text edge list held in DEVICE memory (the graphs the paper streams
+ * are text edge lists, read by its I/O routine: Sec. 5, Table 2): one edge
+ * per line, two unsigned decimal vertex ids separated by any non-digit
+ * bytes; lines starting with '#' or '%' are comments; '\r\n' and a missing
+ * final newline are accepted.  Writes the edges in file order to the DEVICE
+ * array edges (uint32_t[2 * max_edges], caller-owned) and their number to
+ * *nedges (HOST).  Blocking (it returns the count).  TC_EINVAL for NULL
+ * pointers, an odd number of ids, an id above 2^32 - 1, a line longer than
+ * 4096 bytes, or more than max_edges edges (nothing useful is written
+ * then); TC_ENOMEM if its scratch cannot be allocated. */
+int tc_parse_edges(const char *text, uint64_t nbytes, uint32_t *edges,
+                   uint64_t max_edges, uint64_t *nedges, void *stream);
+
 /* ---- diagnostics: per-kernel device time --------------------------------
  * mask: bit k (k < tc_num_kernels()) times kernel k; TC_TIME_ALL times every
  * kernel; 0 turns timing off.  While on, every step records a HIP event

@@ -60,6 +60,7 @@ def lib():
         "tc_process_batch": ([vp, vp, u32, vp], i32),
         "tc_process_stream": ([vp, vp, u64, u32, vp], i32),
         "tc_process_batch_naive": ([vp, vp, u32, vp], i32),
+        "tc_parse_edges": ([vp, u64, vp, u64, P64, vp], i32),
         "tc_set_vertex_bound": ([vp, u64], i32),
         "tc_estimate_mom": ([vp, u32, ctypes.POINTER(ctypes.c_double), P64], i32),
         "tc_multi_estimate_mom": ([vp, u32, u32, ctypes.POINTER(ctypes.c_double), P64], i32),
@@ -112,7 +113,7 @@ EXPORTS = ("tc_create", "tc_process_batch", "tc_process_stream", "tc_estimate", 
            "tc_reserve", "tc_multi_reserve", "tc_reset", "tc_multi_reset",
            "tc_multi_graph_reserve", "tc_multi_assign", "tc_set_vertex_bound",
            "tc_multi_set_vertex_bound", "tc_estimate_mom", "tc_multi_estimate_mom",
-           "tc_estimators_needed", "tc_process_batch_naive")
+           "tc_estimators_needed", "tc_process_batch_naive", "tc_parse_edges")
 
 
 def _check(rc: int):
@@ -159,6 +160,21 @@ def tc_process_batch_naive(state: int, edges, w: int | None = None, stream=None)
     ptr, n = _edge_ptr(edges) if edges is not None else (0, 0)
     _check(lib().tc_process_batch_naive(state, ptr or None, n if w is None else w,
                                         _stream_handle(stream)))
+
+
+def tc_parse_edges(text: torch.Tensor, max_edges: int | None = None, stream=None):
+    """Parse a text edge list held in a uint8 CUDA tensor; returns an
+    (m, 2) int32 CUDA tensor of the edges (uint32 ids as bit patterns)."""
+    if not isinstance(text, torch.Tensor) or not text.is_cuda or text.dtype != torch.uint8:
+        raise TypeError("text must be a uint8 CUDA tensor")
+    n = text.numel()
+    if max_edges is None:
+        max_edges = n // 4 + 1  # an edge takes at least four bytes ("1 2\n")
+    out = torch.empty((max(max_edges, 1), 2), dtype=torch.int32, device=text.device)
+    cnt = ctypes.c_uint64()
+    _check(lib().tc_parse_edges(text.data_ptr() if n else None, n, out.data_ptr(), max_edges,
+                                ctypes.byref(cnt), _stream_handle(stream)))
+    return out[:cnt.value]
 
 
 def tc_process_stream(state: int, edges, w: int, stream=None) -> None:

@@ -677,6 +677,11 @@ struct Engine {
 
 }  // namespace
 
+namespace tc {
+// error text for the entry points defined in other files
+int report(int code, const char* msg) { return fail(code, msg); }
+}  // namespace tc
+
 struct tc_multi {
   Engine e;
 };

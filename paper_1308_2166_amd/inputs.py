@@ -281,3 +281,40 @@ def many_streams(nstreams: int = 256, seed: int = 404, device="cpu",
             r = max(16, int(r * size_scale))
         out.append({"edges": e, "r": r, "seed": gseed ^ 0x5A5A, "kind": kind, "n": nv})
     return out
+
+
+def edge_list_text(edges: torch.Tensor, sep: str = "\t", header: str = "") -> torch.Tensor:
+    """A stream as a text edge list ("a<sep>b\\n" per edge, variable-width
+    decimal ids, optional comment header) in a uint8 tensor on the edges'
+    device: the input form of the text parser."""
+    dev = edges.device
+    e = edges.to(torch.int64) & 0xFFFFFFFF
+    m = e.shape[0]
+    if m == 0:
+        return torch.tensor(list(header.encode()), dtype=torch.uint8, device=dev)
+    pw = torch.tensor([10 ** k for k in range(11)], dtype=torch.int64, device=dev)
+
+    def ndig(v):
+        return (v.unsqueeze(1) >= pw[1:].unsqueeze(0)).sum(1) + 1
+
+    na, nb = ndig(e[:, 0]), ndig(e[:, 1])
+    s = sep.encode()
+    length = na + nb + len(s) + 1
+    hb = header.encode()
+    off = torch.cumsum(length, 0) - length + len(hb)
+    out = torch.empty(int(length.sum()) + len(hb), dtype=torch.uint8, device=dev)
+    if hb:
+        out[:len(hb)] = torch.tensor(list(hb), dtype=torch.uint8, device=dev)
+
+    def put(v, nd, base):
+        for k in range(10):
+            live = nd > k
+            d = (v // pw[(nd - 1 - k).clamp(min=0)]) % 10
+            out[(base + k)[live]] = (48 + d[live]).to(torch.uint8)
+
+    put(e[:, 0], na, off)
+    for i, ch in enumerate(s):
+        out[off + na + i] = ch
+    put(e[:, 1], nb, off + na + len(s))
+    out[off + length - 1] = 10
+    return out

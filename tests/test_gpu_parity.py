@@ -621,3 +621,68 @@ def test_naive_boundary(tc):
     with pytest.raises(tc.TcError) as ei:
         g.sync()
     assert ei.value.code == tc.TC_EBADEDGE
+
+
+# -- text edge lists parsed on the device -------------------------------------------
+
+def _ref_parse(text: bytes):
+    """Plain reference: non-comment lines, digit runs, pairs."""
+    toks = []
+    for line in text.split(b"\n"):
+        if line[:1] in (b"#", b"%"):
+            continue
+        cur = None
+        for ch in line + b" ":
+            if 48 <= ch <= 57:
+                cur = (cur or 0) * 10 + ch - 48
+            elif cur is not None:
+                toks.append(cur)
+                cur = None
+    assert len(toks) % 2 == 0
+    return np.array(toks, dtype=np.uint64).reshape(-1, 2)
+
+
+def _dev_bytes(b: bytes) -> torch.Tensor:
+    return torch.tensor(list(b), dtype=torch.uint8).cuda()
+
+
+def test_parse_handmade_texts(tc):
+    texts = [
+        b"1 2\n3 4\n",
+        b"# SNAP header\n# Nodes: 5\n1\t2\r\n3\t4\r\n\n5 6",
+        b"% matrix market style\n7,8\n  9   10  \n4294967295 0\n",
+        b"",
+        b"#only a comment",
+        b"12 34\n#c 99 98\n56\t78\n" * 1000,
+    ]
+    # a long line (under the 4096-byte limit) and tokens across 256-byte thread spans
+    texts.append(b" " * 3000 + b"11 22\n" + b"1" * 9 + b" " + b"2" * 9 + b"\n")
+    texts.append(b"".join(b"%d %d\n" % (i, i * 7 + 1) for i in range(70000)))
+    for t in texts:
+        got = tc.tc_parse_edges(_dev_bytes(t)) if t else tc.tc_parse_edges(
+            torch.empty(0, dtype=torch.uint8, device="cuda"))
+        want = _ref_parse(t)
+        assert got.shape[0] == want.shape[0]
+        assert np.array_equal(got.cpu().numpy().view(np.uint32).astype(np.uint64), want)
+
+
+def test_parse_round_trip_and_process(tc):
+    G = inputs.rmat(14, 60000, seed=31, device="cuda")
+    for sep in ("\t", " ", ", "):
+        txt = inputs.edge_list_text(G, sep=sep, header="# R-MAT scale 14\n% second comment\n")
+        got = tc.tc_parse_edges(txt)
+        assert torch.equal(got, G)
+    # the parsed stream through the step, against the oracle on the original
+    g = tc.Bank(20000, 5)
+    g.process_stream(got, 9001)
+    o = O.run_stream(np_edges(G), 20000, 5, 9001)
+    assert_same(g.state(), o.state(), "parsed stream")
+
+
+def test_parse_errors(tc):
+    for bad in (b"1 2 3\n", b"4294967296 1\n", b"1 " + b" " * 5000 + b"2\n"):
+        with pytest.raises(tc.TcError) as ei:
+            tc.tc_parse_edges(_dev_bytes(bad))
+        assert ei.value.code == tc.TC_EINVAL
+    with pytest.raises(tc.TcError):
+        tc.tc_parse_edges(_dev_bytes(b"1 2\n3 4\n5 6\n"), max_edges=2)
