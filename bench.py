@@ -84,6 +84,50 @@ def cpu_baseline(E_host, r, seed, w, budget_s=12.0):
     return b, nb, dt
 
 
+def oracle_worker(path, r, seed, w, nb):
+    """Child-process mode (no GPU, no torch): the oracle on the first nb
+    batches saved at `path`; prints the seconds it took."""
+    import numpy as np
+    import oracle as O
+    E = np.load(path)
+    b = O.Bank(r, seed)
+    t0 = time.perf_counter()
+    for k in range(nb):
+        if b.process(E[k * w:(k + 1) * w]) != O.OK:
+            raise SystemExit("oracle failed")
+    print(json.dumps({"seconds": time.perf_counter() - t0}), flush=True)
+
+
+def cpu_baseline_all_cores(E_host, r, seed, w, nb, workers):
+    """The same oracle, unchanged, on every host core: the bank is split
+    into `workers` independent banks of r/workers estimators (own seeds),
+    each advanced over the same nb batches by its own process; the rate is
+    r * nb * w over the slowest worker's time."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "batches.npy")
+        np.save(path, E_host[:nb * w])
+        rw = max(1, r // workers)
+        procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker",
+                                   path, str(rw), str(seed + 1 + k), str(w), str(nb)],
+                                  stdout=subprocess.PIPE, text=True)
+                 for k in range(workers)]
+        secs = []
+        for p in procs:
+            o, _ = p.communicate()
+            if p.returncode != 0:
+                raise RuntimeError("oracle worker failed")
+            secs.append(json.loads(o.strip().splitlines()[-1])["seconds"])
+    worst = max(secs)
+    return {"value": rw * workers * nb * w / worst, "unit": "estimator-edge updates/s",
+            "cores": workers, "kind": "oracle",
+            "sample": f"first {nb} batch(es) of the same stream, {workers} processes of "
+                      f"r/{workers} = {rw} estimators each (own seeds), paper-steps oracle "
+                      f"variant, slowest process {worst:.1f} s"}
+
+
 def batched_comparison(tc, inputs, nstreams=256, ks=(4, 8, 16), replays=3):
     """Plain (one bank per stream, one launch set per chunk) against batched
     (every stream's chunk in one launch set per step) and graph replay of the
@@ -495,7 +539,13 @@ def main():
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="summarize rocprofv3 CSV dirs of this benchmark into profiles/")
     ap.add_argument("--summary-command", default="")
+    ap.add_argument("--oracle-worker", nargs=5, metavar=("NPY", "R", "SEED", "W", "NB"),
+                    help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_worker:
+        path, rr, sd, ww, nbb = args.oracle_worker
+        oracle_worker(path, int(rr), int(sd), int(ww), int(nbb))
+        return
     if args.summarize:
         summarize(*args.summarize, calib_mib=args.calib_copy_mib,
                   out_dir=os.path.join(ROOT, "profiles"), command=args.summary_command,
@@ -707,6 +757,9 @@ def main():
             "cores": 1, "kind": "oracle",
             "sample": f"first {nbo} batch(es) of the same stream (r={r}, w={w}), "
                       f"paper-steps oracle variant, single thread, {odt:.1f} s"}
+        workers = max(1, min(16, os.cpu_count() or 1))
+        log(f"[bench] CPU oracle on {workers} cores")
+        out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(E_host, r, seed, w, nbo, workers)
         # the same batches on the GPU must give the oracle's state
         chk = new_bank()
         chk.process_stream(G[:min(m, nbo * w)], w, stream)
