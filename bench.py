@@ -60,7 +60,7 @@ def alg_bytes(kernel: str, w: int, r: int, nontrivial: list) -> float:
     if kernel == "k_est":
         return r * (20.0 + 4.0 + 12.0 + 12.0)
     if kernel == "k_post":
-        return r * 12.0
+        return r * 8.0
     if kernel == "k_probe":
         return 8.0 * w
     return 0.0

@@ -88,7 +88,7 @@ uint32_t launched_kernels(uint32_t npass) {
 // phases touch exists twice and step s uses copy s & 1.
 struct ParityScratch {
   SegWork* work = nullptr;    // per-segment histograms, counters, modes
-  QRec* qt = nullptr;         // Step-3 query tables
+  uint32_t* qt = nullptr;     // Step-3 query tables (owners)
   uint8_t* qfp = nullptr;
   SegDesc* segs = nullptr;    // device copy of the step's descriptors
 };
@@ -302,7 +302,7 @@ struct Engine {
           hipMemsetAsync(need, 0, cap_need, st);
     for (ParityScratch& p : par)
       bad = bad || hipMemsetAsync(p.work, 0, sizeof(SegWork) * cap_segs, st) ||
-            hipMemsetAsync(p.qt, 0xFF, sizeof(QRec) * cap_qt, st) ||
+            hipMemsetAsync(p.qt, 0xFF, sizeof(uint32_t) * cap_qt, st) ||
             hipMemsetAsync(p.qfp, 0, cap_qt, st);
     if (bad || hipStreamSynchronize(st))
       return fail(TC_EHIP, "clearing step scratch failed");

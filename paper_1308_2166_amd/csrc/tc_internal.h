@@ -96,17 +96,14 @@ struct DirSlot {
   uint32_t end;
 };
 
-// Step-3 query table (one region per segment, linear probing): slot s is
-// the record qt[s] -- estimator `own` (kNone = free) waits for closing edge
-// `key` at a batch position >= `lim` -- plus qfp[s], a nonzero 8-bit
-// fingerprint of the key's hash (0 = free), which is what a probe scans.
-// Every waiting estimator owns one slot (equal keys share a probe cluster).
-// The records and fingerprints are reset at the start of every step.
-struct QRec {
-  uint64_t key;
-  uint32_t lim;
-  uint32_t own;
-};
+// Step-3 query table (one region per segment, linear probing): slot s
+// holds qt[s], the estimator that owns it (kNone = free), and qfp[s], a
+// nonzero 8-bit fingerprint of the hash of the closing edge that estimator
+// waits for (0 = free), which is what a probe scans.  The edge itself and
+// the first batch position that closes it are the owner's qq and qthr
+// entries.  Every waiting estimator owns one slot (equal edges share a
+// probe cluster).  Owners and fingerprints are reset at the start of every
+// step.
 
 struct StepArgs {
   const SegDesc* segs;    // device copy of all segment descriptors
@@ -130,7 +127,7 @@ struct StepArgs {
   uint32_t* csum;         // per radix chunk: digit sums [chunk][pass][digit]
   uint32_t nchunk;        // total radix chunks over segments
   DirSlot* dir;
-  QRec* qt;               // query table records
+  uint32_t* qt;           // query table: owner per slot
   uint8_t* qfp;           // query table: key fingerprint per slot
   uint64_t qt_slots;      // query-table slots over all segments
   uint32_t* j1;           // per estimator: Step-1 replacement (see kSideV)

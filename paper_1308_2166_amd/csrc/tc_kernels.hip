@@ -187,8 +187,8 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
   {
     // (slot counts are multiples of 1024, so whole uint4s cover them)
     uint4* o4 = reinterpret_cast<uint4*>(a.qt);
-    const uint4 none = make_uint4(0, 0, 0, kNone);  // own = kNone
-    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.qt_slots;
+    const uint4 none = make_uint4(kNone, kNone, kNone, kNone);
+    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.qt_slots / 4;
          t += (uint64_t)a.nhblk * kBlock)
       o4[t] = none;
     uint4* f4 = reinterpret_cast<uint4*>(a.qfp);
@@ -803,7 +803,7 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   // stores one value lands whole); k_post checks which estimator won and
   // moves the others on, so the common case needs no atomic
   if (q != kEmpty)
-    a.qt[S.qt_off + q_home(mix64(q), (1u << S.qt_log2) - 1u)].own = (uint32_t)e;
+    a.qt[S.qt_off + q_home(mix64(q), (1u << S.qt_log2) - 1u)] = (uint32_t)e;
   a.qthr[e] = (p2 == kNone) ? 0u : p2 + 1;  // closes at a position >= this
   a.r2[e] = r2;
   a.cc[e] = (uint32_t)c | (closed ? kClosed : 0u);
@@ -813,8 +813,8 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
 // k_post: every waiting estimator owns a slot of its segment's query table:
 // the home slot if its claim there stood, else the first free slot after
 // it, taken with a CAS (a slot once owned stays owned, so the slots
-// between a key's home and its slot are all occupied); then the slot's key,
-// limit and fingerprint
+// between a key's home and its slot are all occupied); then the slot's
+// fingerprint
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_post(StepArgs a) {
   const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -827,9 +827,9 @@ __global__ __launch_bounds__(kBlock) void k_post(StepArgs a) {
   if (q == kEmpty) return;
   const uint32_t mask = (1u << S.qt_log2) - 1u;
   const uint64_t hq = mix64(q);
-  QRec* qt = a.qt + S.qt_off;
+  uint32_t* qt = a.qt + S.qt_off;
   uint32_t s = q_home(hq, mask);
-  if (qt[s].own != (uint32_t)e) {
+  if (qt[s] != (uint32_t)e) {
     uint32_t probe = 0;
     do {
       s = (s + 1) & mask;
@@ -837,15 +837,8 @@ __global__ __launch_bounds__(kBlock) void k_post(StepArgs a) {
         atomicOr(a.err, kErrProbe);
         return;
       }
-    } while (atomicCAS(&qt[s].own, kNone, (uint32_t)e) != kNone);
+    } while (atomicCAS(&qt[s], kNone, (uint32_t)e) != kNone);
   }
-  // one 16-byte store (own is rewritten with its own value: no other
-  // thread touches an owned slot)
-  QRec rec;
-  rec.key = q;
-  rec.lim = a.qthr[e];
-  rec.own = (uint32_t)e;
-  qt[s] = rec;
   a.qfp[S.qt_off + s] = q_fp(hq);
 }
 
@@ -868,7 +861,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
     const uint2* W = reinterpret_cast<const uint2*>(S.edges);
     const uint32_t mask = (1u << S.qt_log2) - 1u;
     const uint8_t* fp = a.qfp + S.qt_off;
-    const QRec* qt = a.qt + S.qt_off;
+    const uint32_t* qt = a.qt + S.qt_off;
     constexpr uint64_t k01 = 0x0101010101010101ull, k80 = 0x8080808080808080ull;
     for (int k = 0; k < kProbeEdges; ++k) {
       const uint32_t j = ebase + k * kBlock + tid;
@@ -880,7 +873,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
       // the fingerprints (one byte per slot, a few MB, stay in L2) rule out
       // nearly every edge; they are read eight at a time (aligned words):
       // the scan ends at the first free slot (zero byte), and a byte equal
-      // to the edge's fingerprint before it is checked against the key
+      // to the edge's fingerprint before it is checked against the edge
+      // its owner waits for
       uint32_t sl = q_home(hq, mask);
       for (uint32_t probe = 0; probe <= mask + 8; probe += 8) {
         const uint32_t b8 = sl & ~7u;
@@ -893,8 +887,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
         if (z) mt &= (z & (~z + 1)) - 1;          // only ever rechecked)
         while (mt) {
           const uint32_t at = b8 + ((uint32_t)__ffsll((long long)mt) - 1u) / 8u;
-          const QRec rec = qt[at];
-          if (rec.key == q && j >= rec.lim) atomicOr(&a.cc[rec.own], kClosed);
+          const uint32_t own = qt[at];
+          if (a.qq[own] == q && j >= a.qthr[own]) atomicOr(&a.cc[own], kClosed);
           mt &= mt - 1;
         }
         if (z) break;
