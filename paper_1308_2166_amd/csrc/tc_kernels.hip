@@ -658,7 +658,10 @@ __device__ __forceinline__ uint2 dir_find(const DirSlot* dir, uint32_t log2,
   return make_uint2(0, 0);
 }
 
+// The block's tile of sorted arcs (plus one arc on each side) is loaded up
+// front into LDS; each arc then finds its neighbours there.
 __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
+  __shared__ uint64_t s_arc[kTile + 2];  // s_arc[1 + t] = arc base + t
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
   const uint32_t gtile = blockIdx.x;
@@ -671,18 +674,31 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
   const uint64_t* arc = a.arcs[wk->final_buf] + S.arc_off;
   const uint32_t n = 2u * S.w;
   const uint32_t base = (gtile - S.tile_off) * kTile;
-  const uint32_t end = min(base + (uint32_t)kTile, n);
+  const uint32_t nv = min((uint32_t)kTile, n - base);
+  {
+    // clamped loads past the ragged end are never used as arcs
+    uint64_t v[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) v[k] = arc[min(base + k * kBlock + tid, n - 1)];
+    if (tid == 0) s_arc[0] = arc[base > 0 ? base - 1 : 0];
+    if (tid == 1) s_arc[kTile + 1] = arc[min(base + kTile, n - 1)];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) s_arc[1 + k * kBlock + tid] = v[k];
+  }
+  __syncthreads();
   DirSlot* dir = a.dir + S.dir_off;
   const bool dense = wk->dense != 0;
   const uint32_t mask = (1u << S.dir_log2) - 1u;
   const uint32_t tag = uniform(*a.tagp);
   uint32_t* inv = a.inv + S.arc_off;
-  for (uint32_t i = base + tid; i < end; i += kBlock) {
-    const uint32_t id = (uint32_t)arc[i];
+  for (uint32_t t = tid; t < nv; t += kBlock) {
+    const uint32_t i = base + t;
+    const uint64_t e = s_arc[1 + t];
+    const uint32_t id = (uint32_t)e;
     if (id & kNeedFlag) inv[id & kIdMask] = i;
-    const uint32_t x = (uint32_t)(arc[i] >> 32);
-    const bool head = i == 0 || (uint32_t)(arc[i - 1] >> 32) != x;
-    const bool tail = i + 1 == n || (uint32_t)(arc[i + 1] >> 32) != x;
+    const uint32_t x = (uint32_t)(e >> 32);
+    const bool head = i == 0 || (uint32_t)(s_arc[t] >> 32) != x;
+    const bool tail = i + 1 == n || (uint32_t)(s_arc[t + 2] >> 32) != x;
     if (!head && !tail) continue;
     if (dense) {
       if (x > mask) continue;  // cannot happen: x <= max id < 2^dir_log2
