@@ -359,7 +359,15 @@ def parse_rate(tc, inputs, G, reps=3):
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1308_2166_amd", "csrc", "tc_kernels.hip")
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_rmat20.json")
+def traffic_json(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
+PROFILE_TITLES = {
+    "rmat20": "R-MAT scale 20 (r=2^20, w=2^22)",
+    "rmat24": "R-MAT scale 24 (r=2^22, w=2^24)",
+    "gnm-2k": "G(2000, 20000) (r=4096, w=2048)",
+}
 
 
 def kernel_source_hash() -> str:
@@ -376,7 +384,8 @@ def _short(name: str) -> str:
     return n.strip().replace("k_scat4<", "k_scat<")
 
 
-def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command, timed=0):
+def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command, timed=0,
+              workload="rmat20"):
     """Turn rocprofv3 CSV output of this benchmark into the committed
     summaries: per-kernel average duration (kernel trace) and per-kernel HBM
     traffic from FETCH_SIZE / WRITE_SIZE, each scaled by what the counter
@@ -399,16 +408,20 @@ def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command, time
     for r in rows(trace_dir, "*kernel_trace.csv"):
         durs.setdefault(_short(r["Kernel_Name"]), []).append(
             (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    ctr = {}
+    ctr, first_copy = {}, {}
     for d, name in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
         for r in rows(d, "*counter_collection.csv"):
             if r["Counter_Name"] == name:
                 ctr.setdefault((_short(r["Kernel_Name"]), name), []).append(
                     float(r["Counter_Value"]))
-    copy = [k for (k, n) in ctr if "copyBuffer" in k and n == "FETCH_SIZE"]
+                # the calibration copy is the run's first copy dispatch
+                if "copyBuffer" in r["Kernel_Name"]:
+                    did = int(r["Dispatch_Id"])
+                    if name not in first_copy or did < first_copy[name][0]:
+                        first_copy[name] = (did, float(r["Counter_Value"]))
     calib_bytes = calib_mib * 2**20
-    fcopy = max(ctr[(copy[0], "FETCH_SIZE")]) if copy else None
-    wcopy = max(ctr[(copy[0], "WRITE_SIZE")]) if copy else None
+    fcopy = first_copy["FETCH_SIZE"][1] if "FETCH_SIZE" in first_copy else None
+    wcopy = first_copy["WRITE_SIZE"][1] if "WRITE_SIZE" in first_copy else None
     ff = calib_bytes / (fcopy * 1024) if fcopy else None
     fw = calib_bytes / (wcopy * 1024) if wcopy else None
     kernels = [k for k in durs if k.startswith("k_")]
@@ -436,10 +449,10 @@ def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command, time
     rec = {"kernel_source_sha256_16": kernel_source_hash(), "calib_copy_mib": calib_mib,
            "fetch_factor": ff, "write_factor": fw, "per_kernel": per,
            "command": command}
-    with open(os.path.join(out_dir, "traffic_rmat20.json"), "w") as f:
+    with open(os.path.join(out_dir, f"traffic_{workload}.json"), "w") as f:
         json.dump(rec, f, indent=1)
-    with open(os.path.join(out_dir, "step_kernels_rmat20.md"), "w") as f:
-        f.write("# Step kernels, R-MAT scale 20 (r=2^20, w=2^22), plain form\n\n")
+    with open(os.path.join(out_dir, f"step_kernels_{workload}.md"), "w") as f:
+        f.write(f"# Step kernels, {PROFILE_TITLES[workload]}, plain form\n\n")
         f.write("Commands (run from the repository root on one MI355X):\n\n```\n"
                 + command + "\n```\n\n")
         f.write(f"Calibration: a {calib_mib} MiB device copy (`__amd_rocclr_copyBuffer`) "
@@ -549,7 +562,7 @@ def main():
     if args.summarize:
         summarize(*args.summarize, calib_mib=args.calib_copy_mib,
                   out_dir=os.path.join(ROOT, "profiles"), command=args.summary_command,
-                  timed=args.steps)
+                  timed=args.steps, workload=args.workload)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
@@ -691,10 +704,9 @@ def main():
                     "alg_bytes_per_launch": ab,
                     "avg_launch_us_alone": round(per_kernel[dom] / timed * 1e3, 2)}
         try:
-            with open(TRAFFIC_JSON) as f:
+            with open(traffic_json(args.workload)) as f:
                 rec = json.load(f)
-            if (args.workload == "rmat20"
-                    and rec["kernel_source_sha256_16"] == kernel_source_hash()
+            if (rec["kernel_source_sha256_16"] == kernel_source_hash()
                     and rec["per_kernel"].get(dom, {}).get("hbm_bytes")):
                 roofline["traffic"] = rec["per_kernel"][dom]["hbm_bytes"]
                 # the whole step: measured HBM bytes of every kernel it
