@@ -112,7 +112,7 @@ class Bank:
 
     def __del__(self):
         p = getattr(self, "_p", None)
-        if p:
+        if p and lib is not None:  # (module globals may be gone at exit)
             lib().orc_destroy(p)
             self._p = None
 

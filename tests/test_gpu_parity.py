@@ -136,6 +136,60 @@ def test_batch_of_one_then_large(tc):
         assert_same(g.state(), o.state(), f"[{a},{b})")
 
 
+def _random_case(k: int):
+    """Configuration k of a seeded sweep: graph family and size, id layout
+    (compact, strided, or spread over 32 bits so the directory is hashed),
+    bank size, batch size (ragged tails), and whether a vertex bound is
+    declared.  Drawn from numpy's seeded generator; nothing here depends on
+    the device."""
+    rng = np.random.default_rng(1000 + k)
+    fam = k % 3
+    if fam == 0:
+        n = int(rng.integers(3, 3000))
+        m = int(min(rng.integers(1, 25000), n * (n - 1) // 2))
+        E = np_edges(inputs.gnm(n, m, seed=k + 1))
+    elif fam == 1:
+        scale = int(rng.integers(6, 14))
+        n = 1 << scale
+        m = int(min(rng.integers(1, 30000), n * 4))
+        E = np_edges(inputs.rmat(scale, m, seed=k + 1))
+    else:
+        n = int(rng.integers(50, 4000))
+        m = int(rng.integers(n, 8 * n))
+        E = np_edges(inputs.chung_lu(n, m, seed=k + 1))
+        n = int(E.max()) + 1
+    layout = int(rng.integers(0, 3))
+    bound = None
+    if layout == 1:  # strided ids: sparse, still below a declared bound
+        stride = int(rng.integers(2, 50))
+        E = (E.astype(np.uint64) * stride + int(rng.integers(0, stride))).astype(np.uint32)
+        bound = int(E.max()) + 1 + int(rng.integers(0, 1000))
+    elif layout == 2:  # spread over [0, 2^32)
+        E = ((E.astype(np.uint64) * 2654435761 + 12345) % (2**32 - 7)).astype(np.uint32)
+    elif rng.integers(0, 2):
+        bound = n
+    r = int(rng.integers(1, 6000))
+    w = int(rng.integers(1, max(2, len(E) // int(rng.integers(1, 9)) + 1)))
+    seed = int(rng.integers(0, 2**63))
+    return E, r, w, seed, bound, f"fam={fam} n={n} m={len(E)} layout={layout} r={r} w={w} bound={bound}"
+
+
+@pytest.mark.parametrize("k", range(24))
+def test_random_configurations(tc, k):
+    E, r, w, seed, bound, desc = _random_case(k)
+    say(f"  case {k}: {desc}")
+    dev = to_dev(E)
+    g, o = tc.Bank(r, seed), O.Bank(r, seed)
+    if bound is not None:
+        tc.tc_set_vertex_bound(g.h, bound)
+    for j in range(0, len(E), w):
+        g.process(dev[j:j + w])
+        assert o.process(E[j:j + w]) == O.OK
+    assert_same(g.state(), o.state(), desc)
+    S, m, _ = tc.tc_estimate_ex(g.h)
+    assert S == o.sum() and m == len(E)
+
+
 # -- boundary behaviour ------------------------------------------------------------
 
 def test_empty_batch_is_a_noop(tc):
