@@ -26,7 +26,7 @@ def libtc():
     return ctypes.CDLL(path)
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_main_entry_points():
     names = _declared()
     for n in ("tc_create", "tc_process_batch", "tc_estimate", "tc_read_state",
               "tc_destroy", "tc_multi_create", "tc_multi_process"):
