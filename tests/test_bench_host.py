@@ -25,3 +25,48 @@ def test_all_cores_oracle_baseline_runs_every_worker():
     assert res["cores"] == 2 and res["kind"] == "oracle"
     assert res["value"] > 0 and np.isfinite(res["value"])
     assert "r/2 = 2048" in res["sample"]
+
+
+def _write_csv(path, header, rows):
+    import csv
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        wr = csv.writer(f)
+        wr.writerow(header)
+        wr.writerows(rows)
+
+
+def test_summarize_calibrates_with_the_first_copy(tmp_path):
+    """The calibration copy is the run's first copy dispatch, even when a
+    later copy (the input stream) is larger; traffic per launch is each
+    counter times its calibration factor; the timed region is the last
+    `timed` launches."""
+    bench = _bench()
+    mib = 4
+    trace = ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    ctr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    copy = "__amd_rocclr_copyBuffer"
+    t_rows = [[1, copy, 0, 1000], [2, copy, 2000, 9000]]
+    f_rows = [[1, copy, "FETCH_SIZE", mib * 1024 / 2], [2, copy, "FETCH_SIZE", 99999.0]]
+    w_rows = [[1, copy, "WRITE_SIZE", mib * 1024], [2, copy, "WRITE_SIZE", 88888.0]]
+    durs = [10.0, 20.0, 30.0]  # us
+    for k, d in enumerate(durs):
+        t_rows.append([3 + k, "tc::k_est(tc::StepArgs)", 10000 * k, 10000 * k + int(d * 1000)])
+        f_rows.append([3 + k, "tc::k_est(tc::StepArgs)", "FETCH_SIZE", 100.0])
+        w_rows.append([3 + k, "tc::k_est(tc::StepArgs)", "WRITE_SIZE", 50.0])
+    _write_csv(str(tmp_path / "t" / "run_kernel_trace.csv"), trace, t_rows)
+    _write_csv(str(tmp_path / "f" / "run_counter_collection.csv"), ctr, f_rows)
+    _write_csv(str(tmp_path / "w" / "run_counter_collection.csv"), ctr, w_rows)
+    out = tmp_path / "out"
+    bench.summarize(str(tmp_path / "t"), str(tmp_path / "f"), str(tmp_path / "w"), mib,
+                    str(out), "cmd", timed=2, workload="rmat20")
+    import json
+    rec = json.load(open(out / "traffic_rmat20.json"))
+    assert rec["fetch_factor"] == pytest.approx(2.0)
+    assert rec["write_factor"] == pytest.approx(1.0)
+    k = rec["per_kernel"]["k_est"]
+    assert k["launches"] == 3
+    assert k["avg_us"] == pytest.approx(20.0)
+    assert k["avg_us_timed"] == pytest.approx(25.0)
+    assert k["hbm_bytes"] == pytest.approx(100.0 * 1024 * 2.0 + 50.0 * 1024 * 1.0)
+    assert "cmd" in (out / "step_kernels_rmat20.md").read_text()
