@@ -376,6 +376,11 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+STEP_ORDER = (["k_hist", "k_fold_step1", "k_scat<0>"]
+              + [f"{k}<{p}>" for p in range(1, 4) for k in ("k_cnt", "k_csum", "k_scat")]
+              + ["k_dir", "k_est", "k_post", "k_probe"])
+
+
 def _short(name: str) -> str:
     """Kernel name as tc_kernel_name gives it (the four-wave build of a
     radix pass, k_scat4<P>, is the launch k_scat<P>)."""
@@ -425,10 +430,7 @@ def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command, time
     ff = calib_bytes / (fcopy * 1024) if fcopy else None
     fw = calib_bytes / (wcopy * 1024) if wcopy else None
     kernels = [k for k in durs if k.startswith("k_")]
-    order = (["k_hist", "k_fold_step1", "k_scat<0>"]
-             + [f"{k}<{p}>" for p in range(1, 4) for k in ("k_cnt", "k_csum", "k_scat")]
-             + ["k_dir", "k_est", "k_post", "k_probe"])
-    kernels.sort(key=lambda k: order.index(k) if k in order else 99)
+    kernels.sort(key=lambda k: STEP_ORDER.index(k) if k in STEP_ORDER else 99)
     per = {}
     lines = ["| kernel | launches | avg us | min us | max us | avg us, timed region "
              "| FETCH KiB/launch | WRITE KiB/launch | HBM bytes/launch (calibrated) |",
@@ -461,6 +463,43 @@ def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command, time
                 "counters to bytes.\n\n" if ff and fw else "No calibration copy found.\n\n")
         f.write("\n".join(lines) + "\n")
     print(json.dumps(rec, indent=1))
+
+
+def summarize_l2(ctr_dir, out_dir, command, workload="rmat20"):
+    """L2 (TCC) hits and misses per step kernel from one rocprofv3 --pmc run
+    of TCC_HIT_sum and TCC_MISS_sum: per-launch means and the hit rate."""
+    import csv
+    import glob
+    import statistics as stt
+    f = glob.glob(os.path.join(ctr_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not f:
+        raise FileNotFoundError(f"counter_collection.csv under {ctr_dir}")
+    vals = {}
+    with open(f[0]) as fh:
+        for r in csv.DictReader(fh):
+            k = _short(r["Kernel_Name"])
+            if k.startswith("k_"):
+                vals.setdefault((k, r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+    kernels = sorted({k for k, _ in vals}, key=lambda k: STEP_ORDER.index(k)
+                     if k in STEP_ORDER else 99)
+    lines = ["| kernel | launches | L2 hits/launch | L2 misses/launch | hit rate |",
+             "|---|---|---|---|---|"]
+    for k in kernels:
+        h = vals.get((k, "TCC_HIT_sum"), [])
+        m = vals.get((k, "TCC_MISS_sum"), [])
+        if not h or not m:
+            continue
+        hm, mm = stt.mean(h), stt.mean(m)
+        rate = hm / (hm + mm) if hm + mm else float("nan")
+        lines.append(f"| {k} | {len(h)} | {hm:.4g} | {mm:.4g} | {rate:.3f} |")
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, f"l2_hits_{workload}.md"), "w") as fo:
+        fo.write(f"# L2 hits and misses of the step kernels, {PROFILE_TITLES[workload]}\n\n")
+        fo.write("Commands (run from the repository root on one MI355X):\n\n```\n"
+                 + command + "\n```\n\n")
+        fo.write("TCC requests that hit or missed the XCD's L2, summed over its channels, "
+                 "averaged over the launches of the run.\n\n")
+        fo.write("\n".join(lines) + "\n")
 
 
 def served_comparison(tc, inputs, nstreams=1024, ngraphs=64, r=1 << 16,
@@ -552,12 +591,18 @@ def main():
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="summarize rocprofv3 CSV dirs of this benchmark into profiles/")
     ap.add_argument("--summary-command", default="")
+    ap.add_argument("--summarize-l2", metavar="PMC_DIR",
+                    help="summarize a TCC_HIT_sum/TCC_MISS_sum rocprofv3 run into profiles/")
     ap.add_argument("--oracle-worker", nargs=5, metavar=("NPY", "R", "SEED", "W", "NB"),
                     help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.oracle_worker:
         path, rr, sd, ww, nbb = args.oracle_worker
         oracle_worker(path, int(rr), int(sd), int(ww), int(nbb))
+        return
+    if args.summarize_l2:
+        summarize_l2(args.summarize_l2, os.path.join(ROOT, "profiles"),
+                     args.summary_command, args.workload)
         return
     if args.summarize:
         summarize(*args.summarize, calib_mib=args.calib_copy_mib,
