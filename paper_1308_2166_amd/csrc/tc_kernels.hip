@@ -637,17 +637,21 @@ __device__ __forceinline__ uint32_t dir_claim(DirSlot* dir, uint32_t mask,
   return kNone;
 }
 
-// [start, end) of x's arcs, or an empty range
-__device__ __forceinline__ uint2 dir_find(const DirSlot* dir, uint32_t log2,
-                                          bool dense, uint32_t x,
-                                          uint32_t tag) {
-  const uint32_t mask = (1u << log2) - 1u;
-  if (dense) {
-    if (x > mask) return make_uint2(0, 0);
-    const uint4 e = *reinterpret_cast<const uint4*>(&dir[x]);
-    if (e.y == tag && e.x == x) return make_uint2(e.z, e.w);
-    return make_uint2(0, 0);
-  }
+// [start, end) of x's arcs, or an empty range.  Dense directory: one
+// 16-byte load whose four fields all feed selects, so the load is neither
+// split nor put behind a branch, and two lookups in a row are both in
+// flight before either is used.
+__device__ __forceinline__ uint2 dir_find_dense(const DirSlot* dir, uint32_t mask,
+                                                uint32_t x, uint32_t tag) {
+  const uint4 e = *reinterpret_cast<const uint4*>(&dir[min(x, mask)]);
+  const bool ok = (x <= mask) & (e.y == tag) & (e.x == x);
+  return make_uint2(ok ? e.z : 0u, ok ? e.w : 0u);
+}
+
+// hashed directory: linear probing from x's hash to its key or a slot that
+// is not live this step
+__device__ __forceinline__ uint2 dir_find_hashed(const DirSlot* dir, uint32_t mask,
+                                                 uint32_t x, uint32_t tag) {
   uint32_t h = mix32(x) & mask;
   for (uint32_t probe = 0; probe <= mask; ++probe) {
     const uint4 e = *reinterpret_cast<const uint4*>(&dir[h]);
@@ -671,7 +675,8 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
   const SegWork* wk = a.work + sidx;
-  const uint64_t* arc = a.arcs[wk->final_buf] + S.arc_off;
+  // (a select, not an index into the argument array: see k_est)
+  const uint64_t* arc = (wk->final_buf ? a.arcs[1] : a.arcs[0]) + S.arc_off;
   const uint32_t n = 2u * S.w;
   const uint32_t base = (gtile - S.tile_off) * kTile;
   const uint32_t nv = min((uint32_t)kTile, n - base);
@@ -743,10 +748,16 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   const uint64_t e = S.est_off + i;
   const uint2* W = reinterpret_cast<const uint2*>(S.edges);
 
+  // every load that does not depend on another is issued here: the
+  // estimator's state and the segment's words (its sorted-arc buffer, the
+  // directory mode, the step's tag)
   const uint64_t r1 = a.r1[e];  // Step 1 (k_step1) already wrote a new f1
   uint64_t r2 = a.r2[e];
   const uint32_t ccw = a.cc[e];
   const uint32_t jw = a.j1[e];
+  const uint32_t fbuf = wk->final_buf;
+  const bool dense = wk->dense != 0;
+  const uint32_t tag = *a.tagp;
   uint64_t c = ccw & kChiMax;
   bool closed = (ccw & kClosed) != 0;
   const uint64_t kb = mix64(mix64(S.key0 ^ (uint64_t)i) ^ S.batch);
@@ -760,19 +771,30 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
     closed = false;
   }
 
-  // Step 2 (Sec. 4.3): chi+ = rank(u->v) + rank(v->u) with u < v
+  // Step 2 (Sec. 4.3): chi+ = rank(u->v) + rank(v->u) with u < v.  The
+  // inverse-index pair of W[j1] is loaded together with the two directory
+  // slots (an unused, always valid pair when there is no new f1)
   const uint32_t u = (uint32_t)(r1 >> 32), v = (uint32_t)r1;
-  const bool dense = wk->dense != 0;
-  const uint32_t tag = *a.tagp;
-  const uint2 su = dir_find(a.dir + S.dir_off, S.dir_log2, dense, u, tag);
-  const uint2 sv = dir_find(a.dir + S.dir_off, S.dir_log2, dense, v, tag);
-  const uint64_t* arc = a.arcs[wk->final_buf] + S.arc_off;
+  const uint2 iv2 = *reinterpret_cast<const uint2*>(
+      a.inv + S.arc_off + 2ull * (j1 == kNone ? 0u : j1));
+  const DirSlot* dir = a.dir + S.dir_off;
+  const uint32_t dmask = (1u << S.dir_log2) - 1u;
+  uint2 su, sv;
+  if (dense) {
+    su = dir_find_dense(dir, dmask, u, tag);
+    sv = dir_find_dense(dir, dmask, v, tag);
+  } else {
+    su = dir_find_hashed(dir, dmask, u, tag);
+    sv = dir_find_hashed(dir, dmask, v, tag);
+  }
+  // (a select of the two buffer pointers: indexing the argument array by
+  // a value read at run time would load the pointer from memory)
+  const uint64_t* arc = (fbuf ? a.arcs[1] : a.arcs[0]) + S.arc_off;
   uint32_t ld, rd;
   if (j1 != kNone) {
     // f1 is W[j1]: the arcs after it on each endpoint are those after its
     // own arcs in their segments (the guard only keeps every later index
     // inside the segment)
-    const uint2 iv2 = *reinterpret_cast<const uint2*>(a.inv + S.arc_off + 2ull * j1);
     const uint32_t iu = side_u ? iv2.y : iv2.x;
     const uint32_t iv = side_u ? iv2.x : iv2.y;
     const bool ok = iu >= su.x && iu < su.y && iv >= sv.x && iv < sv.y;
