@@ -126,6 +126,18 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// The hardware deals a launch's workgroups to the eight XCDs in turn (XCD =
+// index mod 8), each XCD with its own L2.  The radix kernels map their tile
+// index through this bijection of [0, n) so that the tiles one XCD receives
+// are contiguous: neighbouring tiles' runs of a digit then meet in the same
+// L2.  (The kernels with random accesses keep the plain order, which spreads
+// a segment's tables over all eight L2s.)
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
+  const uint32_t x = b & 7u, k = b >> 3;
+  const uint32_t q = n >> 3, rem = n & 7u;
+  return x * q + min(x, rem) + k;
+}
+
 // exclusive scan of one value per thread over the block (kBlock threads)
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v,
                                                     uint32_t* s_tmp,
@@ -340,7 +352,8 @@ __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
   __shared__ uint32_t s_h[kDigits];
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
-  if (tid == 0) s_seg = seg_of_tile(a, blockIdx.x);
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  if (tid == 0) s_seg = seg_of_tile(a, blk);
   s_h[tid] = 0;
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
@@ -349,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
   const uint32_t maxid = uniform(a.work[sidx].maxid);
   if (!pass_runs(maxid, P)) return;
   const int nbits = digit_bits(maxid, P);
-  const uint32_t base = (blockIdx.x - S.tile_off) * kTile;
+  const uint32_t base = (blk - S.tile_off) * kTile;
   const uint32_t nv = min((uint32_t)kTile, n - base);
   // high words (vertex ids) of the pass input, read in order
   const uint32_t* hi = reinterpret_cast<const uint32_t*>(a.arcs[(P + 1) & 1] + S.arc_off + base) + 1;
@@ -378,7 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
       atomicAdd(&s_h[dg], (uint32_t)__popcll(mm));
   }
   __syncthreads();
-  cnt_row(a, blockIdx.x, P)[tid] = s_h[tid];
+  cnt_row(a, blk, P)[tid] = s_h[tid];
 }
 
 template <int P>
@@ -412,14 +425,15 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
   __shared__ uint32_t s_seg;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) s_seg = seg_of_tile(a, blockIdx.x);
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  if (tid == 0) s_seg = seg_of_tile(a, blk);
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
   SegWork* wk = a.work + sidx;
   const uint32_t n = 2u * S.w;
   const uint32_t maxid = uniform(wk->maxid);
-  if (P == 0 && blockIdx.x == S.tile_off && tid == 0) {
+  if (P == 0 && blk == S.tile_off && tid == 0) {
     int K = 0;  // passes run (the launched ones that do not skip)
 #pragma unroll
     for (int d = 0; d < kPasses; ++d) K += (d < (int)a.npass && pass_runs(maxid, d)) ? 1 : 0;
@@ -430,7 +444,7 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
   if (!pass_runs(maxid, P)) return;
   const int nbits = digit_bits(maxid, P);
   const uint32_t hist_p = wk->hist[P][tid];
-  const uint32_t ltile = blockIdx.x - S.tile_off;
+  const uint32_t ltile = blk - S.tile_off;
   const uint64_t* src = a.arcs[(P + 1) & 1] + S.arc_off;
   uint64_t* dst = a.arcs[P & 1] + S.arc_off;
   const uint32_t base = ltile * kTile;
