@@ -712,6 +712,12 @@ def test_parse_handmade_texts(tc):
     # a long line (under the 4096-byte limit) and tokens across 256-byte thread spans
     texts.append(b" " * 3000 + b"11 22\n" + b"1" * 9 + b" " + b"2" * 9 + b"\n")
     texts.append(b"".join(b"%d %d\n" % (i, i * 7 + 1) for i in range(70000)))
+    # text denser than four bytes per id (more ids than a block stages)
+    texts.append(b"1 2\n" * 20000 + b"3,4\n" * 20000)
+    # ids and comment lines crossing 128-byte thread slices and 32 KB tiles
+    texts.append(b"".join((b"#" + b"x" * (i % 300) + b"\n" if i % 7 == 0 else
+                           b"%d%s%d\n" % (i * 104729 % 4294967291, b" " * (1 + i % 37),
+                                          i * 7919 % 4294967291)) for i in range(9000)))
     for t in texts:
         got = tc.tc_parse_edges(_dev_bytes(t)) if t else tc.tc_parse_edges(
             torch.empty(0, dtype=torch.uint8, device="cuda"))
