@@ -129,13 +129,15 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
 // The hardware deals a launch's workgroups to the eight XCDs in turn (XCD =
 // index mod 8), each XCD with its own L2.  The radix kernels map their tile
 // index through this bijection of [0, n) so that the tiles one XCD receives
-// are contiguous: neighbouring tiles' runs of a digit then meet in the same
-// L2.  (The kernels with random accesses keep the plain order, which spreads
+// come in runs of eight: neighbouring tiles' runs of a digit then mostly
+// meet in the same L2.  (The kernels with random accesses keep the plain order, which spreads
 // a segment's tables over all eight L2s.)
 __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
-  const uint32_t x = b & 7u, k = b >> 3;
-  const uint32_t q = n >> 3, rem = n & 7u;
-  return x * q + min(x, rem) + k;
+  // groups of 64 blocks: within a group XCD x takes its 8 consecutive tiles,
+  // so the launch's window of active tiles stays contiguous; the last,
+  // partial group keeps the plain order
+  if (b >= (n & ~63u)) return b;
+  return (b & ~63u) + ((b & 7u) << 3) + ((b >> 3) & 7u);
 }
 
 // exclusive scan of one value per thread over the block (kBlock threads)
