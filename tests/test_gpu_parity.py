@@ -726,6 +726,18 @@ def test_parse_handmade_texts(tc):
         assert np.array_equal(got.cpu().numpy().view(np.uint32).astype(np.uint64), want)
 
 
+def test_parse_misaligned_text(tc):
+    # a text that does not start on a 16-byte boundary (a view into a larger
+    # buffer) is staged byte by byte; the result is the same
+    G = inputs.gnm(3000, 40000, seed=44, device="cuda")
+    txt = inputs.edge_list_text(G, sep=" ", header="# shifted\n")
+    for shift in (1, 3, 8):
+        buf = torch.zeros(txt.numel() + 16, dtype=torch.uint8, device="cuda")
+        buf[shift:shift + txt.numel()] = txt
+        got = tc.tc_parse_edges(buf[shift:shift + txt.numel()])
+        assert torch.equal(got, G), f"shift {shift}"
+
+
 def test_parse_round_trip_and_process(tc):
     G = inputs.rmat(14, 60000, seed=31, device="cuda")
     for sep in ("\t", " ", ", "):
