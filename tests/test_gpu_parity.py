@@ -680,20 +680,8 @@ def test_naive_boundary(tc):
 # -- text edge lists parsed on the device -------------------------------------------
 
 def _ref_parse(text: bytes):
-    """Plain reference: non-comment lines, digit runs, pairs."""
-    toks = []
-    for line in text.split(b"\n"):
-        if line[:1] in (b"#", b"%"):
-            continue
-        cur = None
-        for ch in line + b" ":
-            if 48 <= ch <= 57:
-                cur = (cur or 0) * 10 + ch - 48
-            elif cur is not None:
-                toks.append(cur)
-                cur = None
-    assert len(toks) % 2 == 0
-    return np.array(toks, dtype=np.uint64).reshape(-1, 2)
+    from oracle.parse import parse_edge_list
+    return parse_edge_list(text)
 
 
 def _dev_bytes(b: bytes) -> torch.Tensor:

@@ -343,3 +343,27 @@ def test_theorem_2_guarantee_holds():
         est, _ = bank.mom(9)
         ok += abs(est - tau) <= eps * tau
     assert ok >= 8
+
+
+# -- the reference parser of text edge lists ------------------------------------------
+
+def test_reference_parser_pins():
+    from oracle.parse import ParseError, parse_edge_list
+
+    def P(t):
+        return parse_edge_list(t).tolist()
+
+    assert P(b"1 2\n3 4\n") == [[1, 2], [3, 4]]
+    assert P(b"") == [] and P(b"# only a comment") == []
+    # comments ('#', '%' first), CRLF, tabs, commas, runs of separators,
+    # a missing final newline
+    assert P(b"# SNAP\n% mm\n10\t20\r\n 30 ,  40 \n50 60") == [[10, 20], [30, 40], [50, 60]]
+    # a '#' later in a line is a separator, not a comment
+    assert P(b"7 # 8\n") == [[7, 8]]
+    # the largest id
+    assert P(b"4294967295 0\n") == [[4294967295, 0]]
+    # ids pair up across lines (file order of ids)
+    assert P(b"1\n2 3\n4\n") == [[1, 2], [3, 4]]
+    for bad in (b"1 2 3\n", b"4294967296 1\n"):
+        with pytest.raises(ParseError):
+            parse_edge_list(bad)
