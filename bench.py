@@ -128,7 +128,7 @@ def cpu_baseline_all_cores(E_host, r, seed, w, nb, workers):
                       f"variant, slowest process {worst:.1f} s"}
 
 
-def batched_comparison(tc, inputs, nstreams=256, ks=(4, 8, 16), replays=3):
+def batched_comparison(tc, inputs, nstreams=256, ks=(1, 2, 4, 8, 16), replays=3):
     """Plain (one bank per stream, one launch set per chunk) against batched
     (every stream's chunk in one launch set per step) and graph replay of the
     batched steps, on independent streams of uneven length.  Each stream is
