@@ -371,9 +371,16 @@ PROFILE_TITLES = {
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel source's code: comments and blank space removed, so
+    that only a change to what is compiled invalidates recorded counters."""
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    import re
+    with open(KERNEL_SRC) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = " ".join(src.split())
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 STEP_ORDER = (["k_hist", "k_fold_step1", "k_scat<0>"]

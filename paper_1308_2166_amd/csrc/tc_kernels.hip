@@ -16,8 +16,10 @@
 //           through LDS, coalesced).  Arcs are (vertex << 32 | 2 pos + side); stability keeps every
 //           vertex's arcs in arrival order, which is the rankAll grouping
 //           of the Lemma on rankAll read in increasing pos (rank = arcs
-//           after it in the segment).  Digits constant over a chunk are
-//           skipped on the device.
+//           after it in the segment).  A pass whose digit is zero for
+//           every arc of a segment (above its largest id) is skipped on the
+//           device, and passes above a declared vertex bound are not
+//           launched.
 //  k_dir    vertex -> [start, end) of its arcs (tag-versioned directory),
 //           and the sorted index of the arcs of positions Step 1 picked
 //  k_est    Step 2 for every estimator; records its Step-3 closing edge
@@ -275,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// k_fold (in the k_step1 launch): per radix chunk, the digit-0 sums of its
+// k_fold (in the k_fold_step1 launch): per radix chunk, the digit-0 sums of its
 // tiles (the chunk sums of the first radix pass), added into the segment's
 // digit-0 histogram; and the largest vertex id
 // ---------------------------------------------------------------------------
