@@ -500,6 +500,14 @@ def summarize_l2(ctr_dir, out_dir, command, workload="rmat20"):
         rate = hm / (hm + mm) if hm + mm else float("nan")
         lines.append(f"| {k} | {len(h)} | {hm:.4g} | {mm:.4g} | {rate:.3f} |")
     os.makedirs(out_dir, exist_ok=True)
+    rec = {"kernel_source_sha256_16": kernel_source_hash(), "command": command,
+           "per_kernel": {k: {"launches": len(vals[(k, "TCC_HIT_sum")]),
+                              "hits": stt.mean(vals[(k, "TCC_HIT_sum")]),
+                              "misses": stt.mean(vals[(k, "TCC_MISS_sum")])}
+                          for k in kernels
+                          if (k, "TCC_HIT_sum") in vals and (k, "TCC_MISS_sum") in vals}}
+    with open(os.path.join(out_dir, f"l2_hits_{workload}.json"), "w") as fo:
+        json.dump(rec, fo, indent=1)
     with open(os.path.join(out_dir, f"l2_hits_{workload}.md"), "w") as fo:
         fo.write(f"# L2 hits and misses of the step kernels, {PROFILE_TITLES[workload]}\n\n")
         fo.write("Commands (run from the repository root on one MI355X):\n\n```\n"
@@ -507,6 +515,33 @@ def summarize_l2(ctr_dir, out_dir, command, workload="rmat20"):
         fo.write("TCC requests that hit or missed the XCD's L2, summed over its channels, "
                  "averaged over the launches of the run.\n\n")
         fo.write("\n".join(lines) + "\n")
+
+
+def random_gather_ceiling(table_bytes, n_idx=1 << 26, reps=5):
+    """Random 8-byte gathers per second on this GPU (torch.index_select over
+    a table of `table_bytes` with uniformly random indices): the ceiling for
+    a kernel bound by random line accesses.  Each gather is one L2 request
+    and, for tables far above the L2s, almost always one miss."""
+    import torch
+    n = table_bytes // 8
+    table = torch.arange(n, dtype=torch.int64, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    idx = torch.randint(0, n, (n_idx,), device="cuda", generator=g)
+    out = torch.empty(n_idx, dtype=torch.int64, device="cuda")
+    torch.index_select(table, 0, idx, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.index_select(table, 0, idx, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    ok = bool(torch.equal(out, idx))
+    del table, idx, out
+    return {"table_bytes": table_bytes, "gathers": n_idx, "ms": round(sec * 1e3, 3),
+            "G_per_s": round(n_idx / sec / 1e9, 2), "checked": ok}
 
 
 def served_comparison(tc, inputs, nstreams=1024, ngraphs=64, r=1 << 16,
@@ -769,6 +804,24 @@ def main():
                 roofline["step_traffic_GBs"] = round(step_bytes / (dt / steps) / 1e9, 1)
                 roofline["step_traffic_frac"] = round(
                     step_bytes / (dt / steps) / 1e9 / HBM_PEAK_GBS, 4)
+        except (OSError, KeyError, ValueError):
+            pass
+        # random-access view of the dominant kernel: its measured L2 misses
+        # per second against the random-gather ceiling of this GPU (a table
+        # the size of the memory-side cache, and one far above it)
+        try:
+            with open(os.path.join(ROOT, "profiles", f"l2_hits_{args.workload}.json")) as f:
+                l2 = json.load(f)
+            if (l2["kernel_source_sha256_16"] == kernel_source_hash()
+                    and dom in l2["per_kernel"]):
+                miss = l2["per_kernel"][dom]["misses"]
+                rate = miss / (avg_ms * 1e-3) / 1e9
+                ceil_mall = random_gather_ceiling(128 << 20)
+                ceil_hbm = random_gather_ceiling(1 << 30)
+                roofline["random_access"] = {
+                    "l2_misses_per_launch": miss, "G_misses_per_s": round(rate, 2),
+                    "gather_ceiling_128MB": ceil_mall, "gather_ceiling_1GB": ceil_hbm,
+                    "ratio_to_torch_gather_128MB": round(rate / ceil_mall["G_per_s"], 3)}
         except (OSError, KeyError, ValueError):
             pass
         step_alg = sum(alg_bytes(k_, w, r, nontrivial) for k_ in per_kernel)
