@@ -328,6 +328,36 @@ def test_rmat24_first_batches(tc):
     run_both(tc, E, r, seed, w)
 
 
+def test_largest_batch_bulk_equals_per_estimator(tc):
+    # one batch of TC_MAX_BATCH = 2^28 edges (the whole R-MAT scale-24
+    # stream): too large for the CPU oracle, so the bulk step is checked
+    # against the per-estimator kernel, an independent route to the same
+    # state (itself checked against the oracle at small sizes); then a
+    # second batch on top of it
+    say("  generating rmat24 on the GPU")
+    G, _, _, _ = inputs.workload("rmat24", device="cuda")
+    assert G.shape[0] == tc.TC_MAX_BATCH
+    r, seed = 256, 99
+    n = inputs.vertex_count("rmat24")
+    bulk, naive = tc.Bank(r, seed), tc.Bank(r, seed)
+    tc.tc_set_vertex_bound(bulk.h, 2 * n)
+    bulk.process(G)
+    naive.process_naive(G)
+    assert_same(bulk.state(), naive.state(), "largest batch")
+    # second batch: new edges from existing vertices to fresh ones (none
+    # repeats an edge of the first)
+    k = torch.arange(1 << 20, device="cuda", dtype=torch.int64)
+    tail = torch.stack([G[:1 << 20, 0].to(torch.int64), n + k], 1).to(torch.int32).contiguous()
+    bulk.process(tail)
+    naive.process_naive(tail)
+    assert_same(bulk.state(), naive.state(), "after a second batch")
+    assert tc.tc_estimate_ex(bulk.h)[0] == tc.tc_estimate_ex(naive.h)[0]
+    bulk.close()
+    naive.close()
+    del G
+    torch.cuda.empty_cache()
+
+
 # -- reset and HIP-graph replay ---------------------------------------------------------
 
 def test_reset_gives_a_fresh_bank(tc):
