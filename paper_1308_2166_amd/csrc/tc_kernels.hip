@@ -373,8 +373,20 @@ __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
   uint32_t v[kItems];
 #pragma unroll
   for (int i = 0; i < kItems; ++i) v[i] = hi[2u * min((uint32_t)(i * kBlock + tid), nv - 1)];
-  // lanes with equal digits add once (few distinct digits would otherwise
-  // serialize the LDS atomics)
+  if (P == 1 && nbits >= 7) {
+    // the second byte of arcs ordered by their first: most lanes of a wave
+    // differ, and one LDS atomic per arc is cheaper than matching equal
+    // digits first.  (From pass 2 on, arcs arrive grouped by their low 16
+    // bits, so a high-degree vertex fills many lanes with one digit.)
+#pragma unroll
+    for (int i = 0; i < kItems; ++i)
+      if ((uint32_t)(i * kBlock + tid) < nv) atomicAdd(&s_h[(v[i] >> (8 * P)) & 255u], 1u);
+    __syncthreads();
+    cnt_row(a, blk, P)[tid] = s_h[tid];
+    return;
+  }
+  // few digits: lanes with equal digits add once (one atomic per lane
+  // would serialize on the few bins)
   const int lane = tid & 63;
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
