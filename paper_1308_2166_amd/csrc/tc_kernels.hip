@@ -307,9 +307,14 @@ __device__ void fold_chunk(const StepArgs& a, uint32_t c) {
   const SegDesc S = seg_desc(a, sidx);
   const uint32_t r0 = S.hblk_off + (c - S.chunk_off) * kChunk;
   const uint32_t r1 = min(r0 + kChunk, S.hblk_off + S.nhblk);
+  // all of the chunk's rows in flight at once
   uint32_t acc = 0;
-#pragma unroll 8
-  for (uint32_t rr = r0; rr < r1; ++rr) acc += a.hpart[(size_t)rr * (kPasses * kDigits) + tid];
+  uint32_t v[kChunk];
+#pragma unroll
+  for (uint32_t i = 0; i < kChunk; ++i)
+    v[i] = r0 + i < r1 ? a.hpart[(size_t)(r0 + i) * (kPasses * kDigits) + tid] : 0u;
+#pragma unroll
+  for (uint32_t i = 0; i < kChunk; ++i) acc += v[i];
   if ((uint32_t)tid < r1 - r0) atomicMax(&s_max, a.mpart[r0 + tid]);
   __syncthreads();
   SegWork* wk = a.work + sidx;
@@ -423,9 +428,13 @@ __global__ __launch_bounds__(kBlock) void k_csum(StepArgs a) {
   if (!pass_runs(uniform(wk->maxid), P)) return;
   const uint32_t t0 = S.tile_off + (blockIdx.x - S.chunk_off) * kChunk;
   const uint32_t t1 = min(t0 + kChunk, S.tile_off + S.ntiles);
+  // all of the chunk's rows in flight at once
   uint32_t acc = 0;
-#pragma unroll 8
-  for (uint32_t t = t0; t < t1; ++t) acc += cnt_row(a, t, P)[tid];
+  uint32_t v[kChunk];
+#pragma unroll
+  for (uint32_t i = 0; i < kChunk; ++i) v[i] = t0 + i < t1 ? cnt_row(a, t0 + i, P)[tid] : 0u;
+#pragma unroll
+  for (uint32_t i = 0; i < kChunk; ++i) acc += v[i];
   csum_row(a, blockIdx.x, P)[tid] = acc;
   // the segment's digit-P histogram (the bin starts of the pass)
   if (acc) atomicAdd(&wk->hist[P][tid], acc);
