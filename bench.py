@@ -250,6 +250,47 @@ def batched_comparison(tc, inputs, nstreams=256, ks=(1, 2, 4, 8, 16), replays=3)
     }
 
 
+def batched_profile(tc, inputs, K, reps, nstreams=256):
+    """The batched form alone, for a profiler: the same streams and banks as
+    the batched comparison, each stream cut into K batches; one warm-up pass,
+    then `reps` passes of K steps (so a kernel's last reps*K launches are the
+    measured ones)."""
+    import torch
+    streams = inputs.many_streams(nstreams, device="cuda")
+    rs = [s_["r"] for s_ in streams]
+    ms = [s_["edges"].shape[0] for s_ in streams]
+    steps = []
+    for k in range(K):
+        ids, chunks = [], []
+        for b, st in enumerate(streams):
+            w = (ms[b] + K - 1) // K
+            c = st["edges"][k * w:(k + 1) * w]
+            if c.shape[0]:
+                ids.append(b)
+                chunks.append(c)
+        steps.append((ids, chunks))
+    mb = tc.MultiBank(rs, [s_["seed"] for s_ in streams])
+    tc.tc_multi_set_vertex_bound(mb.h, max(s_["n"] for s_ in streams))
+    tc.tc_multi_reserve(mb.h, steps[0][0], [c.shape[0] for c in steps[0][1]])
+    stream = torch.cuda.current_stream()
+    times = []
+    for rep in range(reps + 1):
+        tc.tc_multi_reset(mb.h, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for ids, chunks in steps:
+            mb.process(ids, chunks, stream)
+        torch.cuda.synchronize()
+        if rep:
+            times.append(time.perf_counter() - t0)
+    mb.close()
+    rm = float(sum(r * m for r, m in zip(rs, ms)))
+    best = min(times)
+    return {"form": "batched", "streams": nstreams, "batches_per_stream": K,
+            "ms_per_step": round(best * 1e3 / K, 3), "value": rm / best,
+            "unit": "estimator-edge updates/s"}
+
+
 def host_fed(tc, G, r, seed, w, nv, reps=2):
     """The same stream fed from pinned host memory: each batch is copied to
     one of two device buffers on a copy stream while the previous batch is
@@ -364,6 +405,7 @@ def traffic_json(workload: str) -> str:
 
 
 PROFILE_TITLES = {
+    "batched": "C4 batched form (256 streams, one batch per stream)",
     "rmat20": "R-MAT scale 20 (r=2^20, w=2^22)",
     "rmat24": "R-MAT scale 24 (r=2^22, w=2^24)",
     "gnm-2k": "G(2000, 20000) (r=4096, w=2048)",
@@ -633,6 +675,11 @@ def main():
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="summarize rocprofv3 CSV dirs of this benchmark into profiles/")
     ap.add_argument("--summary-command", default="")
+    ap.add_argument("--summary-name", default="", choices=["", "batched"],
+                    help="name the profile summary for this form instead of --workload")
+    ap.add_argument("--batched-profile", type=int, default=0, metavar="K",
+                    help="only run the batched form (K batches per stream), "
+                         "one warm-up pass then --steps passes, for a profiler")
     ap.add_argument("--summarize-l2", metavar="PMC_DIR",
                     help="summarize a TCC_HIT_sum/TCC_MISS_sum rocprofv3 run into profiles/")
     ap.add_argument("--oracle-worker", nargs=5, metavar=("NPY", "R", "SEED", "W", "NB"),
@@ -649,7 +696,7 @@ def main():
     if args.summarize:
         summarize(*args.summarize, calib_mib=args.calib_copy_mib,
                   out_dir=os.path.join(ROOT, "profiles"), command=args.summary_command,
-                  timed=args.steps, workload=args.workload)
+                  timed=args.steps, workload=args.summary_name or args.workload)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
@@ -674,6 +721,10 @@ def main():
         dst.copy_(big[:n])
         torch.cuda.synchronize()
         del big, dst
+    if args.batched_profile:
+        print(json.dumps(batched_profile(tc, inputs, args.batched_profile, args.steps,
+                                         args.streams)), flush=True)
+        return
     log(f"[bench] generating {args.workload} on the GPU")
     G, r, w, seed = inputs.workload(args.workload, device="cuda")
     G = G.contiguous()
