@@ -232,7 +232,9 @@ void tc_multi_destroy(tc_multi *s);
  * *nedges (HOST).  Blocking (it returns the count).  TC_EINVAL for NULL
  * pointers, an odd number of ids, an id above 2^32 - 1, a line longer than
  * 4096 bytes, or more than max_edges edges (nothing useful is written
- * then); TC_ENOMEM if its scratch cannot be allocated. */
+ * then); TC_ENOMEM if its scratch cannot be allocated.  It allocates and
+ * frees device scratch (about a sixteenth of the text size) and waits for
+ * `stream`, so it cannot be captured into a HIP graph. */
 int tc_parse_edges(const char *text, uint64_t nbytes, uint32_t *edges,
                    uint64_t max_edges, uint64_t *nedges, void *stream);
 
