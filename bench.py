@@ -753,12 +753,14 @@ def main():
     warm_bank.sync()
     warm_bank.close()
 
-    def fresh_banks(timing):
-        """timing: False, True (every kernel) or a list of kernel names."""
+    def fresh_banks(timing, every=1):
+        """timing: False, True (every kernel) or a list of kernel names, set
+        on every `every`-th bank (each bank walks its stream's batches in
+        order, so any subset of banks samples every batch alike)."""
         out = []
-        for _ in range(nbanks):
+        for i in range(nbanks):
             b = new_bank()
-            if timing:
+            if timing and i % every == 0:
                 tc.tc_set_kernel_timing(b.h, timing)
             out.append(b)
         torch.cuda.synchronize()
@@ -814,8 +816,9 @@ def main():
     per_batch_ms = timed_run(bk, False) * 1e3 / steps
     close_all(bk)
     # 3. the timed region: one tc_process_stream call per bank, events only
-    #    around the dominant kernel
-    banks = fresh_banks([dom] if dom else False)
+    #    around the dominant kernel, on every other bank (each event pair
+    #    costs a few microseconds of the step)
+    banks = fresh_banks([dom] if dom else False, every=2)
     log(f"[bench] timing {steps} steps")
     dt = timed_run(banks, True)
     call_forms = {"per_batch_calls": round(per_batch_ms, 4),
