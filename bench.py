@@ -38,10 +38,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def radix_passes(bound: int, maxid: int) -> list:
+    """Which of the four radix launches move arcs for ids up to maxid under a
+    declared vertex bound, as the library chooses them: 10-bit digits (two
+    passes) when bound - 1 has 17 to 20 bits, else 8-bit digits; a pass
+    whose digit is zero in every id skips on the device."""
+    bound_bits = max(1, (bound - 1).bit_length())
+    d = 10 if 16 < bound_bits <= 20 else 8
+    npass = -(-bound_bits // d)
+    bits = max(1, maxid.bit_length())
+    return [p < npass and d * p < bits for p in range(4)]
+
+
 def alg_bytes(kernel: str, w: int, r: int, nontrivial: list) -> float:
     """Bytes the step's algorithm must move per launch of `kernel` (see the
     design notes): streamed inputs/outputs only, no table or gather traffic,
-    nothing for the radix bookkeeping (the fold, k_csum)."""
+    nothing for the radix bookkeeping (the fold, k_csum, k_cscan)."""
     arcs = 2 * w
     if kernel == "k_hist":
         return 8.0 * w
@@ -425,17 +437,21 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
-STEP_ORDER = (["k_hist", "k_fold_step1", "k_scat<0>"]
-              + [f"{k}<{p}>" for p in range(1, 4) for k in ("k_cnt", "k_csum", "k_scat")]
+STEP_ORDER = (["k_hist", "k_fold_step1", "k_cscan<0>", "k_scat<0>"]
+              + [f"{k}<{p}>" for p in range(1, 4)
+                 for k in ("k_cnt", "k_csum", "k_cscan", "k_scat")]
               + ["k_dir", "k_est", "k_post", "k_probe"])
 
 
 def _short(name: str) -> str:
-    """Kernel name as tc_kernel_name gives it (the four-wave build of a
-    radix pass, k_scat4<P>, is the launch k_scat<P>)."""
+    """Kernel name as tc_kernel_name gives it: the digit width is dropped
+    (k_scat<1, 10> is the launch k_scat<1>, k_hist<8> is k_hist), and the
+    four-wave build of a radix pass, k_scat4<P>, is the launch k_scat<P>."""
     import re
-    n = re.sub(r"\(.*", "", name).replace("void ", "").replace("tc::", "")
-    return n.strip().replace("k_scat4<", "k_scat<")
+    n = re.sub(r"\(.*", "", name).replace("void ", "").replace("tc::", "").strip()
+    n = re.sub(r"<(\d+), \d+>$", r"<\1>", n)
+    n = re.sub(r"^(k_hist|k_fold_step1)<\d+>$", r"\1", n)
+    return n.replace("k_scat4<", "k_scat<")
 
 
 def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command, timed=0,
@@ -832,9 +848,7 @@ def main():
     if dom:
         live, live_n = kernel_totals(banks)
         # non-trivial digit passes of this stream (vertex id width)
-        maxid = int(G.max().item())
-        bits = max(1, math.ceil(math.log2(maxid + 1)))
-        nontrivial = [8 * p < bits for p in range(4)]
+        nontrivial = radix_passes(nv, int(G.max().item()))
         avg_ms = live[dom] / live_n
         ab = alg_bytes(dom, w, r, nontrivial)
         achieved = ab / (avg_ms * 1e-3) / 1e9

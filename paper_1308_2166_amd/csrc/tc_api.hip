@@ -75,11 +75,11 @@ void dfree(T*& p) {
 }
 
 // kernels (bit k = launch k of a step) that a step with npass radix passes
-// launches: the three kernels of each pass at or above npass are skipped
+// launches: the four kernels of each pass at or above npass are skipped
 uint32_t launched_kernels(uint32_t npass) {
   uint32_t m = (1u << kNumKernels) - 1u;
   for (uint32_t p = npass < 1 ? 1 : npass; p < (uint32_t)kPasses; ++p)
-    m &= ~(7u << (3 + 3 * (p - 1)));
+    m &= ~(15u << (4 + 4 * (p - 1)));
   return m;
 }
 
@@ -153,6 +153,7 @@ struct Engine {
   int sticky = TC_OK;
   uint32_t id_limit = 0xFFFFFFFFu;  // declared vertex bound - 1
   uint32_t npass = kPasses;
+  uint32_t dbits = 8;  // radix digit width for that bound
 
   // optional per-kernel timing: a start/end event pair per timed kernel
   // and step (bit k of timing_mask times kernel k)
@@ -284,10 +285,10 @@ struct Engine {
     cap_need = std::max(need_n, cap_need);
     cap_segs = std::max(nseg, cap_segs);
     bool bad = dalloc(&arcs[0], cap_arcs) || dalloc(&arcs[1], cap_arcs) ||
-               dalloc(&csum, ((cap_tiles + kChunk - 1) / kChunk + cap_segs) * kPasses * kDigits) ||
+               dalloc(&csum, ((cap_tiles + kChunk - 1) / kChunk + cap_segs) * kRowWords) ||
                dalloc(&dir, cap_dir) || dalloc(&need, cap_need) ||
                dalloc(&inv, cap_arcs) ||
-               dalloc(&hpart, cap_tiles * kPasses * kDigits) ||
+               dalloc(&hpart, cap_tiles * kRowWords) ||
                dalloc(&mpart, cap_tiles);
     for (ParityScratch& p : par)
       bad = bad || dalloc(&p.work, cap_segs) || dalloc(&p.qt, cap_qt) ||
@@ -446,6 +447,7 @@ struct Engine {
     a.err = err;
     a.id_limit = id_limit;
     a.npass = npass;
+    a.dbits = dbits;
     if (a.nseg > 1) {
       rc = stage_descs(segs, P.segs, st, capturing);
       if (rc) return rc;
@@ -543,12 +545,14 @@ struct Engine {
   }
 
   // every vertex id is below n (2 <= n <= 2^32): the radix passes above
-  // the top byte of n - 1 are not launched
+  // the top digit of n - 1 are not launched.  Ids of 17 to 20 bits take
+  // two passes of 10-bit digits instead of three of 8.
   int set_bound(uint64_t n) {
     if (n < 2 || n > (1ull << 32)) return fail(TC_EINVAL, "vertex bound must be in [2, 2^32]");
     id_limit = (uint32_t)(n - 1);
-    npass = 1;
-    while (npass < kPasses && (id_limit >> (8 * npass)) != 0u) ++npass;
+    const uint32_t bits = 32u - (uint32_t)__builtin_clz(id_limit);
+    dbits = bits > 16 && bits <= (uint32_t)(kWidePasses * kWideBits) ? (uint32_t)kWideBits : 8u;
+    npass = (bits + dbits - 1) / dbits;
     return TC_OK;
   }
 
@@ -806,10 +810,10 @@ int tc_sync(tc_state* s) {
 }
 
 static const char* const kKernelNames[kNumKernels] = {
-    "k_hist", "k_fold_step1", "k_scat<0>",
-    "k_cnt<1>", "k_csum<1>", "k_scat<1>",
-    "k_cnt<2>", "k_csum<2>", "k_scat<2>",
-    "k_cnt<3>", "k_csum<3>", "k_scat<3>",
+    "k_hist", "k_fold_step1", "k_cscan<0>", "k_scat<0>",
+    "k_cnt<1>", "k_csum<1>", "k_cscan<1>", "k_scat<1>",
+    "k_cnt<2>", "k_csum<2>", "k_cscan<2>", "k_scat<2>",
+    "k_cnt<3>", "k_csum<3>", "k_cscan<3>", "k_scat<3>",
     "k_dir", "k_est", "k_post", "k_probe"};
 
 static int set_timing(Engine& e, uint32_t mask) {

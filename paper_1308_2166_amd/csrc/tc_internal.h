@@ -14,14 +14,21 @@ constexpr uint64_t kEmpty = ~0ull;      // empty edge code
 constexpr uint32_t kNone = 0xFFFFFFFFu;  // no index
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 
-// radix sort of the 2w arcs: 8-bit digits of the 32-bit vertex id
+// radix sort of the 2w arcs by vertex id, in passes of D-bit digits: D = 8
+// (up to four passes), or D = 10 when a declared vertex bound above 2^16
+// leaves at most 20 bits (two passes instead of three)
 constexpr int kBlock = 256;              // threads per block
 constexpr int kWaves = kBlock / 64;      // wave64
 constexpr int kItems = 16;               // arcs per thread per tile
 constexpr int kTile = kBlock * kItems;   // 4096 arcs per tile
-constexpr int kDigits = 256;
-constexpr int kPasses = 4;
-constexpr int kNumKernels = 16;  // launches per step (k_hist .. k_probe)
+constexpr int kPasses = 4;               // passes of 8-bit digits
+constexpr int kWideBits = 10;            // the wide digit
+constexpr int kWidePasses = 2;           // passes of wide digits
+// words of one tile's (or chunk's, or segment's) digit counts over all
+// passes: pass P's counts start at word P << D
+constexpr int kRowWords = kWidePasses << kWideBits;
+static_assert(kRowWords >= kPasses << 8, "a row holds every 8-bit pass");
+constexpr int kNumKernels = 20;  // launches per step (k_hist .. k_probe)
 constexpr int kHistTiles = 1;   // tiles per k_hist block (one: its counts are
                                 // the per-tile counts of the first radix pass)
 constexpr uint32_t kChunk = 32;  // tiles per chunk of the radix scans (and
@@ -80,7 +87,8 @@ struct SegDesc {
 
 // per-segment values produced during a step (device)
 struct SegWork {
-  uint32_t hist[kPasses][kDigits];  // digit histograms of the 2w arcs
+  uint32_t hist[kRowWords];         // digit histograms of the 2w arcs
+                                    // (pass P at word P << D)
   uint32_t maxid;                   // largest vertex id in the chunk
   uint32_t final_buf;               // arc buffer holding the sorted arcs
   uint32_t dense;                   // directory indexed by vertex id
@@ -112,7 +120,7 @@ struct StepArgs {
   uint32_t ntiles;        // total tiles over segments
   uint32_t nhblk;         // total k_hist blocks over segments
   uint32_t nstep1;        // k_step1 blocks (run in the k_fold launch)
-  uint32_t* hpart;        // per k_hist block: kPasses x kDigits digit counts
+  uint32_t* hpart;        // per tile: kRowWords digit counts (pass P at P << D)
   uint32_t* mpart;        // per k_hist block: largest vertex id
   uint64_t nest;          // total estimator threads over segments
   uint32_t* tagp;         // device word: this step's directory tag (never 0);
@@ -124,7 +132,7 @@ struct StepArgs {
   // scratch
   SegWork* work;          // [nseg]
   uint64_t* arcs[2];      // ping-pong arc buffers
-  uint32_t* csum;         // per radix chunk: digit sums [chunk][pass][digit]
+  uint32_t* csum;         // per radix chunk: kRowWords digit sums
   uint32_t nchunk;        // total radix chunks over segments
   DirSlot* dir;
   uint32_t* qt;           // query table: owner per slot
@@ -140,8 +148,9 @@ struct StepArgs {
                           // for arcs of needed positions)
   uint32_t* err;          // sticky error bits
   uint32_t id_limit;      // largest vertex id allowed (declared bound - 1)
-  uint32_t npass;         // radix passes launched (1..kPasses): the bound's
-                          // byte count
+  uint32_t npass;         // radix passes launched: the number of D-bit
+                          // digits of the bound (1..kPasses)
+  uint32_t dbits;         // digit width D: 8 or kWideBits
 };
 
 // arguments of the per-estimator (naive) step: one bank, one batch

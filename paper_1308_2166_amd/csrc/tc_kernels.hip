@@ -1,19 +1,23 @@
 // Device kernels of the bulk estimator update (Tangwongsan, Pavan,
 // Tirthapura, Sec. 4: bulkUpdateAll) for gfx950.
 //
-// One step = k_hist -> k_fold_step1 -> k_scat<0> -> 3 x (k_cnt -> k_csum ->
-// k_scat) -> k_dir -> k_est -> k_post -> k_probe.
+// One step = k_hist -> k_fold_step1 -> k_cscan<0> -> k_scat<0> -> up to
+// 3 x (k_cnt -> k_csum -> k_cscan -> k_scat) -> k_dir -> k_est -> k_post ->
+// k_probe.
 //
 //  k_hist   per-tile counts of digit 0 of the 2w arcs (+ max id, self-loop
 //           check)
 //  k_fold_step1
-//           per-segment digit histograms and chunk sums from the per-tile
-//           counts; Step 1 (which estimators take a new f1, from where)
-//  k_cnt, k_csum, k_scat
-//           stable LSD radix pass over 8 bits of the vertex id
-//           (reduce-then-scan: tile counts, chunk sums, and a scatter that
-//           adds up its own offsets, ranks with wave64 ballots and writes
-//           through LDS, coalesced).  Arcs are (vertex << 32 | 2 pos + side); stability keeps every
+//           chunk sums and per-segment digit histograms from the per-tile
+//           counts (which become prefixes within their chunk); Step 1
+//           (which estimators take a new f1, from where)
+//  k_cnt, k_csum, k_cscan, k_scat
+//           stable LSD radix pass over D bits of the vertex id (D = 8, or
+//           10 when a declared vertex bound makes that two passes not three)
+//           (reduce-then-scan: tile counts, chunk sums and in-chunk tile
+//           prefixes, chunk bases, and a scatter that reads its offsets in
+//           two rows, ranks with wave64 ballots and writes through LDS,
+//           coalesced).  Arcs are (vertex << 32 | 2 pos + side); stability keeps every
 //           vertex's arcs in arrival order, which is the rankAll grouping
 //           of the Lemma on rankAll read in increasing pos (rank = arcs
 //           after it in the segment).  A pass whose digit is zero for
@@ -168,7 +172,43 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v,
 }
 
 // ---------------------------------------------------------------------------
-// k_hist: per-segment histograms of all four digits of the arc keys
+// Radix layout for D-bit digits: kBins bins; in every per-digit step thread
+// t owns the kPer consecutive bins [kPer t, kPer t + kPer), moved as one
+// word or one uint4.  A tile's (chunk's, segment's) counts of pass P start
+// at word P << D of its kRowWords-word row.
+// ---------------------------------------------------------------------------
+template <int D>
+struct Rdx {
+  static constexpr int kBins = 1 << D;
+  static constexpr int kPer = kBins / kBlock;
+  static constexpr uint32_t kMask = kBins - 1;
+  static_assert(kPer == 1 || kPer == 4, "one word or one uint4 of bins per thread");
+  static_assert(kPasses * 8 >= 32 && kWidePasses * kWideBits <= 32, "id widths");
+};
+
+// this thread's kPer bins at p + kPer * tid (global or LDS, 16-byte aligned)
+template <int N>
+__device__ __forceinline__ void ld_bins(const uint32_t* p, uint32_t (&v)[N]) {
+  if constexpr (N == 1) {
+    v[0] = p[threadIdx.x];
+  } else {
+    static_assert(N == 4, "bins per thread");
+    const uint4 q = reinterpret_cast<const uint4*>(p)[threadIdx.x];
+    v[0] = q.x, v[1] = q.y, v[2] = q.z, v[3] = q.w;
+  }
+}
+template <int N>
+__device__ __forceinline__ void st_bins(uint32_t* p, const uint32_t (&v)[N]) {
+  if constexpr (N == 1) {
+    p[threadIdx.x] = v[0];
+  } else {
+    static_assert(N == 4, "bins per thread");
+    reinterpret_cast<uint4*>(p)[threadIdx.x] = make_uint4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_hist: per-tile counts of digit 0 of the arc keys
 // ---------------------------------------------------------------------------
 // add one to bin `dg`; a digit shared by the whole wave costs one atomic
 __device__ __forceinline__ void hist_add(uint32_t* h, uint32_t dg, bool valid) {
@@ -182,8 +222,10 @@ __device__ __forceinline__ void hist_add(uint32_t* h, uint32_t dg, bool valid) {
   }
 }
 
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
-  __shared__ uint32_t h[kDigits];
+  using R = Rdx<D>;
+  __shared__ __align__(16) uint32_t h[R::kBins];
   __shared__ uint32_t s_max;
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
@@ -198,7 +240,8 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
     const uint32_t t = *a.tagp + 1u;
     *a.tagp = t ? t : 1u;
   }
-  h[tid] = 0;
+#pragma unroll
+  for (int j = 0; j < R::kPer; ++j) h[tid + j * kBlock] = 0;
   // empty the Step-3 query tables (first used by k_est of this step)
   {
     // (slot counts are multiples of 1024, so whole uint4s cover them)
@@ -261,10 +304,10 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
       vmax = max(vmax, max(x.z, x.w));
     }
     // digit 0 only: the later passes count their own input order
-    hist_add(h, x.x & 255u, v01);
-    hist_add(h, x.y & 255u, v01);
-    hist_add(h, x.z & 255u, v23);
-    hist_add(h, x.w & 255u, v23);
+    hist_add(h, x.x & R::kMask, v01);
+    hist_add(h, x.y & R::kMask, v01);
+    hist_add(h, x.z & R::kMask, v23);
+    hist_add(h, x.w & R::kMask, v23);
   }
   if (loop) atomicOr(a.err, kErrSelfLoop);
   if (vmax > a.id_limit) atomicOr(a.err, kErrRange);
@@ -272,7 +315,9 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
   __syncthreads();
   // the block's counts go out with plain stores; the fold sums them, so
   // no global bin takes one atomic per block
-  a.hpart[(size_t)hb * (kPasses * kDigits) + tid] = h[tid];
+  uint32_t v[R::kPer];
+  ld_bins(h, v);
+  st_bins(a.hpart + (size_t)hb * kRowWords, v);
   if (tid == 0) a.mpart[hb] = s_max;
 }
 
@@ -291,13 +336,43 @@ __device__ __forceinline__ uint32_t seg_of_chunk(const StepArgs& a, uint32_t c) 
   return lo;
 }
 
+// row of chunk c's digit sums (pass P) in the chunk-sum array
+template <int D>
 __device__ __forceinline__ uint32_t* csum_row(const StepArgs& a, uint32_t c, int P) {
-  return a.csum + ((size_t)c * kPasses + P) * kDigits;
+  return a.csum + (size_t)c * kRowWords + ((size_t)P << D);
 }
 
-__device__ void fold_chunk(const StepArgs& a, uint32_t c) {
+// row of tile t's digit counts (pass P) in the partial-count array
+template <int D>
+__device__ __forceinline__ uint32_t* cnt_row(const StepArgs& a, uint32_t t, int P) {
+  return a.hpart + (size_t)t * kRowWords + ((size_t)P << D);
+}
+
+// Rows [r0, r1) (at most kChunk, kRowWords apart from `rows`) of one chunk,
+// word d: each row is replaced by the exclusive prefix of the rows before
+// it, and their total is returned.  All loads are in flight at once.
+__device__ __forceinline__ uint32_t chunk_prefix(uint32_t* rows, uint32_t r0, uint32_t r1,
+                                                 uint32_t d) {
+  uint32_t v[kChunk];
+#pragma unroll
+  for (uint32_t i = 0; i < kChunk; ++i)
+    v[i] = r0 + i < r1 ? rows[(size_t)(r0 + i) * kRowWords + d] : 0u;
+  uint32_t run = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kChunk; ++i) {
+    if (r0 + i < r1) rows[(size_t)(r0 + i) * kRowWords + d] = run;
+    run += v[i];
+  }
+  return run;
+}
+
+// block b of the fold: chunk b / kPer, digits (b % kPer) kBlock + [0, kBlock)
+template <int D>
+__device__ void fold_chunk(const StepArgs& a, uint32_t b) {
+  using R = Rdx<D>;
   __shared__ uint32_t s_seg, s_max;
   const int tid = threadIdx.x;
+  const uint32_t c = b / R::kPer, q = b % R::kPer;
   if (tid == 0) {
     s_seg = seg_of_chunk(a, c);
     s_max = 0;
@@ -307,70 +382,70 @@ __device__ void fold_chunk(const StepArgs& a, uint32_t c) {
   const SegDesc S = seg_desc(a, sidx);
   const uint32_t r0 = S.hblk_off + (c - S.chunk_off) * kChunk;
   const uint32_t r1 = min(r0 + kChunk, S.hblk_off + S.nhblk);
-  // all of the chunk's rows in flight at once
-  uint32_t acc = 0;
-  uint32_t v[kChunk];
-#pragma unroll
-  for (uint32_t i = 0; i < kChunk; ++i)
-    v[i] = r0 + i < r1 ? a.hpart[(size_t)(r0 + i) * (kPasses * kDigits) + tid] : 0u;
-#pragma unroll
-  for (uint32_t i = 0; i < kChunk; ++i) acc += v[i];
-  if ((uint32_t)tid < r1 - r0) atomicMax(&s_max, a.mpart[r0 + tid]);
+  const uint32_t d = q * kBlock + tid;
+  const uint32_t tot = chunk_prefix(a.hpart, r0, r1, d);
+  if (q == 0 && (uint32_t)tid < r1 - r0) atomicMax(&s_max, a.mpart[r0 + tid]);
   __syncthreads();
   SegWork* wk = a.work + sidx;
-  csum_row(a, c, 0)[tid] = acc;
-  if (acc) atomicAdd(&wk->hist[0][tid], acc);
-  if (tid == 0) atomicMax(&wk->maxid, s_max);
+  csum_row<D>(a, c, 0)[d] = tot;
+  if (tot) atomicAdd(&wk->hist[d], tot);
+  if (q == 0 && tid == 0) atomicMax(&wk->maxid, s_max);
 }
 
 // ---------------------------------------------------------------------------
-// Radix passes.  Pass P orders the arcs stably by bits 8P..8P+7 of the
+// Radix passes.  Pass P orders the arcs stably by bits DP..DP+D-1 of the
 // vertex id (LSD), by reduce-then-scan: k_cnt<P> counts the digits of every
 // tile, k_csum<P> sums the counts of every chunk of kChunk tiles (and the
-// segment's digit histogram), and k_scat<P> adds up its tile's global
-// offsets from them and moves its arcs.  No block waits for another.
-// Passes above the largest vertex id's top digit are skipped on the device;
-// pass 0 takes its counts from k_hist and the fold.
+// segment's digit histogram) and turns each tile's counts into the prefix
+// of its chunk's earlier tiles, k_cscan<P> turns the chunk sums into chunk
+// bases, and k_scat<P> adds its two offset rows and moves its arcs.  No
+// block waits for another.  Passes above the largest vertex id's top digit
+// are skipped on the device; pass 0 takes its counts from k_hist and the
+// fold.
 // ---------------------------------------------------------------------------
 
 // Pass P runs for a segment iff some vertex id has a nonzero digit at or
-// above P (max id >= 2^(8P)); otherwise digit P is zero for every arc and
+// above P (max id >= 2^(DP)); otherwise digit P is zero for every arc and
 // the pass would leave the order unchanged.  Pass 0 always runs (an edge
 // has two distinct ids), so the passes that run are 0 .. K-1 and pass P
 // reads buffer (P+1)&1 (W for P = 0) and writes buffer P&1.
+template <int D>
 __device__ __forceinline__ bool pass_runs(uint32_t maxid, int P) {
-  return P == 0 || (maxid >> (8 * P)) != 0u;
+  return P == 0 || (maxid >> (D * P)) != 0u;
 }
 
 // bits of digit P that can be nonzero (the match needs only those; used
-// from pass 2 on, where ids often stop short of the digit's top -- on the
-// lower passes the early exit costs more than it saves)
+// from pass 2 on with 8-bit digits, where ids often stop short of the
+// digit's top -- on the lower passes the early exit costs more than it
+// saves -- and on every pass of wide digits)
+template <int D>
 __device__ __forceinline__ int digit_bits(uint32_t maxid, int P) {
-  const uint32_t top = maxid >> (8 * P);
-  return top == 0u ? 1 : min(8, 32 - __clz(top));
+  const uint32_t top = maxid >> (D * P);
+  return top == 0u ? 1 : min(D, 32 - __clz(top));
+}
+template <int D>
+__device__ __forceinline__ bool match_stops(int P) {
+  return P >= 2;
 }
 
-// row of tile t's digit counts (pass P) in the partial-count array
-__device__ __forceinline__ uint32_t* cnt_row(const StepArgs& a, uint32_t t, int P) {
-  return a.hpart + (size_t)t * (kPasses * kDigits) + (size_t)P * kDigits;
-}
-
-template <int P>
+template <int P, int D>
 __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
   static_assert(P >= 1, "k_hist counts the first pass");
-  __shared__ uint32_t s_h[kDigits];
+  using R = Rdx<D>;
+  __shared__ __align__(16) uint32_t s_h[R::kBins];
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   if (tid == 0) s_seg = seg_of_tile(a, blk);
-  s_h[tid] = 0;
+#pragma unroll
+  for (int j = 0; j < R::kPer; ++j) s_h[tid + j * kBlock] = 0;
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
   const uint32_t n = 2u * S.w;
   const uint32_t maxid = uniform(a.work[sidx].maxid);
-  if (!pass_runs(maxid, P)) return;
-  const int nbits = digit_bits(maxid, P);
+  if (!pass_runs<D>(maxid, P)) return;
+  const int nbits = digit_bits<D>(maxid, P);
   const uint32_t base = (blk - S.tile_off) * kTile;
   const uint32_t nv = min((uint32_t)kTile, n - base);
   // high words (vertex ids) of the pass input, read in order
@@ -378,16 +453,19 @@ __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
   uint32_t v[kItems];
 #pragma unroll
   for (int i = 0; i < kItems; ++i) v[i] = hi[2u * min((uint32_t)(i * kBlock + tid), nv - 1)];
+  uint32_t row[R::kPer];
   if (P == 1 && nbits >= 7) {
-    // the second byte of arcs ordered by their first: most lanes of a wave
-    // differ, and one LDS atomic per arc is cheaper than matching equal
-    // digits first.  (From pass 2 on, arcs arrive grouped by their low 16
-    // bits, so a high-degree vertex fills many lanes with one digit.)
+    // the second digit of arcs ordered by their first: most lanes of a
+    // wave differ, and one LDS atomic per arc is cheaper than matching
+    // equal digits first.  (From the third 8-bit digit on, arcs arrive
+    // grouped by their low 16 bits, so a high-degree vertex fills many
+    // lanes with one digit.)
 #pragma unroll
     for (int i = 0; i < kItems; ++i)
-      if ((uint32_t)(i * kBlock + tid) < nv) atomicAdd(&s_h[(v[i] >> (8 * P)) & 255u], 1u);
+      if ((uint32_t)(i * kBlock + tid) < nv) atomicAdd(&s_h[(v[i] >> (D * P)) & R::kMask], 1u);
     __syncthreads();
-    cnt_row(a, blk, P)[tid] = s_h[tid];
+    ld_bins(s_h, row);
+    st_bins(cnt_row<D>(a, blk, P), row);
     return;
   }
   // few digits: lanes with equal digits add once (one atomic per lane
@@ -396,12 +474,12 @@ __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
     const bool valid = (uint32_t)(i * kBlock + tid) < nv;
-    const uint32_t dg = (v[i] >> (8 * P)) & 255u;
+    const uint32_t dg = (v[i] >> (D * P)) & R::kMask;
     const uint64_t vm = __ballot(valid);
     uint32_t lo = (uint32_t)vm, hi2 = (uint32_t)(vm >> 32);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      if (P >= 2 && b >= nbits) break;  // higher digit bits are zero in every arc
+    for (int b = 0; b < D; ++b) {
+      if (match_stops<D>(P) && b >= nbits) break;  // higher digit bits are zero in every arc
       const uint32_t t = (uint32_t)((int32_t)(dg << (31 - b)) >> 31);
       const uint64_t bb = __ballot(t != 0u);
       lo = __builtin_amdgcn_bitop3_b32(lo, t, (uint32_t)bb, 0x90);
@@ -412,42 +490,104 @@ __global__ __launch_bounds__(kBlock) void k_cnt(StepArgs a) {
       atomicAdd(&s_h[dg], (uint32_t)__popcll(mm));
   }
   __syncthreads();
-  cnt_row(a, blk, P)[tid] = s_h[tid];
+  ld_bins(s_h, row);
+  st_bins(cnt_row<D>(a, blk, P), row);
 }
 
-template <int P>
+// block b: chunk b / kPer, digits (b % kPer) kBlock + [0, kBlock): the
+// chunk's tile rows become prefixes, its sums go to csum and into the
+// segment's digit-P histogram
+template <int P, int D>
 __global__ __launch_bounds__(kBlock) void k_csum(StepArgs a) {
   static_assert(P >= 1, "the fold sums the first pass");
+  using R = Rdx<D>;
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
-  if (tid == 0) s_seg = seg_of_chunk(a, blockIdx.x);
+  const uint32_t c = blockIdx.x / R::kPer, q = blockIdx.x % R::kPer;
+  if (tid == 0) s_seg = seg_of_chunk(a, c);
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
   SegWork* wk = a.work + sidx;
-  if (!pass_runs(uniform(wk->maxid), P)) return;
-  const uint32_t t0 = S.tile_off + (blockIdx.x - S.chunk_off) * kChunk;
+  if (!pass_runs<D>(uniform(wk->maxid), P)) return;
+  const uint32_t t0 = S.tile_off + (c - S.chunk_off) * kChunk;
   const uint32_t t1 = min(t0 + kChunk, S.tile_off + S.ntiles);
-  // all of the chunk's rows in flight at once
-  uint32_t acc = 0;
-  uint32_t v[kChunk];
-#pragma unroll
-  for (uint32_t i = 0; i < kChunk; ++i) v[i] = t0 + i < t1 ? cnt_row(a, t0 + i, P)[tid] : 0u;
-#pragma unroll
-  for (uint32_t i = 0; i < kChunk; ++i) acc += v[i];
-  csum_row(a, blockIdx.x, P)[tid] = acc;
-  // the segment's digit-P histogram (the bin starts of the pass)
-  if (acc) atomicAdd(&wk->hist[P][tid], acc);
+  const uint32_t d = q * kBlock + tid;
+  const uint32_t tot = chunk_prefix(cnt_row<D>(a, 0, P), t0, t1, d);
+  csum_row<D>(a, c, P)[d] = tot;
+  if (tot) atomicAdd(&wk->hist[(P << D) + d], tot);
 }
 
-template <int P>
+// block b: segment b / kPer, digits (b % kPer) kBlock + [0, kBlock).  Each
+// chunk sum of pass P becomes the chunk's base: the digit's bin start (an
+// exclusive scan of the segment's digit histogram) plus the digit's arcs in
+// the segment's earlier chunks.  A scatter block then finds its offsets in
+// two rows.  The first kCscanBatch chunk sums are loaded before the scan of
+// the histogram, so the two waits overlap.
+constexpr uint32_t kCscanBatch = 64;
+template <int P, int D>
+__global__ __launch_bounds__(kBlock) void k_cscan(StepArgs a) {
+  using R = Rdx<D>;
+  __shared__ __align__(16) uint32_t s_bin[R::kBins];
+  __shared__ uint32_t s_tmp[kWaves];
+  const int tid = threadIdx.x;
+  const uint32_t sidx = blockIdx.x / R::kPer, q = blockIdx.x % R::kPer;
+  const SegDesc S = seg_desc(a, sidx);
+  SegWork* wk = a.work + sidx;
+  if (!pass_runs<D>(uniform(wk->maxid), P)) return;
+  uint32_t* col = csum_row<D>(a, S.chunk_off, P) + q * kBlock + tid;
+  const uint32_t nc = S.nchunks;
+  uint32_t v[kCscanBatch];
+#pragma unroll
+  for (uint32_t i = 0; i < kCscanBatch; ++i)
+    v[i] = i < nc ? col[(size_t)i * kRowWords] : 0u;
+  uint32_t h[R::kPer], bins[R::kPer], t = 0, tot;
+  ld_bins(wk->hist + (P << D), h);
+#pragma unroll
+  for (int j = 0; j < R::kPer; ++j) t += h[j];
+  uint32_t bin = block_excl_scan(t, s_tmp, &tot);
+#pragma unroll
+  for (int j = 0; j < R::kPer; ++j) {
+    bins[j] = bin;
+    bin += h[j];
+  }
+  st_bins(s_bin, bins);
+  __syncthreads();
+  uint32_t run = s_bin[q * kBlock + tid];
+  for (uint32_t c0 = 0;;) {
+#pragma unroll
+    for (uint32_t i = 0; i < kCscanBatch; ++i) {
+      if (c0 + i < nc) col[(size_t)(c0 + i) * kRowWords] = run;
+      run += v[i];
+    }
+    c0 += kCscanBatch;
+    if (c0 >= nc) break;
+#pragma unroll
+    for (uint32_t i = 0; i < kCscanBatch; ++i)
+      v[i] = c0 + i < nc ? col[(size_t)(c0 + i) * kRowWords] : 0u;
+  }
+}
+
+template <int P, int D>
 __device__ __forceinline__ void scat_body(const StepArgs& a) {
-  __shared__ uint64_t s_el[kTile];
-  __shared__ uint32_t s_wh[kWaves][kDigits];
-  __shared__ uint32_t s_loc[kDigits];
-  __shared__ uint32_t s_dst[kDigits];
+  using R = Rdx<D>;
+  constexpr int kBins = R::kBins, kPer = R::kPer;
+  // 8-bit digits: the per-wave bins and the tile's digit offsets have
+  // arrays of their own (38 KB in all).  Wide digits: both live in the
+  // staging buffer, whose use they precede, so a block still takes 36 KB
+  // rather than 56 and a CU still holds four.
+  constexpr bool kAlias = D > 8;
+  static_assert((kWaves + 1) * kBins * 4 <= kTile * 8, "aliased bins fit the staging buffer");
+  __shared__ __align__(16) uint64_t s_el[kTile];
+  __shared__ __align__(16) uint32_t s_wh_own[kAlias ? 1 : kWaves * kBins];
+  __shared__ __align__(16) uint32_t s_loc_own[kAlias ? 1 : kBins];
+  __shared__ __align__(16) uint32_t s_dst[kBins];
   __shared__ uint32_t s_tmp[kWaves];
   __shared__ uint32_t s_seg;
+  // s_wh[w * kBins + d]: wave w's arcs of digit d, then the offset of that
+  // wave's first one among the tile's; s_loc[d]: the tile's first arc of d
+  uint32_t* const s_wh = kAlias ? reinterpret_cast<uint32_t*>(s_el) : s_wh_own;
+  uint32_t* const s_loc = kAlias ? reinterpret_cast<uint32_t*>(s_el) + kWaves * kBins : s_loc_own;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -461,14 +601,13 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
   if (P == 0 && blk == S.tile_off && tid == 0) {
     int K = 0;  // passes run (the launched ones that do not skip)
 #pragma unroll
-    for (int d = 0; d < kPasses; ++d) K += (d < (int)a.npass && pass_runs(maxid, d)) ? 1 : 0;
+    for (int d = 0; d < kPasses; ++d) K += (d < (int)a.npass && pass_runs<D>(maxid, d)) ? 1 : 0;
     wk->final_buf = (uint32_t)((K + 1) & 1);  // (K - 1) & 1, K >= 1
     const uint64_t span = (uint64_t)maxid + 1;
     wk->dense = span <= (1ull << S.dir_log2) ? 1u : 0u;
   }
-  if (!pass_runs(maxid, P)) return;
-  const int nbits = digit_bits(maxid, P);
-  const uint32_t hist_p = wk->hist[P][tid];
+  if (!pass_runs<D>(maxid, P)) return;
+  const int nbits = digit_bits<D>(maxid, P);
   const uint32_t ltile = blk - S.tile_off;
   const uint64_t* src = a.arcs[(P + 1) & 1] + S.arc_off;
   uint64_t* dst = a.arcs[P & 1] + S.arc_off;
@@ -506,38 +645,20 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
       el[i] = src[gi];
     }
   }
-  // this tile's first arc of digit tid goes to: the digit's bin start +
-  // the arcs of that digit in the segment's earlier chunks + those in this
-  // chunk's earlier tiles (the loads overlap the ranking below)
-  const uint32_t c = ltile / kChunk;
-  uint32_t off = 0;
-  {
-    // rows to add: c chunk sums, then ltile % kChunk tile counts, each
-    // kPasses * kDigits words apart; read in batches of independent loads
-    constexpr uint32_t kRow = kPasses * kDigits;
-    const uint32_t* crow = a.csum + ((size_t)S.chunk_off * kPasses + P) * kDigits + tid;
-    const uint32_t* trow =
-        a.hpart + ((size_t)(S.tile_off + c * kChunk) * kPasses + P) * kDigits + tid;
-    const uint32_t nt = ltile % kChunk;
-    for (uint32_t r0 = 0; r0 < c; r0 += 16) {
-      uint32_t v[16];
+  // this tile's first arc of each of the thread's digits goes to: its
+  // chunk's base for the digit (bin start + the segment's earlier chunks)
+  // + the chunk's earlier tiles (both loads overlap the ranking below)
+  uint32_t off[kPer], pre_t[kPer];
+  ld_bins(csum_row<D>(a, S.chunk_off + ltile / kChunk, P), off);
+  ld_bins(cnt_row<D>(a, S.tile_off + ltile, P), pre_t);
 #pragma unroll
-      for (uint32_t i = 0; i < 16; ++i) v[i] = r0 + i < c ? crow[(size_t)(r0 + i) * kRow] : 0u;
+  for (int j = 0; j < kPer; ++j) off[j] += pre_t[j];
+  // wide digits: parked in the thread's own words of s_dst until the scan
+  // (issued after the arc loads, so the wait costs nothing the ranking
+  // would not wait for anyway), which leaves the ranking more registers
+  if constexpr (kAlias) st_bins(s_dst, off);
 #pragma unroll
-      for (uint32_t i = 0; i < 16; ++i) off += v[i];
-    }
-    for (uint32_t r0 = 0; r0 < nt; r0 += 16) {
-      uint32_t v[16];
-#pragma unroll
-      for (uint32_t i = 0; i < 16; ++i) v[i] = r0 + i < nt ? trow[(size_t)(r0 + i) * kRow] : 0u;
-#pragma unroll
-      for (uint32_t i = 0; i < 16; ++i) off += v[i];
-    }
-  }
-  s_wh[wave][lane] = 0;
-  s_wh[wave][lane + 64] = 0;
-  s_wh[wave][lane + 128] = 0;
-  s_wh[wave][lane + 192] = 0;
+  for (int i = 0; i < kWaves * kPer; ++i) s_wh[tid + i * kBlock] = 0;
   __syncthreads();
 
   // stable rank of each arc among equal digits of its wave: a ballot match
@@ -553,12 +674,12 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
   for (int i = 0; i < kItems; ++i) {
     const uint32_t li = wave * 64 * kItems + i * 64 + lane;
     const bool valid = li < nv;
-    const uint32_t dg = (uint32_t)(el[i] >> (32 + 8 * P)) & 255u;
+    const uint32_t dg = (uint32_t)(el[i] >> (32 + D * P)) & R::kMask;
     const uint64_t vm = __ballot(valid);
     uint32_t lo = (uint32_t)vm, hi = (uint32_t)(vm >> 32);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      if (P >= 2 && b >= nbits) break;  // higher digit bits are zero in every arc
+    for (int b = 0; b < D; ++b) {
+      if (match_stops<D>(P) && b >= nbits) break;  // higher digit bits are zero in every arc
       const uint32_t t = (uint32_t)((int32_t)(dg << (31 - b)) >> 31);  // 0 or ~0
       const uint64_t bb = __ballot(t != 0u);
       lo = __builtin_amdgcn_bitop3_b32(lo, t, (uint32_t)bb, 0x90);
@@ -567,7 +688,7 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
     const uint64_t mm = ((uint64_t)hi << 32) | lo;
     const uint32_t below = __popcll(mm & lt_mask);
     uint32_t bse = 0;
-    if (valid && below == 0) bse = atomicAdd(&s_wh[wave][dg], (uint32_t)__popcll(mm));
+    if (valid && below == 0) bse = atomicAdd(&s_wh[wave * kBins + dg], (uint32_t)__popcll(mm));
     rk[i] = bse;
     lb[i] = (((uint32_t)__ffsll((long long)mm) - 1u) & 63u) | (below << 8);
   }
@@ -576,33 +697,64 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
     rk[i] = __shfl(rk[i], (int)(lb[i] & 63u)) + (lb[i] >> 8);
   __syncthreads();
 
-  // per digit (thread = digit): wave offsets, tile count, tile offsets
-  uint32_t cnt = 0;
+  // per digit (thread = kPer digits): wave offsets, tile counts, tile
+  // offsets and the global destination of the tile's first arc of each
+  uint32_t cnt[kPer] = {};
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) {
-    const uint32_t cw = s_wh[w][tid];
-    s_wh[w][tid] = cnt;
-    cnt += cw;
+    uint32_t cw[kPer], pre[kPer];
+    ld_bins(s_wh + w * kBins, cw);
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      pre[j] = cnt[j];
+      cnt[j] += cw[j];
+    }
+    st_bins(s_wh + w * kBins, pre);
   }
-  uint32_t tot;
-  s_loc[tid] = block_excl_scan(cnt, s_tmp, &tot);
-  const uint32_t bin = block_excl_scan(hist_p, s_tmp, &tot);
-  s_dst[tid] = bin + off - s_loc[tid];
+  if constexpr (kAlias) ld_bins(s_dst, off);
+  uint32_t ctot = 0, tot;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) ctot += cnt[j];
+  uint32_t loc = block_excl_scan(ctot, s_tmp, &tot);
+  uint32_t locs[kPer], dsts[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    locs[j] = loc;
+    dsts[j] = off[j] - loc;
+    loc += cnt[j];
+  }
+  st_bins(s_loc, locs);
+  st_bins(s_dst, dsts);
   __syncthreads();
 
   // scatter into LDS in digit order, then write runs out coalesced
+  if constexpr (kAlias) {
+    // every position is read before the staging buffer is overwritten
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    const uint32_t li = wave * 64 * kItems + i * 64 + lane;
-    if (li < nv) {
-      const uint32_t dg = (uint32_t)(el[i] >> (32 + 8 * P)) & 255u;
-      s_el[s_loc[dg] + s_wh[wave][dg] + rk[i]] = el[i];
+    for (int i = 0; i < kItems; ++i) {
+      const uint32_t dg = (uint32_t)(el[i] >> (32 + D * P)) & R::kMask;
+      rk[i] += s_loc[dg] + s_wh[wave * kBins + dg];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const uint32_t li = wave * 64 * kItems + i * 64 + lane;
+      if (li < nv) s_el[rk[i]] = el[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const uint32_t li = wave * 64 * kItems + i * 64 + lane;
+      if (li < nv) {
+        const uint32_t dg = (uint32_t)(el[i] >> (32 + D * P)) & R::kMask;
+        s_el[s_loc[dg] + s_wh[wave * kBins + dg] + rk[i]] = el[i];
+      }
     }
   }
   __syncthreads();
   for (uint32_t i = tid; i < nv; i += kBlock) {
     const uint64_t e = s_el[i];
-    const uint32_t dg = (uint32_t)(e >> (32 + 8 * P)) & 255u;
+    const uint32_t dg = (uint32_t)(e >> (32 + D * P)) & R::kMask;
     dst[s_dst[dg] + i] = e;
   }
 }
@@ -610,15 +762,16 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
 // The body needs about 140 registers; passes whose build fits in 128
 // without spilling run with four waves per SIMD (one more block per CU),
 // the others (the first pass reads W and the need bytes and sets up the
-// directory mode; the last one) with three.
-template <int P>
+// directory mode; the last 8-bit one) with three.
+template <int P, int D>
 __global__ __launch_bounds__(kBlock) void k_scat(StepArgs a) {
-  scat_body<P>(a);
+  scat_body<P, D>(a);
 }
-template <int P>
+template <int P, int D>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_scat4(StepArgs a) {
-  scat_body<P>(a);
+  scat_body<P, D>(a);
 }
+
 
 // ---------------------------------------------------------------------------
 // k_step1: Step 1 (Sec. 4.2) draws for every estimator; the replacement
@@ -646,9 +799,11 @@ __device__ void step1_block(const StepArgs& a, uint32_t blk) {
 
 // one launch for two independent jobs: blocks [0, nchunk) fold the k_hist
 // counts, the rest run Step 1
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_fold_step1(StepArgs a) {
-  if (blockIdx.x < a.nchunk) fold_chunk(a, blockIdx.x);
-  else step1_block(a, blockIdx.x - a.nchunk);
+  const uint32_t nfold = a.nchunk * (uint32_t)Rdx<D>::kPer;
+  if (blockIdx.x < nfold) fold_chunk<D>(a, blockIdx.x);
+  else step1_block(a, blockIdx.x - nfold);
 }
 
 // ---------------------------------------------------------------------------
@@ -1257,6 +1412,37 @@ __global__ __launch_bounds__(kBlock) void k_fill32(uint32_t* p, uint64_t n,
 // on another stream, overlapping the next step's phase A.  ev: optional
 // 2 * kNumKernels events; kernel k is bracketed by ev[2k] and ev[2k+1]
 // when those are non-null (untimed kernels get no event).
+// the grouping sort of one step with D-bit digits: launch 0 k_hist, 1 the
+// fold (and Step 1), 2 k_cscan<0>, 3 k_scat<0>; pass P >= 1 is launches
+// 4 + 4 (P - 1) + {k_cnt, k_csum, k_cscan, k_scat}.  Passes above the
+// declared vertex bound are not launched (k_hist reports an id above it).
+template <int D, class Run>
+void launch_sort(const StepArgs& a, hipStream_t st, Run& run) {
+  constexpr uint32_t kPer = Rdx<D>::kPer;
+  const dim3 blk(kBlock), tiles(a.ntiles);
+  const dim3 chunks(a.nchunk * kPer), segs(a.nseg * kPer);
+  run(0, [&] { hipLaunchKernelGGL(k_hist<D>, dim3(a.nhblk), blk, 0, st, a); });
+  run(1, [&] {
+    hipLaunchKernelGGL(k_fold_step1<D>, dim3(a.nchunk * kPer + a.nstep1), blk, 0, st, a);
+  });
+  run(2, [&] { hipLaunchKernelGGL((k_cscan<0, D>), segs, blk, 0, st, a); });
+  run(3, [&] { hipLaunchKernelGGL((k_scat<0, D>), tiles, blk, 0, st, a); });
+  auto pass = [&](int P, auto cntk, auto csumk, auto cscank, auto scatk) {
+    const int k = 4 + 4 * (P - 1);
+    run(k, [&] { hipLaunchKernelGGL(cntk, tiles, blk, 0, st, a); });
+    run(k + 1, [&] { hipLaunchKernelGGL(csumk, chunks, blk, 0, st, a); });
+    run(k + 2, [&] { hipLaunchKernelGGL(cscank, segs, blk, 0, st, a); });
+    run(k + 3, [&] { hipLaunchKernelGGL(scatk, tiles, blk, 0, st, a); });
+  };
+  if constexpr (D == 8) {
+    if (a.npass > 1) pass(1, k_cnt<1, 8>, k_csum<1, 8>, k_cscan<1, 8>, k_scat4<1, 8>);
+    if (a.npass > 2) pass(2, k_cnt<2, 8>, k_csum<2, 8>, k_cscan<2, 8>, k_scat4<2, 8>);
+    if (a.npass > 3) pass(3, k_cnt<3, 8>, k_csum<3, 8>, k_cscan<3, 8>, k_scat<3, 8>);
+  } else {
+    if (a.npass > 1) pass(1, k_cnt<1, D>, k_csum<1, D>, k_cscan<1, D>, k_scat4<1, D>);
+  }
+}
+
 hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st,
                         hipEvent_t* ev) {
   const dim3 blk(kBlock);
@@ -1269,24 +1455,12 @@ hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st,
     if (t) (void)hipEventRecord(ev[2 * k + 1], st);
   };
   if (phase == 0) {
-    run(0, [&] { hipLaunchKernelGGL(k_hist, dim3(a.nhblk), blk, 0, st, a); });
-    run(1, [&] {
-      hipLaunchKernelGGL(k_fold_step1, dim3(a.nchunk + a.nstep1), blk, 0, st, a);
-    });
-    const dim3 chunks(a.nchunk);
-    run(2, [&] { hipLaunchKernelGGL(k_scat<0>, tiles, blk, 0, st, a); });
-    // launch k of pass P (P >= 1) is 3 + 3 (P - 1) + {0, 1, 2}
-    auto pass = [&](int P, auto cntk, auto csumk, auto scatk) {
-      const int k = 3 + 3 * (P - 1);
-      run(k, [&] { hipLaunchKernelGGL(cntk, tiles, blk, 0, st, a); });
-      run(k + 1, [&] { hipLaunchKernelGGL(csumk, chunks, blk, 0, st, a); });
-      run(k + 2, [&] { hipLaunchKernelGGL(scatk, tiles, blk, 0, st, a); });
-    };
-    // passes above the declared vertex bound are not launched (k_hist
-    // reports an id above it)
-    if (a.npass > 1) pass(1, k_cnt<1>, k_csum<1>, k_scat4<1>);
-    if (a.npass > 2) pass(2, k_cnt<2>, k_csum<2>, k_scat4<2>);
-    if (a.npass > 3) pass(3, k_cnt<3>, k_csum<3>, k_scat<3>);
+    if (a.dbits == (uint32_t)kWideBits) {
+      static_assert(kWidePasses == 2, "wide digits take two passes");
+      launch_sort<kWideBits>(a, st, run);
+    } else {
+      launch_sort<8>(a, st, run);
+    }
     run(kNumKernels - 4, [&] { hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a); });
   } else if (phase == 1) {
     run(kNumKernels - 3, [&] { hipLaunchKernelGGL(k_est, ests, blk, 0, st, a); });

@@ -608,9 +608,111 @@ def test_kernel_timing_with_bound(tc):
     g.process(E[1500:])
     times, steps = tc.tc_kernel_times(g.h)
     assert steps == 2
-    assert times["k_scat<0>"] > 0 and times["k_est"] > 0
+    assert times["k_scat<0>"] > 0 and times["k_cscan<0>"] > 0 and times["k_est"] > 0
     for p in (1, 2, 3):
-        assert times[f"k_scat<{p}>"] == 0.0 and times[f"k_cnt<{p}>"] == 0.0
+        for k in ("k_cnt", "k_csum", "k_cscan", "k_scat"):
+            assert times[f"{k}<{p}>"] == 0.0
+
+
+# -- 10-bit digits: a declared bound of 17 to 20 bits sorts in two passes ----------
+
+def _spread_ids(E: np.ndarray, bound: int, seed: int) -> np.ndarray:
+    """E's ids (all below `bound`) sent through x -> (A x + B) mod bound with
+    gcd(A, bound) = 1: a bijection of [0, bound) that spreads them over the
+    whole range, so every digit bit varies."""
+    import math
+    rng = np.random.default_rng(seed)
+    while True:
+        A = int(rng.integers(max(2, bound // 16), bound))
+        if math.gcd(A, bound) == 1:
+            break
+    B = int(rng.integers(0, bound))
+    return ((E.astype(np.uint64) * A + B) % bound).astype(np.uint32)
+
+
+@pytest.mark.parametrize("bound,w", [((1 << 16) + 1, 300001), ((1 << 18) + 5, 100003),
+                                     (1 << 20, 65537), (1 << 20, 257)])
+def test_wide_digit_bounds(tc, bound, w):
+    # several radix chunks of 32 tiles (2w > 131072 arcs) with a ragged
+    # tail, ids over the whole bound, two passes of 10-bit digits
+    n = min(bound, 60000)
+    E = _spread_ids(np_edges(inputs.gnm(n, 3 * w + 17, seed=w)), bound, seed=w)
+    assert int(E.max()) < bound
+    dev = to_dev(E)
+    g, o = tc.Bank(5000, 7), O.Bank(5000, 7)
+    tc.tc_set_vertex_bound(g.h, bound)
+    for k, j in enumerate(range(0, len(E), w)):
+        g.process(dev[j:j + w])
+        assert o.process(E[j:j + w]) == O.OK
+        assert_same(g.state(), o.state(), f"bound {bound} batch {k}")
+    assert tc.tc_estimate_ex(g.h)[0] == o.sum()
+
+
+def test_wide_digit_rmat_skew(tc):
+    # R-MAT ids (scale 20, so the bound is 2^20): a few vertices fill whole
+    # waves with one digit, which the ballot match groups
+    E = np_edges(inputs.rmat(20, 600000, seed=5))
+    g = tc.Bank(20000, 3)
+    tc.tc_set_vertex_bound(g.h, 1 << 20)
+    g.process_stream(to_dev(E), 200000)
+    o = O.run_stream(E, 20000, 3, 200000)
+    assert_same(g.state(), o.state(), "rmat scale 20, bound 2^20")
+
+
+@pytest.mark.parametrize("id_bits", [10, 15])
+def test_wide_digit_bound_above_the_ids(tc, id_bits):
+    # bound 2^20 but every id below 2^10 (the second pass finds its digit
+    # zero everywhere and skips on the device) or below 2^15 (its digit has
+    # five bits, few enough that the count matches equal digits first)
+    E = _spread_ids(np_edges(inputs.gnm(1000, 60000, seed=8)), 1 << id_bits, id_bits)
+    g = tc.Bank(3000, 4)
+    tc.tc_set_vertex_bound(g.h, 1 << 20)
+    g.process_stream(to_dev(E), 20000)
+    assert_same(g.state(), O.run_stream(E, 3000, 4, 20000).state(), f"ids below 2^{id_bits}")
+
+
+def test_wide_digit_multi(tc):
+    rs, seeds, w = [900, 4000, 1], [5, 6, 7], 70001
+    Es = [_spread_ids(np_edges(inputs.gnm(20000, 2 * w + 99 * b, seed=60 + b)), 1 << 19, b)
+          for b in range(3)]
+    mb = tc.MultiBank(rs, seeds)
+    tc.tc_multi_set_vertex_bound(mb.h, 1 << 19)
+    for k in range(3):
+        mb.process([0, 1, 2], [to_dev(E[k * w:(k + 1) * w]) for E in Es])
+    for b in range(3):
+        assert_same(mb.state(b), O.run_stream(Es[b], rs[b], seeds[b], w).state(), f"bank {b}")
+
+
+def test_wide_digit_kernel_timing(tc):
+    # a 20-bit bound launches passes 0 and 1 only
+    E = to_dev(_spread_ids(np_edges(inputs.gnm(5000, 40000, seed=9)), 1 << 20, 9))
+    g = tc.Bank(1000, 2)
+    tc.tc_set_vertex_bound(g.h, 1 << 20)
+    tc.tc_set_kernel_timing(g.h, True)
+    g.process(E[:20000])
+    g.process(E[20000:])
+    times, steps = tc.tc_kernel_times(g.h)
+    assert steps == 2
+    for k in ("k_cnt", "k_csum", "k_cscan", "k_scat"):
+        assert times[f"{k}<1>"] > 0
+        for p in (2, 3):
+            assert times[f"{k}<{p}>"] == 0.0
+
+
+@pytest.mark.parametrize("bound,bad_id", [((1 << 17) + 1, (1 << 17) + 100),
+                                          ((1 << 20) - 3, (1 << 20) + 7)])
+def test_wide_digit_bound_violation(tc, bound, bad_id):
+    E = _spread_ids(np_edges(inputs.gnm(3000, 20000, seed=3)), bound, 3)
+    g = tc.Bank(800, 3)
+    tc.tc_set_vertex_bound(g.h, bound)
+    g.process(to_dev(E[:10000]))
+    g.sync()
+    bad = E[10000:].copy()
+    bad[123] = (bad[123][0], bad_id)
+    g.process(to_dev(bad))
+    with pytest.raises(tc.TcError) as ei:
+        g.sync()
+    assert ei.value.code == tc.TC_EINVAL
 
 
 # -- median-of-means aggregate -----------------------------------------------------
