@@ -518,33 +518,51 @@ __global__ __launch_bounds__(kBlock) void k_csum(StepArgs a) {
   if (tot) atomicAdd(&wk->hist[(P << D) + d], tot);
 }
 
-// block b: segment b / kPer, digits (b % kPer) kBlock + [0, kBlock).  Each
-// chunk sum of pass P becomes the chunk's base: the digit's bin start (an
-// exclusive scan of the segment's digit histogram) plus the digit's arcs in
-// the segment's earlier chunks.  A scatter block then finds its offsets in
-// two rows.  The first kCscanBatch chunk sums are loaded before the scan of
-// the histogram, so the two waits overlap.
+// Each chunk sum of pass P becomes the chunk's base: the digit's bin start
+// (an exclusive scan of the segment's digit histogram) plus the digit's
+// arcs in the segment's earlier chunks.  A scatter block then finds its
+// offsets in two rows.  Block b serves segment b / (kBins / 64) and the 64
+// digits 64 (b % (kBins / 64)) + lane; wave w takes the w-th quarter of the
+// segment's chunks, whose first kCscanBatch sums are loaded before the scan
+// of the histogram (so the two waits overlap) and stay in registers (a
+// quarter of more chunks loads the rest twice, in smaller batches).
 constexpr uint32_t kCscanBatch = 64;
+constexpr uint32_t kCscanMore = 16;  // loads per batch past the first
 template <int P, int D>
 __global__ __launch_bounds__(kBlock) void k_cscan(StepArgs a) {
   using R = Rdx<D>;
+  constexpr uint32_t kGroups = R::kBins / 64;  // 64-digit groups per segment
   __shared__ __align__(16) uint32_t s_bin[R::kBins];
+  __shared__ uint32_t s_part[kWaves][64];
   __shared__ uint32_t s_tmp[kWaves];
-  const int tid = threadIdx.x;
-  const uint32_t sidx = blockIdx.x / R::kPer, q = blockIdx.x % R::kPer;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t sidx = blockIdx.x / kGroups;
+  const uint32_t d = (blockIdx.x % kGroups) * 64 + lane;
   const SegDesc S = seg_desc(a, sidx);
   SegWork* wk = a.work + sidx;
   if (!pass_runs<D>(uniform(wk->maxid), P)) return;
-  uint32_t* col = csum_row<D>(a, S.chunk_off, P) + q * kBlock + tid;
   const uint32_t nc = S.nchunks;
-  uint32_t v[kCscanBatch];
+  const uint32_t per = (nc + kWaves - 1) / kWaves;
+  const uint32_t c_lo = min((uint32_t)wave * per, nc), c_hi = min(c_lo + per, nc);
+  uint32_t* col = csum_row<D>(a, S.chunk_off, P) + d;
+  uint32_t v[kCscanBatch], sum = 0;
 #pragma unroll
   for (uint32_t i = 0; i < kCscanBatch; ++i)
-    v[i] = i < nc ? col[(size_t)i * kRowWords] : 0u;
+    v[i] = c_lo + i < c_hi ? col[(size_t)(c_lo + i) * kRowWords] : 0u;
   uint32_t h[R::kPer], bins[R::kPer], t = 0, tot;
   ld_bins(wk->hist + (P << D), h);
 #pragma unroll
   for (int j = 0; j < R::kPer; ++j) t += h[j];
+#pragma unroll
+  for (uint32_t i = 0; i < kCscanBatch; ++i) sum += v[i];
+  for (uint32_t c0 = c_lo + kCscanBatch; c0 < c_hi; c0 += kCscanMore) {
+    uint32_t u[kCscanMore];
+#pragma unroll
+    for (uint32_t i = 0; i < kCscanMore; ++i)
+      u[i] = c0 + i < c_hi ? col[(size_t)(c0 + i) * kRowWords] : 0u;
+#pragma unroll
+    for (uint32_t i = 0; i < kCscanMore; ++i) sum += u[i];
+  }
   uint32_t bin = block_excl_scan(t, s_tmp, &tot);
 #pragma unroll
   for (int j = 0; j < R::kPer; ++j) {
@@ -552,19 +570,26 @@ __global__ __launch_bounds__(kBlock) void k_cscan(StepArgs a) {
     bin += h[j];
   }
   st_bins(s_bin, bins);
+  s_part[wave][lane] = sum;
   __syncthreads();
-  uint32_t run = s_bin[q * kBlock + tid];
-  for (uint32_t c0 = 0;;) {
+  uint32_t run = s_bin[d];
 #pragma unroll
-    for (uint32_t i = 0; i < kCscanBatch; ++i) {
-      if (c0 + i < nc) col[(size_t)(c0 + i) * kRowWords] = run;
-      run += v[i];
+  for (int k = 0; k < kWaves; ++k) run += k < wave ? s_part[k][lane] : 0u;
+#pragma unroll
+  for (uint32_t i = 0; i < kCscanBatch; ++i) {
+    if (c_lo + i < c_hi) col[(size_t)(c_lo + i) * kRowWords] = run;
+    run += v[i];
+  }
+  for (uint32_t c0 = c_lo + kCscanBatch; c0 < c_hi; c0 += kCscanMore) {
+    uint32_t u[kCscanMore];
+#pragma unroll
+    for (uint32_t i = 0; i < kCscanMore; ++i)
+      u[i] = c0 + i < c_hi ? col[(size_t)(c0 + i) * kRowWords] : 0u;
+#pragma unroll
+    for (uint32_t i = 0; i < kCscanMore; ++i) {
+      if (c0 + i < c_hi) col[(size_t)(c0 + i) * kRowWords] = run;
+      run += u[i];
     }
-    c0 += kCscanBatch;
-    if (c0 >= nc) break;
-#pragma unroll
-    for (uint32_t i = 0; i < kCscanBatch; ++i)
-      v[i] = c0 + i < nc ? col[(size_t)(c0 + i) * kRowWords] : 0u;
   }
 }
 
@@ -1420,7 +1445,7 @@ template <int D, class Run>
 void launch_sort(const StepArgs& a, hipStream_t st, Run& run) {
   constexpr uint32_t kPer = Rdx<D>::kPer;
   const dim3 blk(kBlock), tiles(a.ntiles);
-  const dim3 chunks(a.nchunk * kPer), segs(a.nseg * kPer);
+  const dim3 chunks(a.nchunk * kPer), segs(a.nseg * (Rdx<D>::kBins / 64));
   run(0, [&] { hipLaunchKernelGGL(k_hist<D>, dim3(a.nhblk), blk, 0, st, a); });
   run(1, [&] {
     hipLaunchKernelGGL(k_fold_step1<D>, dim3(a.nchunk * kPer + a.nstep1), blk, 0, st, a);
