@@ -98,8 +98,9 @@ int tc_process_stream(tc_state *s, const uint32_t *edges, uint64_t m,
 
 /* Declare that every vertex id of this bank's stream is below n
  * (2 <= n <= 2^32; the default is 2^32).  The grouping sort then runs only
- * as many 8-bit radix passes as n - 1 has bytes, fewer kernel launches per
- * batch.  An id >= n in a later batch is detected on the device: that step
+ * as many radix passes as n - 1 needs: its bytes in 8-bit digits, or two
+ * passes of 10-bit digits when n - 1 has 17 to 20 bits; fewer kernel
+ * launches per batch.  An id >= n in a later batch is detected on the device: that step
  * is abandoned and the next synchronising call returns TC_EINVAL (sticky;
  * the bank is then unspecified).  Applies to batches enqueued afterwards.
  * TC_EINVAL for n out of range. */

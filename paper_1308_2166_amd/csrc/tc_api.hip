@@ -75,11 +75,14 @@ void dfree(T*& p) {
 }
 
 // kernels (bit k = launch k of a step) that a step with npass radix passes
-// launches: the four kernels of each pass at or above npass are skipped
-uint32_t launched_kernels(uint32_t npass) {
+// launches: the four kernels of each pass at or above npass are skipped,
+// and every pass's k_cscan when the step's segments are single chunks
+uint32_t launched_kernels(uint32_t npass, bool single_chunk) {
   uint32_t m = (1u << kNumKernels) - 1u;
   for (uint32_t p = npass < 1 ? 1 : npass; p < (uint32_t)kPasses; ++p)
     m &= ~(15u << (4 + 4 * (p - 1)));
+  if (single_chunk)
+    for (uint32_t p = 0; p < (uint32_t)kPasses; ++p) m &= ~(1u << (2 + 4 * p));
   return m;
 }
 
@@ -448,6 +451,7 @@ struct Engine {
     a.id_limit = id_limit;
     a.npass = npass;
     a.dbits = dbits;
+    a.single_chunk = dbits == 8 && chunks == segs.size() ? 1u : 0u;
     if (a.nseg > 1) {
       rc = stage_descs(segs, P.segs, st, capturing);
       if (rc) return rc;
@@ -465,7 +469,7 @@ struct Engine {
               return fail(TC_EHIP, "hipEventCreate failed");
       }
       ev_pending.push_back(ev);
-      ev_launched.push_back(launched_kernels(npass));
+      ev_launched.push_back(launched_kernels(npass, a.single_chunk != 0));
     }
     // A: group the batch; B: Steps 1-2, after the previous step's Step 3;
     // C: Step 3, on st2 when it may overlap the next step's A

@@ -110,8 +110,8 @@ struct DirSlot {
 // waits for (0 = free), which is what a probe scans.  The edge itself and
 // the first batch position that closes it are the owner's qq and qthr
 // entries.  Every waiting estimator owns one slot (equal edges share a
-// probe cluster).  Owners and fingerprints are reset at the start of every
-// step.
+// probe cluster).  Owners and fingerprints are reset during every step's
+// grouping (by spare blocks of k_cscan<0>), before k_est first claims.
 
 struct StepArgs {
   const SegDesc* segs;    // device copy of all segment descriptors
@@ -151,6 +151,10 @@ struct StepArgs {
   uint32_t npass;         // radix passes launched: the number of D-bit
                           // digits of the bound (1..kPasses)
   uint32_t dbits;         // digit width D: 8 or kWideBits
+  uint32_t single_chunk;  // 1: every segment is one radix chunk and D = 8;
+                          // the count sums then write each chunk's bin
+                          // starts as its bases, no k_cscan runs, and
+                          // k_hist clears the query tables
 };
 
 // arguments of the per-estimator (naive) step: one bank, one batch

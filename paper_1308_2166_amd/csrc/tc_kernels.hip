@@ -207,6 +207,21 @@ __device__ __forceinline__ void st_bins(uint32_t* p, const uint32_t (&v)[N]) {
   }
 }
 
+// Blocks [0, nb) of a launch empty the Step-3 query tables (first used by
+// k_est of this step); slot counts are multiples of 1024, so whole uint4s
+// cover them.  Run by spare blocks of k_cscan<0>, whose scan blocks are
+// few and bound by latency, so the stores use bandwidth that would idle
+// (by k_hist when no k_cscan runs).
+constexpr uint32_t kClearBlocks = 1024;
+__device__ void clear_qtables(const StepArgs& a, uint32_t b, uint32_t nb) {
+  const uint64_t t0 = (uint64_t)b * kBlock + threadIdx.x, step = (uint64_t)nb * kBlock;
+  uint4* o4 = reinterpret_cast<uint4*>(a.qt);
+  const uint4 none = make_uint4(kNone, kNone, kNone, kNone);
+  for (uint64_t t = t0; t < a.qt_slots / 4; t += step) o4[t] = none;
+  uint4* f4 = reinterpret_cast<uint4*>(a.qfp);
+  for (uint64_t t = t0; t < a.qt_slots / 16; t += step) f4[t] = make_uint4(0, 0, 0, 0);
+}
+
 // ---------------------------------------------------------------------------
 // k_hist: per-tile counts of digit 0 of the arc keys
 // ---------------------------------------------------------------------------
@@ -242,18 +257,10 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
   }
 #pragma unroll
   for (int j = 0; j < R::kPer; ++j) h[tid + j * kBlock] = 0;
-  // empty the Step-3 query tables (first used by k_est of this step)
+  // clear the need bytes (Step 1 marks them next; the query tables are
+  // cleared by spare blocks of k_cscan<0>, or here when it does not run)
+  if (a.single_chunk) clear_qtables(a, hb, a.nhblk);
   {
-    // (slot counts are multiples of 1024, so whole uint4s cover them)
-    uint4* o4 = reinterpret_cast<uint4*>(a.qt);
-    const uint4 none = make_uint4(kNone, kNone, kNone, kNone);
-    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.qt_slots / 4;
-         t += (uint64_t)a.nhblk * kBlock)
-      o4[t] = none;
-    uint4* f4 = reinterpret_cast<uint4*>(a.qfp);
-    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.qt_slots / 16;
-         t += (uint64_t)a.nhblk * kBlock)
-      f4[t] = make_uint4(0, 0, 0, 0);
     uint4* n4 = reinterpret_cast<uint4*>(a.need);
     for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.need_bytes / 16;
          t += (uint64_t)a.nhblk * kBlock)
@@ -348,6 +355,22 @@ __device__ __forceinline__ uint32_t* cnt_row(const StepArgs& a, uint32_t t, int 
   return a.hpart + (size_t)t * kRowWords + ((size_t)P << D);
 }
 
+// What a count-sum block stores for its chunk: the chunk's sum of digit
+// threadIdx.x (k_cscan turns it into the chunk's base), or, when every
+// segment is a single chunk and one block holds all 256 digits, the base
+// itself: the digit's bin start, an exclusive scan of those sums.
+template <int D>
+__device__ __forceinline__ uint32_t single_chunk_base(const StepArgs& a, uint32_t tot) {
+  if constexpr (D == 8) {
+    __shared__ uint32_t s_tmp[kWaves];
+    if (a.single_chunk) {
+      uint32_t all;
+      return block_excl_scan(tot, s_tmp, &all);
+    }
+  }
+  return tot;
+}
+
 // Rows [r0, r1) (at most kChunk, kRowWords apart from `rows`) of one chunk,
 // word d: each row is replaced by the exclusive prefix of the rows before
 // it, and their total is returned.  All loads are in flight at once.
@@ -387,7 +410,7 @@ __device__ void fold_chunk(const StepArgs& a, uint32_t b) {
   if (q == 0 && (uint32_t)tid < r1 - r0) atomicMax(&s_max, a.mpart[r0 + tid]);
   __syncthreads();
   SegWork* wk = a.work + sidx;
-  csum_row<D>(a, c, 0)[d] = tot;
+  csum_row<D>(a, c, 0)[d] = single_chunk_base<D>(a, tot);
   if (tot) atomicAdd(&wk->hist[d], tot);
   if (q == 0 && tid == 0) atomicMax(&wk->maxid, s_max);
 }
@@ -514,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_csum(StepArgs a) {
   const uint32_t t1 = min(t0 + kChunk, S.tile_off + S.ntiles);
   const uint32_t d = q * kBlock + tid;
   const uint32_t tot = chunk_prefix(cnt_row<D>(a, 0, P), t0, t1, d);
-  csum_row<D>(a, c, P)[d] = tot;
+  csum_row<D>(a, c, P)[d] = single_chunk_base<D>(a, tot);
   if (tot) atomicAdd(&wk->hist[(P << D) + d], tot);
 }
 
@@ -528,6 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_csum(StepArgs a) {
 // quarter of more chunks loads the rest twice, in smaller batches).
 constexpr uint32_t kCscanBatch = 64;
 constexpr uint32_t kCscanMore = 16;  // loads per batch past the first
+
 template <int P, int D>
 __global__ __launch_bounds__(kBlock) void k_cscan(StepArgs a) {
   using R = Rdx<D>;
@@ -535,6 +559,10 @@ __global__ __launch_bounds__(kBlock) void k_cscan(StepArgs a) {
   __shared__ __align__(16) uint32_t s_bin[R::kBins];
   __shared__ uint32_t s_part[kWaves][64];
   __shared__ uint32_t s_tmp[kWaves];
+  if (P == 0 && blockIdx.x >= a.nseg * kGroups) {
+    clear_qtables(a, blockIdx.x - a.nseg * kGroups, gridDim.x - a.nseg * kGroups);
+    return;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t sidx = blockIdx.x / kGroups;
   const uint32_t d = (blockIdx.x % kGroups) * 64 + lane;
@@ -1440,23 +1468,28 @@ __global__ __launch_bounds__(kBlock) void k_fill32(uint32_t* p, uint64_t n,
 // the grouping sort of one step with D-bit digits: launch 0 k_hist, 1 the
 // fold (and Step 1), 2 k_cscan<0>, 3 k_scat<0>; pass P >= 1 is launches
 // 4 + 4 (P - 1) + {k_cnt, k_csum, k_cscan, k_scat}.  Passes above the
-// declared vertex bound are not launched (k_hist reports an id above it).
+// declared vertex bound are not launched (k_hist reports an id above it),
+// nor is k_cscan when every segment is a single chunk (8-bit digits).
 template <int D, class Run>
 void launch_sort(const StepArgs& a, hipStream_t st, Run& run) {
   constexpr uint32_t kPer = Rdx<D>::kPer;
   const dim3 blk(kBlock), tiles(a.ntiles);
   const dim3 chunks(a.nchunk * kPer), segs(a.nseg * (Rdx<D>::kBins / 64));
+  const uint32_t nclear = (uint32_t)std::min<uint64_t>(
+      kClearBlocks, (a.qt_slots / 4 + kBlock - 1) / kBlock);
+  const dim3 segs_clear(a.nseg * (Rdx<D>::kBins / 64) + nclear);
   run(0, [&] { hipLaunchKernelGGL(k_hist<D>, dim3(a.nhblk), blk, 0, st, a); });
   run(1, [&] {
     hipLaunchKernelGGL(k_fold_step1<D>, dim3(a.nchunk * kPer + a.nstep1), blk, 0, st, a);
   });
-  run(2, [&] { hipLaunchKernelGGL((k_cscan<0, D>), segs, blk, 0, st, a); });
+  if (!a.single_chunk)
+    run(2, [&] { hipLaunchKernelGGL((k_cscan<0, D>), segs_clear, blk, 0, st, a); });
   run(3, [&] { hipLaunchKernelGGL((k_scat<0, D>), tiles, blk, 0, st, a); });
   auto pass = [&](int P, auto cntk, auto csumk, auto cscank, auto scatk) {
     const int k = 4 + 4 * (P - 1);
     run(k, [&] { hipLaunchKernelGGL(cntk, tiles, blk, 0, st, a); });
     run(k + 1, [&] { hipLaunchKernelGGL(csumk, chunks, blk, 0, st, a); });
-    run(k + 2, [&] { hipLaunchKernelGGL(cscank, segs, blk, 0, st, a); });
+    if (!a.single_chunk) run(k + 2, [&] { hipLaunchKernelGGL(cscank, segs, blk, 0, st, a); });
     run(k + 3, [&] { hipLaunchKernelGGL(scatk, tiles, blk, 0, st, a); });
   };
   if constexpr (D == 8) {

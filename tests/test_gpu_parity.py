@@ -599,7 +599,8 @@ def test_multi_vertex_bound(tc):
 
 
 def test_kernel_timing_with_bound(tc):
-    # passes above the bound are not launched: their times stay zero
+    # passes above the bound are not launched: their times stay zero; a
+    # batch of one radix chunk (8-bit digits) launches no chunk scan
     E = to_dev(np_edges(inputs.gnm(200, 3000, seed=9)))
     g = tc.Bank(1000, 2)
     tc.tc_set_vertex_bound(g.h, 200)
@@ -608,8 +609,29 @@ def test_kernel_timing_with_bound(tc):
     g.process(E[1500:])
     times, steps = tc.tc_kernel_times(g.h)
     assert steps == 2
-    assert times["k_scat<0>"] > 0 and times["k_cscan<0>"] > 0 and times["k_est"] > 0
+    assert times["k_scat<0>"] > 0 and times["k_est"] > 0 and times["k_cscan<0>"] == 0.0
     for p in (1, 2, 3):
+        for k in ("k_cnt", "k_csum", "k_cscan", "k_scat"):
+            assert times[f"{k}<{p}>"] == 0.0
+
+
+def test_kernel_timing_two_chunks(tc):
+    # 75000 edges: 150000 arcs, 37 tiles, two radix chunks, so the chunk
+    # scans run; a 13-bit bound launches two 8-bit passes
+    E = np_edges(inputs.gnm(5000, 150000, seed=10))
+    g, o = tc.Bank(3000, 5), O.Bank(3000, 5)
+    tc.tc_set_vertex_bound(g.h, 5000)
+    tc.tc_set_kernel_timing(g.h, True)
+    dev = to_dev(E)
+    for j in (0, 75000):
+        g.process(dev[j:j + 75000])
+        assert o.process(E[j:j + 75000]) == O.OK
+    assert_same(g.state(), o.state(), "two chunks, bound 5000")
+    times, steps = tc.tc_kernel_times(g.h)
+    assert steps == 2
+    for k in ("k_cscan<0>", "k_cnt<1>", "k_csum<1>", "k_cscan<1>", "k_scat<1>"):
+        assert times[k] > 0, k
+    for p in (2, 3):
         for k in ("k_cnt", "k_csum", "k_cscan", "k_scat"):
             assert times[f"{k}<{p}>"] == 0.0
 
