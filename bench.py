@@ -440,7 +440,7 @@ def kernel_source_hash() -> str:
 STEP_ORDER = (["k_hist", "k_fold_step1", "k_cscan<0>", "k_scat<0>"]
               + [f"{k}<{p}>" for p in range(1, 4)
                  for k in ("k_cnt", "k_csum", "k_cscan", "k_scat")]
-              + ["k_dir", "k_est", "k_post", "k_probe"])
+              + ["k_dir", "k_est", "k_post", "k_qbits", "k_probe"])
 
 
 def _short(name: str) -> str:

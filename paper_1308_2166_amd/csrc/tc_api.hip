@@ -76,15 +76,22 @@ void dfree(T*& p) {
 
 // kernels (bit k = launch k of a step) that a step with npass radix passes
 // launches: the four kernels of each pass at or above npass are skipped,
-// and every pass's k_cscan when the step's segments are single chunks
-uint32_t launched_kernels(uint32_t npass, bool single_chunk) {
+// every pass's k_cscan when the step's segments are single chunks, and
+// k_qbits when the step's query tables go without the bitmap
+uint32_t launched_kernels(uint32_t npass, bool single_chunk, bool bitmap) {
   uint32_t m = (1u << kNumKernels) - 1u;
   for (uint32_t p = npass < 1 ? 1 : npass; p < (uint32_t)kPasses; ++p)
     m &= ~(15u << (4 + 4 * (p - 1)));
   if (single_chunk)
     for (uint32_t p = 0; p < (uint32_t)kPasses; ++p) m &= ~(1u << (2 + 4 * p));
+  if (!bitmap) m &= ~(1u << (kNumKernels - 2));
   return m;
 }
+
+// Query tables of more slots than this (one fingerprint byte each) get the
+// occupancy bitmap: below it the bytes mostly stay in a 4 MB XCD L2 anyway
+// and k_qbits would be a launch for nothing.
+constexpr uint64_t kBitmapMinSlots = 1ull << 22;
 
 // Per-parity scratch: the Step-3 phase of step s (on the engine's second
 // stream) overlaps the grouping phase of step s+1, so everything both
@@ -93,6 +100,7 @@ struct ParityScratch {
   SegWork* work = nullptr;    // per-segment histograms, counters, modes
   uint32_t* qt = nullptr;     // Step-3 query tables (owners)
   uint8_t* qfp = nullptr;
+  uint32_t* qbits = nullptr;  // occupancy bitmap of the query tables
   SegDesc* segs = nullptr;    // device copy of the step's descriptors
 };
 
@@ -222,7 +230,7 @@ struct Engine {
     dfree(arcs[0]), dfree(arcs[1]), dfree(csum);
     dfree(dir), dfree(need), dfree(inv), dfree(hpart), dfree(mpart);
     for (ParityScratch& p : par) {
-      dfree(p.work), dfree(p.qt), dfree(p.qfp);
+      dfree(p.work), dfree(p.qt), dfree(p.qfp), dfree(p.qbits);
       dfree(p.segs);
     }
     cap_arcs = cap_tiles = cap_dir = cap_qt = cap_need = 0;
@@ -295,7 +303,7 @@ struct Engine {
                dalloc(&mpart, cap_tiles);
     for (ParityScratch& p : par)
       bad = bad || dalloc(&p.work, cap_segs) || dalloc(&p.qt, cap_qt) ||
-            dalloc(&p.qfp, cap_qt) ||
+            dalloc(&p.qfp, cap_qt) || dalloc(&p.qbits, cap_qt / 32) ||
             dalloc(&p.segs, cap_segs);
     if (bad) {
       free_scratch();
@@ -440,6 +448,7 @@ struct Engine {
     a.dir = dir;
     a.qt = P.qt;
     a.qfp = P.qfp;
+    a.qbits = qt_n > kBitmapMinSlots ? P.qbits : nullptr;
     a.qt_slots = qt_n;
     a.j1 = J1;
     a.qq = QQ;
@@ -469,7 +478,7 @@ struct Engine {
               return fail(TC_EHIP, "hipEventCreate failed");
       }
       ev_pending.push_back(ev);
-      ev_launched.push_back(launched_kernels(npass, a.single_chunk != 0));
+      ev_launched.push_back(launched_kernels(npass, a.single_chunk != 0, a.qbits != nullptr));
     }
     // A: group the batch; B: Steps 1-2, after the previous step's Step 3;
     // C: Step 3, on st2 when it may overlap the next step's A
@@ -818,7 +827,7 @@ static const char* const kKernelNames[kNumKernels] = {
     "k_cnt<1>", "k_csum<1>", "k_cscan<1>", "k_scat<1>",
     "k_cnt<2>", "k_csum<2>", "k_cscan<2>", "k_scat<2>",
     "k_cnt<3>", "k_csum<3>", "k_cscan<3>", "k_scat<3>",
-    "k_dir", "k_est", "k_post", "k_probe"};
+    "k_dir", "k_est", "k_post", "k_qbits", "k_probe"};
 
 static int set_timing(Engine& e, uint32_t mask) {
   int rc = e.collect_times();

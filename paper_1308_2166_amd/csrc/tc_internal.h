@@ -28,7 +28,7 @@ constexpr int kWidePasses = 2;           // passes of wide digits
 // passes: pass P's counts start at word P << D
 constexpr int kRowWords = kWidePasses << kWideBits;
 static_assert(kRowWords >= kPasses << 8, "a row holds every 8-bit pass");
-constexpr int kNumKernels = 20;  // launches per step (k_hist .. k_probe)
+constexpr int kNumKernels = 21;  // launches per step (k_hist .. k_probe)
 constexpr int kHistTiles = 1;   // tiles per k_hist block (one: its counts are
                                 // the per-tile counts of the first radix pass)
 constexpr uint32_t kChunk = 32;  // tiles per chunk of the radix scans (and
@@ -137,6 +137,9 @@ struct StepArgs {
   DirSlot* dir;
   uint32_t* qt;           // query table: owner per slot
   uint8_t* qfp;           // query table: key fingerprint per slot
+  uint32_t* qbits;        // query table: bit s of word s / 32 set iff slot s
+                          // is taken (built from qfp after k_post); null
+                          // when the step's tables are small (no bitmap)
   uint64_t qt_slots;      // query-table slots over all segments
   uint32_t* j1;           // per estimator: Step-1 replacement (see kSideV)
   uint64_t* qq;           // per estimator: closing edge it waits for, or kEmpty

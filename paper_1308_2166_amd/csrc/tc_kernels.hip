@@ -3,7 +3,7 @@
 //
 // One step = k_hist -> k_fold_step1 -> k_cscan<0> -> k_scat<0> -> up to
 // 3 x (k_cnt -> k_csum -> k_cscan -> k_scat) -> k_dir -> k_est -> k_post ->
-// k_probe.
+// k_qbits -> k_probe.
 //
 //  k_hist   per-tile counts of digit 0 of the 2w arcs (+ max id, self-loop
 //           check)
@@ -28,6 +28,7 @@
 //           and the sorted index of the arcs of positions Step 1 picked
 //  k_est    Step 2 for every estimator; records its Step-3 closing edge
 //  k_post   Step 3 queries into a hash table with a fingerprint byte per slot
+//  k_qbits  the table's occupancy bitmap (one bit per slot, from the bytes)
 //  k_probe  Step 3: one pass over W closes the estimators waiting for it
 #include <algorithm>
 
@@ -1133,6 +1134,31 @@ __global__ __launch_bounds__(kBlock) void k_post(StepArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int kProbeEdges = kTile / 2 / kBlock;  // edges per thread
 
+// k_qbits: one bit per query-table slot, set iff its fingerprint byte is
+// nonzero (the slot is taken).  At load <= 1/4 most probes start at a free
+// slot; the bitmap (an eighth of the fingerprint table: 0.5 MB at r = 2^20,
+// 2 MB at r = 2^22) stays in each XCD's L2 where the fingerprints do not.
+// One thread per 32 slots: two 16-byte loads, one word stored, every word
+// of the map rewritten each step.
+__device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t x) {
+  // bit i (i = 0..3) set iff byte i of x is nonzero
+  const uint32_t h = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;  // top bit per byte
+  const uint32_t t = (h >> 7) & 0x01010101u;
+  return (t | (t >> 7) | (t >> 14) | (t >> 21)) & 0xFu;
+}
+
+__global__ __launch_bounds__(kBlock) void k_qbits(StepArgs a) {
+  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= a.qt_slots / 32) return;
+  const uint4* f = reinterpret_cast<const uint4*>(a.qfp) + 2 * t;
+  const uint4 x = f[0], y = f[1];
+  const uint32_t b = nonzero_bytes4(x.x) | nonzero_bytes4(x.y) << 4 |
+                     nonzero_bytes4(x.z) << 8 | nonzero_bytes4(x.w) << 12 |
+                     nonzero_bytes4(y.x) << 16 | nonzero_bytes4(y.y) << 20 |
+                     nonzero_bytes4(y.z) << 24 | nonzero_bytes4(y.w) << 28;
+  a.qbits[t] = b;
+}
+
 __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
@@ -1147,6 +1173,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
     const uint32_t mask = (1u << S.qt_log2) - 1u;
     const uint8_t* fp = a.qfp + S.qt_off;
     const uint32_t* qt = a.qt + S.qt_off;
+    // occupancy bitmap, when the step has one (qt_off: a multiple of 1024)
+    const uint32_t* qb = a.qbits ? a.qbits + S.qt_off / 32 : nullptr;
     constexpr uint64_t k01 = 0x0101010101010101ull, k80 = 0x8080808080808080ull;
     for (int k = 0; k < kProbeEdges; ++k) {
       const uint32_t j = ebase + k * kBlock + tid;
@@ -1155,12 +1183,14 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
       const uint64_t q = canon(ed.x, ed.y);
       const uint64_t hq = mix64(q);
       const uint64_t fx = k01 * q_fp(hq);
-      // the fingerprints (one byte per slot, a few MB, stay in L2) rule out
-      // nearly every edge; they are read eight at a time (aligned words):
+      // the fingerprints (one byte per slot) rule out nearly every other
+      // edge; they are read eight at a time (aligned words):
       // the scan ends at the first free slot (zero byte), and a byte equal
       // to the edge's fingerprint before it is checked against the edge
       // its owner waits for
       uint32_t sl = q_home(hq, mask);
+      // a free home slot (most edges) ends the probe at the bitmap
+      if (qb && ((qb[sl >> 5] >> (sl & 31u)) & 1u) == 0u) continue;
       for (uint32_t probe = 0; probe <= mask + 8; probe += 8) {
         const uint32_t b8 = sl & ~7u;
         const uint64_t wd = *reinterpret_cast<const uint64_t*>(fp + b8);
@@ -1519,11 +1549,14 @@ hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st,
     } else {
       launch_sort<8>(a, st, run);
     }
-    run(kNumKernels - 4, [&] { hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a); });
+    run(kNumKernels - 5, [&] { hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a); });
   } else if (phase == 1) {
-    run(kNumKernels - 3, [&] { hipLaunchKernelGGL(k_est, ests, blk, 0, st, a); });
+    run(kNumKernels - 4, [&] { hipLaunchKernelGGL(k_est, ests, blk, 0, st, a); });
   } else {
-    run(kNumKernels - 2, [&] { hipLaunchKernelGGL(k_post, ests, blk, 0, st, a); });
+    const dim3 qwords((uint32_t)((a.qt_slots / 32 + kBlock - 1) / kBlock));
+    run(kNumKernels - 3, [&] { hipLaunchKernelGGL(k_post, ests, blk, 0, st, a); });
+    if (a.qbits)
+      run(kNumKernels - 2, [&] { hipLaunchKernelGGL(k_qbits, qwords, blk, 0, st, a); });
     run(kNumKernels - 1, [&] { hipLaunchKernelGGL(k_probe, tiles, blk, 0, st, a); });
   }
   return hipGetLastError();

@@ -737,6 +737,30 @@ def test_wide_digit_bound_violation(tc, bound, bad_id):
     assert ei.value.code == tc.TC_EINVAL
 
 
+# -- query tables above 2^22 slots: probes start at the occupancy bitmap ----------
+
+def test_query_bitmap_one_bank(tc):
+    # r = 2^20 + 1: 4r rounds up to 2^23 slots
+    E = np_edges(inputs.rmat(16, 300000, seed=12))
+    r, w = (1 << 20) + 1, 100000
+    g = tc.Bank(r, 8)
+    g.process_stream(to_dev(E), w)
+    o = O.run_stream(E, r, 8, w)
+    assert_same(g.state(), o.state(), "r = 2^20 + 1")
+    assert tc.tc_estimate_ex(g.h)[0] == o.sum()
+
+
+def test_query_bitmap_batched(tc):
+    # five banks of 2^20 slots each: the step's tables hold 5 * 2^20 slots
+    rs, seeds, w = [1 << 18] * 5, [21, 22, 23, 24, 25], 30000
+    Es = [np_edges(inputs.gnm(3000 + 500 * b, 90000, seed=70 + b)) for b in range(5)]
+    mb = tc.MultiBank(rs, seeds)
+    for k in range(3):
+        mb.process(list(range(5)), [to_dev(E[k * w:(k + 1) * w]) for E in Es])
+    for b in range(5):
+        assert_same(mb.state(b), O.run_stream(Es[b], rs[b], seeds[b], w).state(), f"bank {b}")
+
+
 # -- median-of-means aggregate -----------------------------------------------------
 
 def _assert_mom(got, want):
