@@ -88,10 +88,6 @@ uint32_t launched_kernels(uint32_t npass, bool single_chunk, bool bitmap) {
   return m;
 }
 
-// Query tables of more slots than this (one fingerprint byte each) get the
-// occupancy bitmap: below it the bytes mostly stay in a 4 MB XCD L2 anyway
-// and k_qbits would be a launch for nothing.
-constexpr uint64_t kBitmapMinSlots = 1ull << 22;
 
 // Per-parity scratch: the Step-3 phase of step s (on the engine's second
 // stream) overlaps the grouping phase of step s+1, so everything both
@@ -371,6 +367,7 @@ struct Engine {
     std::vector<char> seen(nbanks, 0);
     uint64_t arcs_n = 0, tiles = 0, dir_n = 0, qt_n = 0, need_n = 0, nest = 0,
              hblks = 0, chunks = 0;
+    bool big_qt = false;  // some segment's query table gets the bitmap
     for (uint32_t k = 0; k < nchunks; ++k) {
       const uint32_t b = ids[k];
       if (b >= nbanks) return fail(TC_EINVAL, "bank id out of range");
@@ -403,6 +400,7 @@ struct Engine {
       chunks += d.nchunks;
       d.dir_log2 = dir_log2_for(w[k]);
       d.qt_log2 = qt_log2_for(r[b]);
+      big_qt = big_qt || d.qt_log2 > kBitmapMinLog2;
       d.need_off = (uint32_t)need_n;
       need_n += (w[k] + 15) / 16 * 16;
       arcs_n += 2ull * w[k];
@@ -448,7 +446,7 @@ struct Engine {
     a.dir = dir;
     a.qt = P.qt;
     a.qfp = P.qfp;
-    a.qbits = qt_n > kBitmapMinSlots ? P.qbits : nullptr;
+    a.qbits = big_qt ? P.qbits : nullptr;
     a.qt_slots = qt_n;
     a.j1 = J1;
     a.qq = QQ;

@@ -104,14 +104,19 @@ struct DirSlot {
   uint32_t end;
 };
 
+// A segment's query table of more than 2^kBitmapMinLog2 slots (one
+// fingerprint byte each) is probed through an occupancy bitmap: smaller
+// ones mostly stay in a 4 MB XCD L2 anyway.
+constexpr uint32_t kBitmapMinLog2 = 22;
+
 // Step-3 query table (one region per segment, linear probing): slot s
 // holds qt[s], the estimator that owns it (kNone = free), and qfp[s], a
 // nonzero 8-bit fingerprint of the hash of the closing edge that estimator
 // waits for (0 = free), which is what a probe scans.  The edge itself and
 // the first batch position that closes it are the owner's qq and qthr
 // entries.  Every waiting estimator owns one slot (equal edges share a
-// probe cluster).  Owners and fingerprints are reset during every step's
-// grouping (by spare blocks of k_cscan<0>), before k_est first claims.
+// probe cluster).  Owners and fingerprints are reset by k_hist at the
+// start of every step.
 
 struct StepArgs {
   const SegDesc* segs;    // device copy of all segment descriptors
@@ -139,7 +144,8 @@ struct StepArgs {
   uint8_t* qfp;           // query table: key fingerprint per slot
   uint32_t* qbits;        // query table: bit s of word s / 32 set iff slot s
                           // is taken (built from qfp after k_post); null
-                          // when the step's tables are small (no bitmap)
+                          // when no segment's table has more than
+                          // 2^kBitmapMinLog2 slots (no bitmap)
   uint64_t qt_slots;      // query-table slots over all segments
   uint32_t* j1;           // per estimator: Step-1 replacement (see kSideV)
   uint64_t* qq;           // per estimator: closing edge it waits for, or kEmpty
@@ -156,8 +162,7 @@ struct StepArgs {
   uint32_t dbits;         // digit width D: 8 or kWideBits
   uint32_t single_chunk;  // 1: every segment is one radix chunk and D = 8;
                           // the count sums then write each chunk's bin
-                          // starts as its bases, no k_cscan runs, and
-                          // k_hist clears the query tables
+                          // starts as its bases and no k_cscan runs
 };
 
 // arguments of the per-estimator (naive) step: one bank, one batch

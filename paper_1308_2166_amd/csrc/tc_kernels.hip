@@ -210,10 +210,7 @@ __device__ __forceinline__ void st_bins(uint32_t* p, const uint32_t (&v)[N]) {
 
 // Blocks [0, nb) of a launch empty the Step-3 query tables (first used by
 // k_est of this step); slot counts are multiples of 1024, so whole uint4s
-// cover them.  Run by spare blocks of k_cscan<0>, whose scan blocks are
-// few and bound by latency, so the stores use bandwidth that would idle
-// (by k_hist when no k_cscan runs).
-constexpr uint32_t kClearBlocks = 1024;
+// cover them.  Run by k_hist, whose stores overlap its reads of W.
 __device__ void clear_qtables(const StepArgs& a, uint32_t b, uint32_t nb) {
   const uint64_t t0 = (uint64_t)b * kBlock + threadIdx.x, step = (uint64_t)nb * kBlock;
   uint4* o4 = reinterpret_cast<uint4*>(a.qt);
@@ -258,9 +255,8 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
   }
 #pragma unroll
   for (int j = 0; j < R::kPer; ++j) h[tid + j * kBlock] = 0;
-  // clear the need bytes (Step 1 marks them next; the query tables are
-  // cleared by spare blocks of k_cscan<0>, or here when it does not run)
-  if (a.single_chunk) clear_qtables(a, hb, a.nhblk);
+  // clear the query tables and the need bytes (Step 1 marks them next)
+  clear_qtables(a, hb, a.nhblk);
   {
     uint4* n4 = reinterpret_cast<uint4*>(a.need);
     for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.need_bytes / 16;
@@ -560,10 +556,6 @@ __global__ __launch_bounds__(kBlock) void k_cscan(StepArgs a) {
   __shared__ __align__(16) uint32_t s_bin[R::kBins];
   __shared__ uint32_t s_part[kWaves][64];
   __shared__ uint32_t s_tmp[kWaves];
-  if (P == 0 && blockIdx.x >= a.nseg * kGroups) {
-    clear_qtables(a, blockIdx.x - a.nseg * kGroups, gridDim.x - a.nseg * kGroups);
-    return;
-  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t sidx = blockIdx.x / kGroups;
   const uint32_t d = (blockIdx.x % kGroups) * 64 + lane;
@@ -1173,8 +1165,10 @@ __global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
     const uint32_t mask = (1u << S.qt_log2) - 1u;
     const uint8_t* fp = a.qfp + S.qt_off;
     const uint32_t* qt = a.qt + S.qt_off;
-    // occupancy bitmap, when the step has one (qt_off: a multiple of 1024)
-    const uint32_t* qb = a.qbits ? a.qbits + S.qt_off / 32 : nullptr;
+    // occupancy bitmap, for a segment with a table too large for L2
+    // (qt_off: a multiple of 1024)
+    const uint32_t* qb =
+        a.qbits && S.qt_log2 > kBitmapMinLog2 ? a.qbits + S.qt_off / 32 : nullptr;
     constexpr uint64_t k01 = 0x0101010101010101ull, k80 = 0x8080808080808080ull;
     for (int k = 0; k < kProbeEdges; ++k) {
       const uint32_t j = ebase + k * kBlock + tid;
@@ -1505,15 +1499,12 @@ void launch_sort(const StepArgs& a, hipStream_t st, Run& run) {
   constexpr uint32_t kPer = Rdx<D>::kPer;
   const dim3 blk(kBlock), tiles(a.ntiles);
   const dim3 chunks(a.nchunk * kPer), segs(a.nseg * (Rdx<D>::kBins / 64));
-  const uint32_t nclear = (uint32_t)std::min<uint64_t>(
-      kClearBlocks, (a.qt_slots / 4 + kBlock - 1) / kBlock);
-  const dim3 segs_clear(a.nseg * (Rdx<D>::kBins / 64) + nclear);
   run(0, [&] { hipLaunchKernelGGL(k_hist<D>, dim3(a.nhblk), blk, 0, st, a); });
   run(1, [&] {
     hipLaunchKernelGGL(k_fold_step1<D>, dim3(a.nchunk * kPer + a.nstep1), blk, 0, st, a);
   });
   if (!a.single_chunk)
-    run(2, [&] { hipLaunchKernelGGL((k_cscan<0, D>), segs_clear, blk, 0, st, a); });
+    run(2, [&] { hipLaunchKernelGGL((k_cscan<0, D>), segs, blk, 0, st, a); });
   run(3, [&] { hipLaunchKernelGGL((k_scat<0, D>), tiles, blk, 0, st, a); });
   auto pass = [&](int P, auto cntk, auto csumk, auto cscank, auto scatk) {
     const int k = 4 + 4 * (P - 1);

@@ -751,8 +751,9 @@ def test_query_bitmap_one_bank(tc):
 
 
 def test_query_bitmap_batched(tc):
-    # five banks of 2^20 slots each: the step's tables hold 5 * 2^20 slots
-    rs, seeds, w = [1 << 18] * 5, [21, 22, 23, 24, 25], 30000
+    # the second bank's table (2^23 slots, at a nonzero offset) is probed
+    # through the bitmap, the others' (2^20 and less) byte by byte
+    rs, seeds, w = [1 << 18, (1 << 20) + 1, 5000, 1 << 18, 1], [21, 22, 23, 24, 25], 30000
     Es = [np_edges(inputs.gnm(3000 + 500 * b, 90000, seed=70 + b)) for b in range(5)]
     mb = tc.MultiBank(rs, seeds)
     for k in range(3):
