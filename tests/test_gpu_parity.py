@@ -762,6 +762,82 @@ def test_query_bitmap_batched(tc):
         assert_same(mb.state(b), O.run_stream(Es[b], rs[b], seeds[b], w).state(), f"bank {b}")
 
 
+# -- random mixes of digit widths, chunk counts and table sizes -------------------
+
+def _mix_case(k):
+    """A seeded configuration drawn over the choices the step makes by
+    itself: 8- or 10-bit digits (bounds of 17 to 20 bits with ids spread
+    over them), one or several radix chunks, query tables above or below
+    2^22 slots (r > 2^20), dense or hashed directory."""
+    rng = np.random.default_rng(9000 + k)
+    fam = int(rng.integers(0, 3))
+    m = int(rng.integers(1000, 250000))
+    if fam == 0:
+        n = int(rng.integers(50, 60000))
+        E = np_edges(inputs.gnm(n, min(m, n * (n - 1) // 4), seed=k))
+    elif fam == 1:
+        sc = int(rng.integers(8, 18))
+        E = np_edges(inputs.rmat(sc, min(m, (1 << sc) * 8), seed=k))
+    else:
+        n = int(rng.integers(1000, 60000))
+        E = np_edges(inputs.chung_lu(n, min(m, n * 8), seed=k))
+    kind = int(rng.integers(0, 4))
+    bound = None
+    if kind == 1:
+        bound = (1 << int(rng.integers(17, 21))) - int(rng.integers(0, 3))
+        if int(E.max()) < bound:
+            E = _spread_ids(E, bound, seed=k)
+        else:
+            bound = None
+    elif kind == 2:
+        bound = int(E.max()) + 1 + int(rng.integers(0, 100))
+    elif kind == 3:
+        E = ((E.astype(np.uint64) * 2654435761 + 77) % (2**32 - 7)).astype(np.uint32)
+    r = (1 << 20) + int(rng.integers(1, 5000)) if rng.integers(0, 6) == 0 else int(rng.integers(1, 70000))
+    w = int(rng.integers(1, max(2, len(E) // int(rng.integers(1, 6)) + 1)))
+    w = max(w, -(-len(E) // max(1, min(200, int(2e7 // r)))))  # bounded oracle time
+    return E, r, w, bound, f"fam={fam} m={len(E)} kind={kind} bound={bound} r={r} w={w}"
+
+
+@pytest.mark.parametrize("k", range(16))
+def test_random_mix(tc, k):
+    E, r, w, bound, desc = _mix_case(k)
+    say(f"  mix {k}: {desc}")
+    g, o = tc.Bank(r, 1000 + k), O.Bank(r, 1000 + k)
+    if bound is not None:
+        tc.tc_set_vertex_bound(g.h, bound)
+    dev = to_dev(E)
+    for j in range(0, len(E), w):
+        g.process(dev[j:j + w])
+        assert o.process(E[j:j + w]) == O.OK
+    assert_same(g.state(), o.state(), desc)
+    assert tc.tc_estimate_ex(g.h)[0] == o.sum()
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_random_mix_batched(tc, k):
+    rng = np.random.default_rng(7000 + k)
+    nb = int(rng.integers(2, 7))
+    rs = [int(rng.integers(1, 300000)) if rng.integers(0, 4) else (1 << 20) + 3 for _ in range(nb)]
+    seeds = [int(rng.integers(0, 2**62)) for _ in range(nb)]
+    Es = [np_edges(inputs.gnm(int(rng.integers(100, 20000)), int(rng.integers(500, 120000)),
+                              seed=k * 10 + b)) for b in range(nb)]
+    bound = None
+    if rng.integers(0, 2):
+        bound = 1 << int(rng.integers(17, 21))
+        Es = [_spread_ids(E, bound, seed=k * 10 + b) for b, E in enumerate(Es)]
+    w = int(rng.integers(10000, 70000))
+    say(f"  batched mix {k}: nb={nb} rs={rs} w={w} bound={bound}")
+    mb = tc.MultiBank(rs, seeds)
+    if bound:
+        tc.tc_multi_set_vertex_bound(mb.h, bound)
+    for t in range(max(-(-len(E) // w) for E in Es)):
+        ids = [b for b in range(nb) if t * w < len(Es[b])]
+        mb.process(ids, [to_dev(Es[b][t * w:(t + 1) * w]) for b in ids])
+    for b in range(nb):
+        assert_same(mb.state(b), O.run_stream(Es[b], rs[b], seeds[b], w).state(), f"bank {b}")
+
+
 # -- median-of-means aggregate -----------------------------------------------------
 
 def _assert_mom(got, want):
