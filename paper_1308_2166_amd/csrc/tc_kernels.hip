@@ -352,10 +352,10 @@ __device__ __forceinline__ uint32_t* cnt_row(const StepArgs& a, uint32_t t, int 
   return a.hpart + (size_t)t * kRowWords + ((size_t)P << D);
 }
 
-// What a count-sum block stores for its chunk: the chunk's sum of digit
-// threadIdx.x (k_cscan turns it into the chunk's base), or, when every
-// segment is a single chunk and one block holds all 256 digits, the base
-// itself: the digit's bin start, an exclusive scan of those sums.
+// What a count-sum block stores for its chunk: the chunk's sum of the
+// thread's digit (k_cscan turns it into the chunk's base), or, when every
+// segment is a single chunk and one block holds all 256 (8-bit) digits,
+// the base itself: the digit's bin start, an exclusive scan of those sums.
 template <int D>
 __device__ __forceinline__ uint32_t single_chunk_base(const StepArgs& a, uint32_t tot) {
   if constexpr (D == 8) {
