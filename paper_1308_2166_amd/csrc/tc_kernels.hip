@@ -255,14 +255,6 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
   }
 #pragma unroll
   for (int j = 0; j < R::kPer; ++j) h[tid + j * kBlock] = 0;
-  // clear the query tables and the need bytes (Step 1 marks them next)
-  clear_qtables(a, hb, a.nhblk);
-  {
-    uint4* n4 = reinterpret_cast<uint4*>(a.need);
-    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.need_bytes / 16;
-         t += (uint64_t)a.nhblk * kBlock)
-      n4[t] = make_uint4(0, 0, 0, 0);
-  }
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
@@ -293,6 +285,15 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
       x.y = e0.y;
     }
     xs[it] = x;
+  }
+  // clear the query tables and the need bytes (Step 1 marks them next)
+  // while the loads above are in flight
+  clear_qtables(a, hb, a.nhblk);
+  {
+    uint4* n4 = reinterpret_cast<uint4*>(a.need);
+    for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.need_bytes / 16;
+         t += (uint64_t)a.nhblk * kBlock)
+      n4[t] = make_uint4(0, 0, 0, 0);
   }
 #pragma unroll
   for (int it = 0; it < kRounds; ++it) {
