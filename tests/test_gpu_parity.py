@@ -446,6 +446,30 @@ def test_graph_replay_single_bank(tc):
         _ = torch.ones(1000, device="cuda").sum().item()
 
 
+def test_graph_replay_wide_digits_and_bitmap(tc):
+    # the captured step runs both 10-bit passes with their chunk scans
+    # (100 000-edge batches: two radix chunks) and probes through the
+    # occupancy bitmap (r = 2^20 + 1: 2^23 query slots)
+    r, seed, w = (1 << 20) + 1, 41, 100000
+    E = _spread_ids(np_edges(inputs.rmat(16, 300000, seed=16)), 1 << 20, 16)
+    dev = to_dev(E)
+    g = tc.Bank(r, seed)
+    tc.tc_set_vertex_bound(g.h, 1 << 20)
+    tc.tc_reserve(g.h, w)
+    gr = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(gr, stream=cs):
+        tc.tc_reset(g.h, cs)
+        g.process_stream(dev, w, cs)
+    o = O.run_stream(E, r, seed, w)
+    for rep in range(3):
+        gr.replay()
+        torch.cuda.synchronize()
+        assert_same(g.state(), o.state(), f"replay {rep}")
+        _ = torch.ones(1000, device="cuda").sum().item()
+
+
 # -- continuous batching: each stream's result alone == in the mix -----------------------
 
 def test_served_streams_equal_their_alone_runs(tc):
@@ -545,7 +569,8 @@ def test_process_stream_arguments(tc):
 # -- declared vertex bound: fewer radix passes, same results ----------------------
 
 @pytest.mark.parametrize("n,m,w,bound", [(200, 3000, 700, 200), (2000, 20000, 2048, 2000),
-                                         (3000, 30000, 9001, 1 << 16), (250, 2000, 500, 256)])
+                                         (3000, 30000, 9001, 1 << 16), (250, 2000, 500, 256),
+                                         (200, 3000, 700, 1 << 16)])
 def test_vertex_bound_same_results(tc, n, m, w, bound):
     E = np_edges(inputs.gnm(n, m, seed=n + w))
     dev = to_dev(E)
