@@ -85,3 +85,15 @@ def test_estimators_needed_matches_oracle():
             O.estimators_needed(eps, delta, m, deg, tau)
     assert tc.tc_estimators_needed(0.5, 0.1, 30, 6, 10.0) == 15916
     assert tc.tc_estimators_needed(0.5, 1.5, 30, 6, 10.0) == 0
+
+
+def test_kernel_names_in_launch_order():
+    # the per-kernel timing table: a host function of the library, no GPU
+    import paper_1308_2166_amd as tc
+    want = ["k_hist", "k_fold_step1", "k_cscan<0>", "k_scat<0>"]
+    for p in (1, 2, 3):
+        want += [f"k_cnt<{p}>", f"k_csum<{p}>", f"k_cscan<{p}>", f"k_scat<{p}>"]
+    want += ["k_dir", "k_est", "k_post", "k_qbits", "k_probe"]
+    assert [tc.tc_kernel_name(k) for k in range(tc.tc_num_kernels())] == want
+    bench = __import__("bench")
+    assert [n for n in bench.STEP_ORDER] == want

@@ -70,3 +70,29 @@ def test_summarize_calibrates_with_the_first_copy(tmp_path):
     assert k["avg_us_timed"] == pytest.approx(25.0)
     assert k["hbm_bytes"] == pytest.approx(100.0 * 1024 * 2.0 + 50.0 * 1024 * 1.0)
     assert "cmd" in (out / "step_kernels_rmat20.md").read_text()
+
+
+def test_radix_passes_follow_the_library_choice():
+    """The algorithmic bytes count the passes the library runs: 8-bit digits,
+    or two 10-bit passes when bound - 1 has 17 to 20 bits; a pass whose
+    digit is zero in every id skips."""
+    rp = _bench().radix_passes
+    assert rp(1 << 20, (1 << 20) - 1) == [True, True, False, False]   # 10-bit, C2
+    assert rp(1 << 24, (1 << 24) - 1) == [True, True, True, False]    # 8-bit, C3
+    assert rp(2000, 1999) == [True, True, False, False]               # 11 bits: 8-bit
+    assert rp(1 << 16, 200) == [True, False, False, False]            # skipped on device
+    assert rp((1 << 16) + 1, 1 << 16) == [True, True, False, False]   # 17 bits: 10-bit
+    assert rp(1 << 20, 900) == [True, False, False, False]            # 10-bit, top digit 0
+    assert rp(2 ** 32, 5000) == [True, True, False, False]            # no bound
+    assert rp(2 ** 32, 2 ** 32 - 1) == [True] * 4
+
+
+def test_profile_names_map_to_launch_names():
+    short = _bench()._short
+    assert short("void tc::k_scat4<1, 10>(tc::StepArgs)") == "k_scat<1>"
+    assert short("void tc::k_scat<0, 8>(tc::StepArgs)") == "k_scat<0>"
+    assert short("void tc::k_hist<10>(tc::StepArgs)") == "k_hist"
+    assert short("void tc::k_fold_step1<8>(tc::StepArgs)") == "k_fold_step1"
+    assert short("void tc::k_cscan<2, 8>(tc::StepArgs)") == "k_cscan<2>"
+    assert short("tc::k_qbits(tc::StepArgs)") == "k_qbits"
+    assert short("tc::k_est(tc::StepArgs)") == "k_est"
