@@ -3,9 +3,10 @@
 One step = one bulk update (every step of the hot path: Step 1, the arc
 grouping sort, the rank directory, Step 2, Step 3) of a bank of r estimators
 by one batch of w stream edges, inputs resident in HBM.  The default workload
-is an R-MAT scale-20 stream (16 Mi distinct edges, r = 2^20, w = 2^22): the
-stream has four batches, so the timed steps walk fresh banks through the
-stream batch 0, 1, 2, 3, 0, 1, ...
+is the largest single-GPU one: an R-MAT scale-24 stream (2^28 distinct edges,
+r = 2^22, w = 2^24), sixteen batches, so the timed steps walk fresh banks
+through the stream batch 0, 1, ..., 15, 0, 1, ...  The R-MAT scale-20 stream
+(r = 2^20, w = 2^22) is timed beside it as an extra entry.
 
 Prints ONE JSON line (rank 0) with the metric, a roofline entry for the
 dominant kernel (HIP-event time per launch on the step's stream) and the CPU
@@ -668,12 +669,58 @@ def served_comparison(tc, inputs, nstreams=1024, ngraphs=64, r=1 << 16,
     return out
 
 
+def quick_rate(tc, inputs, name, steps=16):
+    """Plain-form rate of another workload: fresh banks walk its stream in
+    one tc_process_stream call each (as the timed region of the headline),
+    `steps` steps after one warm-up bank; no events."""
+    import torch
+    G, r, w, seed = inputs.workload(name, device="cuda")
+    G = G.contiguous()
+    nv = inputs.vertex_count(name)
+    m = G.shape[0]
+    nb = (m + w - 1) // w
+    stream = torch.cuda.current_stream()
+
+    def bank():
+        b = tc.Bank(r, seed)
+        tc.tc_set_vertex_bound(b.h, nv)
+        tc.tc_reserve(b.h, w)
+        return b
+    warm = bank()
+    warm.process_stream(G, w, stream)
+    warm.sync()
+    warm.close()
+    banks = [bank() for _ in range((steps + nb - 1) // nb)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k = 0
+    for b in banks:
+        cnt = min(nb, steps - k)
+        b.process_stream(G[:min(m, cnt * w)], w, stream)
+        k += cnt
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    edges = sum(min(w, m - (j % nb) * w) for j in range(steps))
+    for b in banks:
+        b.sync()
+        b.close()
+    b_alg = 8.0 * w + 32.0 * w + 48.0 * r
+    del G
+    torch.cuda.empty_cache()
+    return {"workload": name, "description": WORKLOADS[name], "r": r, "w": w,
+            "steps": steps, "ms_per_step": dt * 1e3 / steps, "value": r * edges / dt,
+            "unit": "estimator-edge updates/s", "edges_per_s": edges / dt,
+            "method_frac": round(b_alg / (dt / steps) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-extra-workload", action="store_true",
+                    help="skip the extra timing of the R-MAT scale-20 stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the steps without events between kernels")
@@ -925,7 +972,12 @@ def main():
         log("[bench] host-fed stream")
         out["host_fed"] = host_fed(tc, G, r, seed, w, nv)
         log("[bench] text edge list parsed on the device")
-        out["text_parse"] = parse_rate(tc, inputs, G)
+        # (at most the first 2^26 edges: about 1.2 GB of text)
+        out["text_parse"] = parse_rate(tc, inputs, G[:1 << 26])
+
+    if not args.no_extra_workload and args.workload != "rmat20":
+        log("[bench] extra: R-MAT scale 20 stream")
+        out["extra_workloads"] = {"rmat20": quick_rate(tc, inputs, "rmat20")}
 
     if not args.no_batched:
         out["batched"] = batched_comparison(tc, inputs, nstreams=args.streams)

@@ -108,8 +108,12 @@ int tc_set_vertex_bound(tc_state *s, uint64_t n);
 
 /* Pre-size the bank's step scratch for batches of up to max_w edges so that
  * later tc_process_batch calls with w <= max_w allocate nothing (needed
- * before capturing them into a HIP graph).  Blocking.  TC_ENOMEM on
- * failure. */
+ * before capturing them into a HIP graph: a captured step that needs more
+ * scratch than reserved returns TC_EINVAL before it synchronises, allocates
+ * or enqueues anything).  Once some step has been captured, a later growth
+ * of the scratch keeps the old block alive (captured graphs hold its
+ * addresses) until tc_destroy, or tc_multi_graph_reserve for a tc_multi.
+ * Blocking.  TC_ENOMEM on failure. */
 int tc_reserve(tc_state *s, uint32_t max_w);
 
 /* Enqueue on `stream` a return of every estimator to empty, with |E| = 0
@@ -233,9 +237,11 @@ void tc_multi_destroy(tc_multi *s);
  * *nedges (HOST).  Blocking (it returns the count).  TC_EINVAL for NULL
  * pointers, an odd number of ids, an id above 2^32 - 1, a line longer than
  * 4096 bytes, or more than max_edges edges (nothing useful is written
- * then); TC_ENOMEM if its scratch cannot be allocated.  It allocates and
- * frees device scratch (about a sixteenth of the text size) and waits for
- * `stream`, so it cannot be captured into a HIP graph. */
+ * then); TC_ENOMEM if its scratch cannot be allocated.  Its device
+ * scratch (about a sixteenth of the text size) is kept per device, grown to
+ * the largest text parsed so far and reused by later calls until the
+ * process ends; calls from several host threads are serialised.  It waits
+ * for `stream`, so it cannot be captured into a HIP graph. */
 int tc_parse_edges(const char *text, uint64_t nbytes, uint32_t *edges,
                    uint64_t max_edges, uint64_t *nedges, void *stream);
 

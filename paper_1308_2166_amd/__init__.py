@@ -150,16 +150,24 @@ def tc_create(r: int, seed: int) -> int:
     return h
 
 
-def tc_process_batch(state: int, edges, w: int | None = None, stream=None) -> None:
+def _batch_args(edges, w):
+    """(device address or None, w) of a batch; w defaults to the tensor's
+    rows and may not exceed them (the kernels would read past its end)."""
+    if edges is not None and w is not None and hasattr(edges, "shape") \
+            and len(edges.shape) >= 1 and w > edges.shape[0]:
+        raise ValueError(f"w = {w} exceeds the {edges.shape[0]} edges of the tensor")
     ptr, n = _edge_ptr(edges) if edges is not None else (0, 0)
-    _check(lib().tc_process_batch(state, ptr or None, n if w is None else w,
-                                  _stream_handle(stream)))
+    return ptr or None, n if w is None else w
+
+
+def tc_process_batch(state: int, edges, w: int | None = None, stream=None) -> None:
+    ptr, w = _batch_args(edges, w)
+    _check(lib().tc_process_batch(state, ptr, w, _stream_handle(stream)))
 
 
 def tc_process_batch_naive(state: int, edges, w: int | None = None, stream=None) -> None:
-    ptr, n = _edge_ptr(edges) if edges is not None else (0, 0)
-    _check(lib().tc_process_batch_naive(state, ptr or None, n if w is None else w,
-                                        _stream_handle(stream)))
+    ptr, w = _batch_args(edges, w)
+    _check(lib().tc_process_batch_naive(state, ptr, w, _stream_handle(stream)))
 
 
 def tc_parse_edges(text: torch.Tensor, max_edges: int | None = None, stream=None):

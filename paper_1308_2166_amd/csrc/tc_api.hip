@@ -12,10 +12,12 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/tc.h"
 #include "tc_internal.h"
+
 
 namespace tc {
 hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st, hipEvent_t* ev);
@@ -100,6 +102,64 @@ struct ParityScratch {
   SegDesc* segs = nullptr;    // device copy of the step's descriptors
 };
 
+// Sizes a step's scratch must hold.
+struct Sizes {
+  uint64_t arcs = 0;   // arc slots (2 w summed over segments)
+  uint64_t tiles = 0;  // radix tiles
+  uint64_t dir = 0;    // directory slots
+  uint64_t qt = 0;     // query-table slots
+  uint64_t need = 0;   // need bytes
+  uint64_t nest = 0;   // estimators (per-estimator step words)
+  uint32_t segs = 0;   // segments
+  bool fits(const Sizes& z) const {
+    return z.arcs <= arcs && z.tiles <= tiles && z.dir <= dir && z.qt <= qt &&
+           z.need <= need && z.nest <= nest && z.segs <= segs;
+  }
+  void grow(const Sizes& z) {
+    arcs = std::max(arcs, z.arcs), tiles = std::max(tiles, z.tiles);
+    dir = std::max(dir, z.dir), qt = std::max(qt, z.qt), need = std::max(need, z.need);
+    nest = std::max(nest, z.nest), segs = std::max(segs, z.segs);
+  }
+};
+
+// The per-step scratch buffers, carved from one block of device memory.
+struct Scratch {
+  uint64_t* arcs[2] = {nullptr, nullptr};
+  uint32_t* csum = nullptr;   // radix chunk sums / prefixes
+  DirSlot* dir = nullptr;
+  uint8_t* need = nullptr;
+  uint32_t* inv = nullptr;
+  uint32_t* hpart = nullptr;  // k_hist partial counts (one row per tile)
+  uint32_t* mpart = nullptr;  // k_hist partial max ids
+  ParityScratch par[2];
+};
+
+// Lay out the buffers of a step of sizes z from `base` (nullptr: only
+// count), each 256-byte aligned, with `nparity` copies of the per-parity
+// part.  Returns the bytes the layout takes.
+uint64_t carve(uint8_t* base, const Sizes& z, int nparity, Scratch* out) {
+  uint64_t off = 0;
+  auto take = [&](auto*& p, uint64_t n) {
+    using T = std::remove_reference_t<decltype(*p)>;
+    off = (off + 255) & ~255ull;
+    p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += std::max<uint64_t>(n, 1) * sizeof(T);
+  };
+  Scratch s;
+  take(s.arcs[0], z.arcs), take(s.arcs[1], z.arcs);
+  take(s.csum, ((z.tiles + kChunk - 1) / kChunk + z.segs) * kRowWords);
+  take(s.dir, z.dir), take(s.need, z.need), take(s.inv, z.arcs);
+  take(s.hpart, z.tiles * kRowWords), take(s.mpart, z.tiles);
+  for (int p = 0; p < nparity; ++p) {
+    ParityScratch& P = s.par[p];
+    take(P.work, z.segs), take(P.qt, z.qt), take(P.qfp, z.qt), take(P.qbits, z.qt / 32);
+    take(P.segs, z.segs);
+  }
+  if (nparity == 1) s.par[1] = s.par[0];
+  if (out) *out = s;
+  return (off + 255) & ~255ull;
+}
+
 struct Engine {
   int device = 0;
   uint32_t nbanks = 0;
@@ -124,18 +184,15 @@ struct Engine {
   unsigned long long* h_sums = nullptr;  // pinned
   uint32_t* h_err = nullptr;             // pinned
 
-  // step scratch shared by the phases that never overlap
-  uint64_t cap_arcs = 0, cap_tiles = 0, cap_dir = 0, cap_qt = 0,
-           cap_need = 0;
-  uint32_t cap_segs = 0;
-  uint64_t* arcs[2] = {nullptr, nullptr};
-  uint32_t* csum = nullptr;  // radix chunk sums / prefixes
-  DirSlot* dir = nullptr;
-  uint8_t* need = nullptr;
-  uint32_t* inv = nullptr;
-  uint32_t* hpart = nullptr;  // k_hist partial counts (one row per tile)
-  uint32_t* mpart = nullptr;  // k_hist partial max ids
-  ParityScratch par[2];
+  // step scratch (one device block, carved), its capacity, and blocks
+  // retired by a growth after some step was captured into a HIP graph
+  // (a captured graph keeps their addresses; they are freed by
+  // tc_multi_graph_reserve or destroy)
+  Sizes cap;
+  uint8_t* block = nullptr;
+  Scratch S;
+  bool captured = false;
+  std::vector<uint8_t*> retired;
 
   // the Step-3 phase runs on st2; evB orders it after k_est, evC orders
   // the next k_est (and any state access) after it
@@ -210,6 +267,7 @@ struct Engine {
     if (h_err) (void)hipHostFree(h_err);
     h_sums = nullptr, h_err = nullptr;
     free_scratch();
+    free_retired();
     for (int i = 0; i < kRing; ++i) {
       if (stage[i]) (void)hipHostFree(stage[i]);
       if (stage_ev[i]) (void)hipEventDestroy(stage_ev[i]);
@@ -223,14 +281,16 @@ struct Engine {
   }
 
   void free_scratch() {
-    dfree(arcs[0]), dfree(arcs[1]), dfree(csum);
-    dfree(dir), dfree(need), dfree(inv), dfree(hpart), dfree(mpart);
-    for (ParityScratch& p : par) {
-      dfree(p.work), dfree(p.qt), dfree(p.qfp), dfree(p.qbits);
-      dfree(p.segs);
-    }
-    cap_arcs = cap_tiles = cap_dir = cap_qt = cap_need = 0;
-    cap_segs = 0;
+    if (block) (void)hipFree(block);
+    block = nullptr;
+    S = Scratch{};
+    cap = Sizes{};
+  }
+
+  // free the blocks that captured graphs may still have referred to
+  void free_retired() {
+    for (uint8_t* b : retired) (void)hipFree(b);
+    retired.clear();
   }
 
   int init(uint32_t n, const uint32_t* rr, const uint64_t* seeds) {
@@ -276,42 +336,34 @@ struct Engine {
     return TC_OK;
   }
 
-  int ensure_scratch(uint64_t arcs_n, uint64_t tiles, uint64_t dir_n,
-                     uint64_t qt_n, uint64_t need_n, uint32_t nseg,
-                     hipStream_t st) {
-    if (arcs_n <= cap_arcs && tiles <= cap_tiles && dir_n <= cap_dir &&
-        qt_n <= cap_qt && need_n <= cap_need && nseg <= cap_segs)
-      return TC_OK;
+  // Grow the step scratch to hold z (no-op when it does).  After a step
+  // was captured into a HIP graph the old block is retired, not freed: the
+  // graph's kernels keep its addresses.
+  int ensure_scratch(const Sizes& z, hipStream_t st) {
+    if (cap.fits(z)) return TC_OK;
     wait_all();
-    (void)hipStreamSynchronize(st);
+    if (st) (void)hipStreamSynchronize(st);
+    Sizes want = cap;
+    want.grow(z);
+    if (captured && block) {
+      retired.push_back(block);
+      block = nullptr;
+    }
     free_scratch();
-    cap_arcs = std::max(arcs_n, cap_arcs);
-    cap_tiles = std::max(tiles, cap_tiles);
-    cap_dir = std::max(dir_n, cap_dir);
-    cap_qt = std::max(qt_n, cap_qt);
-    cap_need = std::max(need_n, cap_need);
-    cap_segs = std::max(nseg, cap_segs);
-    bool bad = dalloc(&arcs[0], cap_arcs) || dalloc(&arcs[1], cap_arcs) ||
-               dalloc(&csum, ((cap_tiles + kChunk - 1) / kChunk + cap_segs) * kRowWords) ||
-               dalloc(&dir, cap_dir) || dalloc(&need, cap_need) ||
-               dalloc(&inv, cap_arcs) ||
-               dalloc(&hpart, cap_tiles * kRowWords) ||
-               dalloc(&mpart, cap_tiles);
-    for (ParityScratch& p : par)
-      bad = bad || dalloc(&p.work, cap_segs) || dalloc(&p.qt, cap_qt) ||
-            dalloc(&p.qfp, cap_qt) || dalloc(&p.qbits, cap_qt / 32) ||
-            dalloc(&p.segs, cap_segs);
-    if (bad) {
-      free_scratch();
+    const uint64_t bytes = carve(nullptr, want, 2, nullptr);
+    if (hipMalloc(reinterpret_cast<void**>(&block), bytes) != hipSuccess) {
+      block = nullptr;
       return fail(TC_ENOMEM, "device allocation of step scratch failed");
     }
-    // zero = "no tag" for the directory, cleared look-back and work areas
-    bad = hipMemsetAsync(dir, 0, sizeof(DirSlot) * cap_dir, st) ||
-          hipMemsetAsync(need, 0, cap_need, st);
-    for (ParityScratch& p : par)
-      bad = bad || hipMemsetAsync(p.work, 0, sizeof(SegWork) * cap_segs, st) ||
-            hipMemsetAsync(p.qt, 0xFF, sizeof(uint32_t) * cap_qt, st) ||
-            hipMemsetAsync(p.qfp, 0, cap_qt, st);
+    carve(block, want, 2, &S);
+    cap = want;
+    // zero = "no tag" for the directory, cleared work areas
+    bool bad = hipMemsetAsync(S.dir, 0, sizeof(DirSlot) * cap.dir, st) ||
+               hipMemsetAsync(S.need, 0, cap.need, st);
+    for (ParityScratch& p : S.par)
+      bad = bad || hipMemsetAsync(p.work, 0, sizeof(SegWork) * cap.segs, st) ||
+            hipMemsetAsync(p.qt, 0xFF, sizeof(uint32_t) * cap.qt, st) ||
+            hipMemsetAsync(p.qfp, 0, cap.qt, st);
     if (bad || hipStreamSynchronize(st))
       return fail(TC_EHIP, "clearing step scratch failed");
     return TC_OK;
@@ -354,20 +406,21 @@ struct Engine {
     return TC_OK;
   }
 
-  // reserve == true: size the scratch for this step without launching it
-  // overlap == true: Step 3 runs on st2 and the next step (of the same API
-  // call) waits for it before its Steps 1-2; the call's last step must not
-  // overlap, so every call returns with all its work ordered on st
-  int step(uint32_t nchunks, const uint32_t* ids, const uint32_t* const* edges,
-           const uint32_t* w, hipStream_t st, bool reserve = false,
-           bool overlap = false) {
-    if (sticky != TC_OK) return fail(sticky, "an earlier batch failed on the device");
+  // The segments of one step: a descriptor per chunk with w > 0 and the
+  // scratch sizes they take.  Validates the chunk list.
+  struct Plan {
     std::vector<SegDesc> segs;
-    segs.reserve(nchunks);
-    std::vector<char> seen(nbanks, 0);
-    uint64_t arcs_n = 0, tiles = 0, dir_n = 0, qt_n = 0, need_n = 0, nest = 0,
-             hblks = 0, chunks = 0;
+    std::vector<uint32_t> bank;  // bank of each segment
+    Sizes z;
+    uint64_t hblks = 0, chunks = 0;
     bool big_qt = false;  // some segment's query table gets the bitmap
+  };
+
+  int plan(uint32_t nchunks, const uint32_t* ids, const uint32_t* const* edges,
+           const uint32_t* w, bool reserve, Plan& pl) {
+    pl.segs.reserve(nchunks);
+    std::vector<char> seen(nbanks, 0);
+    Sizes& z = pl.z;
     for (uint32_t k = 0; k < nchunks; ++k) {
       const uint32_t b = ids[k];
       if (b >= nbanks) return fail(TC_EINVAL, "bank id out of range");
@@ -384,85 +437,143 @@ struct Engine {
       d.batch = batch[b];
       d.key0 = key0[b];
       d.est_off = est_off[b];
-      d.gest_off = nest;
-      d.arc_off = arcs_n;
-      d.dir_off = dir_n;
-      d.qt_off = qt_n;
+      d.gest_off = z.nest;
+      d.arc_off = z.arcs;
+      d.dir_off = z.dir;
+      d.qt_off = z.qt;
       d.w = w[k];
       d.r = r[b];
-      d.tile_off = (uint32_t)tiles;
+      d.tile_off = (uint32_t)z.tiles;
       d.ntiles = (uint32_t)((2ull * w[k] + kTile - 1) / kTile);
-      d.hblk_off = (uint32_t)hblks;
+      d.hblk_off = (uint32_t)pl.hblks;
       d.nhblk = (d.ntiles + kHistTiles - 1) / kHistTiles;
-      hblks += d.nhblk;
-      d.chunk_off = (uint32_t)chunks;
+      pl.hblks += d.nhblk;
+      d.chunk_off = (uint32_t)pl.chunks;
       d.nchunks = (d.ntiles + kChunk - 1) / kChunk;
-      chunks += d.nchunks;
+      pl.chunks += d.nchunks;
       d.dir_log2 = dir_log2_for(w[k]);
       d.qt_log2 = qt_log2_for(r[b]);
-      big_qt = big_qt || d.qt_log2 > kBitmapMinLog2;
-      d.need_off = (uint32_t)need_n;
-      need_n += (w[k] + 15) / 16 * 16;
-      arcs_n += 2ull * w[k];
-      tiles += d.ntiles;
-      dir_n += 1ull << d.dir_log2;
-      qt_n += 1ull << d.qt_log2;
-      nest += r[b];
-      segs.push_back(d);
+      pl.big_qt = pl.big_qt || d.qt_log2 > kBitmapMinLog2;
+      d.need_off = (uint32_t)z.need;
+      z.need += (w[k] + 15) / 16 * 16;
+      z.arcs += 2ull * w[k];
+      z.tiles += d.ntiles;
+      z.dir += 1ull << d.dir_log2;
+      z.qt += 1ull << d.qt_log2;
+      z.nest += r[b];
+      pl.segs.push_back(d);
+      pl.bank.push_back(b);
     }
-    if (segs.empty()) return TC_OK;
-    if (tiles >= 0x7FFFFFFFull) return fail(TC_EINVAL, "step too large");
-    if (need_n >= 0xFFFFFFFFull) return fail(TC_EINVAL, "step too large");
-    int rc = ensure_scratch(arcs_n, tiles, dir_n, qt_n, need_n,
-                            (uint32_t)segs.size(), st);
-    if (rc || reserve) return rc;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cap) != hipSuccess)
-      return fail(TC_EHIP, "hipStreamIsCapturing failed");
-    const bool capturing = cap == hipStreamCaptureStatusActive;
-    if (capturing && timing) return fail(TC_EINVAL, "kernel timing is on while capturing");
-    if (++steps % 0xFFFF0000ull == 0 && !capturing) {
-      // directory tags are about to wrap: forget every entry (fill, not memset)
-      if (join(st) || launch_fill32(reinterpret_cast<uint32_t*>(dir), cap_dir * 4, 0, st))
-        return fail(TC_EHIP, "table reset failed");
-    }
-    ParityScratch& P = par[steps & 1];
+    z.segs = (uint32_t)pl.segs.size();
+    if (z.tiles >= 0x7FFFFFFFull || z.need >= 0xFFFFFFFFull)
+      return fail(TC_EINVAL, "step too large");
+    return TC_OK;
+  }
+
+  // kernel arguments of a planned step on scratch X (parity copy P)
+  StepArgs make_args(const Plan& pl, const Scratch& X, const ParityScratch& P) const {
+    const Sizes& z = pl.z;
     StepArgs a{};
-    a.nseg = (uint32_t)segs.size();
+    a.nseg = (uint32_t)pl.segs.size();
     a.segs = P.segs;
-    a.seg0 = segs[0];
-    a.ntiles = (uint32_t)tiles;
-    a.nhblk = (uint32_t)hblks;
-    a.nstep1 = (uint32_t)((nest + kBlock - 1) / kBlock);
-    a.hpart = hpart;
-    a.mpart = mpart;
-    a.nest = nest;
+    a.seg0 = pl.segs[0];
+    a.ntiles = (uint32_t)z.tiles;
+    a.nhblk = (uint32_t)pl.hblks;
+    a.nstep1 = (uint32_t)((z.nest + kBlock - 1) / kBlock);
+    a.hpart = X.hpart;
+    a.mpart = X.mpart;
+    a.nest = z.nest;
     a.tagp = tagp;
     a.r1 = R1, a.r2 = R2, a.cc = CC;
     a.work = P.work;
-    a.arcs[0] = arcs[0], a.arcs[1] = arcs[1];
-    a.csum = csum;
-    a.nchunk = (uint32_t)chunks;
-    a.dir = dir;
+    a.arcs[0] = X.arcs[0], a.arcs[1] = X.arcs[1];
+    a.csum = X.csum;
+    a.nchunk = (uint32_t)pl.chunks;
+    a.dir = X.dir;
     a.qt = P.qt;
     a.qfp = P.qfp;
-    a.qbits = big_qt ? P.qbits : nullptr;
-    a.qt_slots = qt_n;
+    a.qbits = pl.big_qt ? P.qbits : nullptr;
+    a.qt_slots = z.qt;
     a.j1 = J1;
     a.qq = QQ;
     a.qthr = QT;
-    a.need = need;
-    a.need_bytes = need_n;
-    a.inv = inv;
+    a.need = X.need;
+    a.need_bytes = z.need;
+    a.inv = X.inv;
     a.err = err;
     a.id_limit = id_limit;
     a.npass = npass;
     a.dbits = dbits;
-    a.single_chunk = dbits == 8 && chunks == segs.size() ? 1u : 0u;
+    a.single_chunk = dbits == 8 && pl.chunks == pl.segs.size() ? 1u : 0u;
+    return a;
+  }
+
+  // Enqueue phases A, B and C of one step (C on st2 when it may overlap
+  // the next step's A), then advance the banks' counters.
+  int launch(const Plan& pl, const StepArgs& a, hipStream_t st, hipEvent_t* ev,
+             bool overlap) {
+    // A: group the batch; B: Steps 1-2, after the previous step's Step 3;
+    // C: Step 3, on st2 when it may overlap the next step's A
+    if (launch_phase(0, a, st, ev) != hipSuccess)
+      return fail(TC_EHIP, "kernel launch failed");
+    int rc = join(st);
+    if (rc != TC_OK) return rc;
+    if (launch_phase(1, a, st, ev) != hipSuccess)
+      return fail(TC_EHIP, "kernel launch failed");
+    if (overlap) {
+      if (hipEventRecord(evB, st) != hipSuccess ||
+          hipStreamWaitEvent(st2, evB, 0) != hipSuccess ||
+          launch_phase(2, a, st2, ev) != hipSuccess ||
+          hipEventRecord(evC, st2) != hipSuccess)
+        return fail(TC_EHIP, "kernel launch failed");
+      c_pending = true;
+    } else if (launch_phase(2, a, st, ev) != hipSuccess) {
+      return fail(TC_EHIP, "kernel launch failed");
+    }
+    for (size_t k = 0; k < pl.segs.size(); ++k) {
+      m[pl.bank[k]] += pl.segs[k].w;
+      batch[pl.bank[k]] += 1;
+    }
+    last = st;
+    return TC_OK;
+  }
+
+  // reserve == true: size the scratch for this step without launching it
+  // overlap == true: Step 3 runs on st2 and the next step (of the same API
+  // call) waits for it before its Steps 1-2; the call's last step must not
+  // overlap, so every call returns with all its work ordered on st
+  int step(uint32_t nchunks, const uint32_t* ids, const uint32_t* const* edges,
+           const uint32_t* w, hipStream_t st, bool reserve = false,
+           bool overlap = false) {
+    if (sticky != TC_OK) return fail(sticky, "an earlier batch failed on the device");
+    Plan pl;
+    int rc = plan(nchunks, ids, edges, w, reserve, pl);
+    if (rc || pl.segs.empty()) return rc;
+    if (reserve) return ensure_scratch(pl.z, st);
+    // the capture status decides before anything may synchronize, allocate
+    // or free: growing the scratch under capture would do all three
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess)
+      return fail(TC_EHIP, "hipStreamIsCapturing failed");
+    const bool capturing = cs == hipStreamCaptureStatusActive;
+    if (capturing && !cap.fits(pl.z))
+      return fail(TC_EINVAL, "a step being captured needs more scratch than reserved "
+                             "(call tc_reserve / tc_multi_reserve before capturing)");
+    if (capturing && timing) return fail(TC_EINVAL, "kernel timing is on while capturing");
+    rc = ensure_scratch(pl.z, st);
+    if (rc) return rc;
+    if (++steps % 0xFFFF0000ull == 0 && !capturing) {
+      // directory tags are about to wrap: forget every entry (fill, not memset)
+      if (join(st) || launch_fill32(reinterpret_cast<uint32_t*>(S.dir), cap.dir * 4, 0, st))
+        return fail(TC_EHIP, "table reset failed");
+    }
+    const ParityScratch& P = S.par[steps & 1];
+    StepArgs a = make_args(pl, S, P);
     if (a.nseg > 1) {
-      rc = stage_descs(segs, P.segs, st, capturing);
+      rc = stage_descs(pl.segs, P.segs, st, capturing);
       if (rc) return rc;
     }
+    if (capturing) captured = true;
     hipEvent_t* ev = nullptr;
     if (timing) {
       if (!ev_free.empty()) {
@@ -478,30 +589,7 @@ struct Engine {
       ev_pending.push_back(ev);
       ev_launched.push_back(launched_kernels(npass, a.single_chunk != 0, a.qbits != nullptr));
     }
-    // A: group the batch; B: Steps 1-2, after the previous step's Step 3;
-    // C: Step 3, on st2 when it may overlap the next step's A
-    if (launch_phase(0, a, st, ev) != hipSuccess)
-      return fail(TC_EHIP, "kernel launch failed");
-    if ((rc = join(st)) != TC_OK) return rc;
-    if (launch_phase(1, a, st, ev) != hipSuccess)
-      return fail(TC_EHIP, "kernel launch failed");
-    if (overlap) {
-      if (hipEventRecord(evB, st) != hipSuccess ||
-          hipStreamWaitEvent(st2, evB, 0) != hipSuccess ||
-          launch_phase(2, a, st2, ev) != hipSuccess ||
-          hipEventRecord(evC, st2) != hipSuccess)
-        return fail(TC_EHIP, "kernel launch failed");
-      c_pending = true;
-    } else if (launch_phase(2, a, st, ev) != hipSuccess) {
-      return fail(TC_EHIP, "kernel launch failed");
-    }
-    for (uint32_t k = 0; k < nchunks; ++k) {
-      if (w[k] == 0) continue;
-      m[ids[k]] += w[k];
-      batch[ids[k]] += 1;
-    }
-    last = st;
-    return TC_OK;
+    return launch(pl, a, st, ev, overlap);
   }
 
   // one batch for bank b by the per-estimator kernel (same state, same draws)
@@ -572,6 +660,10 @@ struct Engine {
     // that depends on no event recorded outside it
     wait_all();
     c_pending = false;
+    // graphs captured before are void from here on: the scratch blocks
+    // they referred to can go
+    free_retired();
+    captured = false;
     for (SegDesc* g : graph_stage) (void)hipHostFree(g);
     graph_stage.assign(nsteps, nullptr);
     graph_next = 0;
@@ -593,7 +685,7 @@ struct Engine {
     if (e & kErrRange) sticky = TC_EINVAL;
     else if (e & kErrSelfLoop) sticky = TC_EBADEDGE;
     else if (e & kErrOverflow) sticky = TC_EOVERFLOW;
-    else if (e & (kErrProbe | kErrStall)) sticky = TC_EHIP;
+    else if (e & (kErrProbe | kErrIndex)) sticky = TC_EHIP;
     if (sticky == TC_EINVAL)
       return fail(sticky, "a batch contained a vertex id at or above the declared bound");
     if (sticky == TC_EBADEDGE) return fail(sticky, "a batch contained a self-loop");

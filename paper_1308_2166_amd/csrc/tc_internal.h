@@ -54,12 +54,11 @@ constexpr uint32_t kChiMax = 0x7FFFFFFFu;
 constexpr uint32_t kErrSelfLoop = 1u;
 constexpr uint32_t kErrOverflow = 2u;
 constexpr uint32_t kErrProbe = 4u;  // a table probe ran past its bound
-constexpr uint32_t kErrStall = 8u;  // a bounded wait gave up
+constexpr uint32_t kErrIndex = 8u;  // an index that no valid step produces
+                                    // (guards against corrupt scratch)
 constexpr uint32_t kErrRange = 16u;  // a vertex id above the declared bound
 // errors after which the rest of a step must not trust its scratch
-constexpr uint32_t kErrFatal = kErrSelfLoop | kErrStall | kErrRange;
-// bounded waits: a look-back or a busy table slot is given this many polls
-constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr uint32_t kErrFatal = kErrSelfLoop | kErrIndex | kErrRange;
 
 // one chunk of a step (device view)
 struct SegDesc {

@@ -1039,7 +1039,7 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
     const uint32_t iu = side_u ? iv2.y : iv2.x;
     const uint32_t iv = side_u ? iv2.x : iv2.y;
     const bool ok = iu >= su.x && iu < su.y && iv >= sv.x && iv < sv.y;
-    if (!ok) atomicOr(a.err, kErrStall);
+    if (!ok) atomicOr(a.err, kErrIndex);
     ld = ok ? su.y - 1 - iu : 0u;
     rd = ok ? sv.y - 1 - iv : 0u;
   } else {
@@ -1059,7 +1059,7 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
                                     : sv.y - 1 - (uint32_t)(phi - ld);
       p2 = ((uint32_t)arc[idx] & kIdMask) >> 1;  // arc id -> batch position
       if (p2 >= S.w) {  // cannot happen: arcs carry positions < w
-        atomicOr(a.err, kErrStall);
+        atomicOr(a.err, kErrIndex);
         p2 = 0;
       }
       const uint2 ed = W[p2];
@@ -1370,7 +1370,7 @@ __global__ __launch_bounds__(kBlock) void k_naive(NaiveArgs a) {
     }
     if (pick) {
       if (p2 == kNone) {  // cannot happen: kk < the count just taken
-        atomicOr(a.err, kErrStall);
+        atomicOr(a.err, kErrIndex);
         pick = false;
       } else {
         const uint2 ed = W[p2];

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "../../include/tc.h"
 
@@ -305,6 +306,16 @@ __global__ __launch_bounds__(kPBlock) void k_tok_write(const uint8_t* text, uint
   }
 }
 
+// Parser scratch, one block per device: grown to the largest text parsed so
+// far and reused by later calls (held until the process ends).  The lock
+// also keeps two host threads from parsing into one block at once.
+struct ParseScratch {
+  uint8_t* p = nullptr;
+  uint64_t cap = 0;
+};
+std::mutex g_parse_mu;
+ParseScratch g_parse[64];
+
 }  // namespace
 
 namespace tc {
@@ -323,11 +334,24 @@ int tc_parse_edges(const char* text, uint64_t nbytes, uint32_t* edges, uint64_t 
   if (!edges) max_edges = 0;  // nothing may be written
   const uint64_t nblk = (nbytes + kPTile - 1) / kPTile;
   if (nblk > 0xFFFFFFFFull / kPBlock) return tc::report(TC_EINVAL, "text too large");
-  // one scratch allocation: [total u64][err u32][pad][block counts][thread counts]
-  uint8_t* scratch = nullptr;
+  // scratch: [total u64][err u32][pad][block counts][thread counts]
   const uint64_t bytes = 16 + sizeof(uint32_t) * nblk * (1 + kPBlock);
-  if (hipMalloc(reinterpret_cast<void**>(&scratch), bytes) != hipSuccess)
-    return tc::report(TC_ENOMEM, "device allocation for parsing failed");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+    return tc::report(TC_EHIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(g_parse_mu);
+  ParseScratch& ps = g_parse[dev];
+  if (ps.cap < bytes) {
+    if (ps.p) (void)hipFree(ps.p);
+    ps.p = nullptr;
+    ps.cap = 0;
+    if (hipMalloc(reinterpret_cast<void**>(&ps.p), bytes) != hipSuccess) {
+      ps.p = nullptr;
+      return tc::report(TC_ENOMEM, "device allocation for parsing failed");
+    }
+    ps.cap = bytes;
+  }
+  uint8_t* scratch = ps.p;
   uint64_t* total = reinterpret_cast<uint64_t*>(scratch);
   uint32_t* err = reinterpret_cast<uint32_t*>(scratch + 8);
   uint32_t* block_tok = reinterpret_cast<uint32_t*>(scratch + 16);
@@ -351,7 +375,6 @@ int tc_parse_edges(const char* text, uint64_t nbytes, uint32_t* edges, uint64_t 
         hipStreamSynchronize(st) != hipSuccess)
       rc = TC_EHIP;
   }
-  (void)hipFree(scratch);
   const uint64_t tot = h[0];
   const uint32_t perr = (uint32_t)h[1];
   if (rc == TC_EHIP) return tc::report(rc, "a HIP call failed while parsing");

@@ -97,3 +97,14 @@ def test_kernel_names_in_launch_order():
     assert [tc.tc_kernel_name(k) for k in range(tc.tc_num_kernels())] == want
     bench = __import__("bench")
     assert [n for n in bench.STEP_ORDER] == want
+
+
+def test_binding_refuses_w_beyond_the_tensor():
+    # a w above the tensor's rows would make the kernels read past its end:
+    # the binding refuses it before any library call (no GPU needed)
+    import torch
+    import paper_1308_2166_amd as tc
+    e = torch.zeros((5, 2), dtype=torch.int32)
+    for f in (tc.tc_process_batch, tc.tc_process_batch_naive):
+        with pytest.raises(ValueError):
+            f(0, e, w=6)

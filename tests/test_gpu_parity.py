@@ -470,6 +470,46 @@ def test_graph_replay_wide_digits_and_bitmap(tc):
         _ = torch.ones(1000, device="cuda").sum().item()
 
 
+def test_capture_refuses_growth_and_graph_survives_later_growth(tc):
+    # (1) a step captured with less scratch reserved than it needs is refused
+    # with TC_EINVAL before it synchronises, allocates or enqueues anything;
+    # (2) a captured graph keeps replaying correctly after an eager step has
+    # grown the bank's scratch (the block it captured is kept, not freed)
+    E = np_edges(inputs.rmat(13, 30000, seed=18))
+    dev = to_dev(E)
+    g = tc.Bank(3000, 23)
+    tc.tc_reserve(g.h, 2000)
+    x = torch.zeros(16, device="cuda")
+    gr = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    rc = None
+    with torch.cuda.graph(gr, stream=cs):
+        x.add_(1)
+        rc = tc.lib().tc_process_batch(g.h, dev[:5000].data_ptr(), 5000, cs.cuda_stream)
+    assert rc == tc.TC_EINVAL and g.batch == 0
+    torch.cuda.synchronize()
+    # (2)
+    h = tc.Bank(3000, 23)
+    tc.tc_reserve(h.h, 2000)
+    gr2 = torch.cuda.CUDAGraph()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(gr2, stream=cs):
+        tc.tc_reset(h.h, cs)
+        tc.tc_process_batch(h.h, dev[:2000], stream=cs)
+    gr2.replay()
+    torch.cuda.synchronize()
+    o = O.run_stream(E[:2000], 3000, 23, 2000)
+    assert_same(h.state(), o.state(), "first replay")
+    tc.tc_process_batch(h.h, dev[2000:30000])  # grows the scratch
+    h.sync()
+    for rep in range(2):
+        gr2.replay()
+        torch.cuda.synchronize()
+        assert_same(h.state(), o.state(), f"replay {rep} after growth")
+        _ = torch.ones(1000, device="cuda").sum().item()
+
+
 # -- continuous batching: each stream's result alone == in the mix -----------------------
 
 def test_served_streams_equal_their_alone_runs(tc):
