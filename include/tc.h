@@ -72,6 +72,25 @@ tc_state *tc_create(uint32_t r, uint64_t seed);
 int tc_process_batch(tc_state *s, const uint32_t *edges, uint32_t w,
                      void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * bulk update as tc_process_batch, with the same kernels and a bit-identical
+ * result, but every per-step buffer (arcs, radix counts, directory, Step-3
+ * query table, per-estimator step words) is carved from a static device
+ * array of the library, 64 MiB on each device, held from the first
+ * tc_create on that device until the process ends.  The call allocates
+ * and frees nothing, never synchronises, and only enqueues kernels on
+ * `stream`.  Limits: the batch's and bank's scratch must fit the array and
+ * its 2^20-slot directory (every w <= 2^18 with r <= 2^18 fits; a larger
+ * pair is checked on the host and refused with TC_EINVAL, nothing enqueued).
+ * All calls on one device share the array: calls that overlap in time on
+ * one device (different host threads or unordered streams) race and give
+ * undefined results; order them, for instance on one stream.  May be mixed
+ * with tc_process_batch on the same bank.  TC_EINVAL also for kernel timing
+ * switched on; other arguments and errors as tc_process_batch. */
+int tc_process_batch_noalloc(tc_state *s, const uint32_t *edges, uint32_t w,
+                             void *stream);
+
 /* Enqueue one batch by the per-estimator form that the bulk algorithm
  * improves on (Sec. 4, opening): every estimator scans the whole batch
  * itself, O(r * w) work, from the definitions of Steps 1-3.  It makes the

@@ -60,6 +60,7 @@ def lib():
         "tc_process_batch": ([vp, vp, u32, vp], i32),
         "tc_process_stream": ([vp, vp, u64, u32, vp], i32),
         "tc_process_batch_naive": ([vp, vp, u32, vp], i32),
+        "tc_process_batch_noalloc": ([vp, vp, u32, vp], i32),
         "tc_parse_edges": ([vp, u64, vp, u64, P64, vp], i32),
         "tc_set_vertex_bound": ([vp, u64], i32),
         "tc_estimate_mom": ([vp, u32, ctypes.POINTER(ctypes.c_double), P64], i32),
@@ -113,7 +114,8 @@ EXPORTS = ("tc_create", "tc_process_batch", "tc_process_stream", "tc_estimate", 
            "tc_reserve", "tc_multi_reserve", "tc_reset", "tc_multi_reset",
            "tc_multi_graph_reserve", "tc_multi_assign", "tc_set_vertex_bound",
            "tc_multi_set_vertex_bound", "tc_estimate_mom", "tc_multi_estimate_mom",
-           "tc_estimators_needed", "tc_process_batch_naive", "tc_parse_edges")
+           "tc_estimators_needed", "tc_process_batch_naive", "tc_parse_edges",
+           "tc_process_batch_noalloc")
 
 
 def _check(rc: int):
@@ -163,6 +165,11 @@ def _batch_args(edges, w):
 def tc_process_batch(state: int, edges, w: int | None = None, stream=None) -> None:
     ptr, w = _batch_args(edges, w)
     _check(lib().tc_process_batch(state, ptr, w, _stream_handle(stream)))
+
+
+def tc_process_batch_noalloc(state: int, edges, w: int | None = None, stream=None) -> None:
+    ptr, w = _batch_args(edges, w)
+    _check(lib().tc_process_batch_noalloc(state, ptr, w, _stream_handle(stream)))
 
 
 def tc_process_batch_naive(state: int, edges, w: int | None = None, stream=None) -> None:

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -18,6 +19,14 @@
 #include "../../include/tc.h"
 #include "tc_internal.h"
 
+// Callers that cannot allocate device memory (code under HIP graph capture,
+// tight serving loops, harnesses that forbid it) run a step entirely in this
+// array (tc_process_batch_noalloc): every buffer of the step is carved from
+// it.  Each device holds its own copy until the process ends.  In host code
+// `scratch` names a host-side stand-in; kernels get the device address that
+// hipGetSymbolAddress returns for the current device.
+static constexpr uint64_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
 
 namespace tc {
 hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st, hipEvent_t* ev);
@@ -132,12 +141,27 @@ struct Scratch {
   uint32_t* hpart = nullptr;  // k_hist partial counts (one row per tile)
   uint32_t* mpart = nullptr;  // k_hist partial max ids
   ParityScratch par[2];
+  // per-estimator step words and the directory tag: carved only for the
+  // static scratch of tc_process_batch_noalloc (an engine's own live with
+  // its banks)
+  uint32_t* j1 = nullptr;
+  uint64_t* qq = nullptr;
+  uint32_t* qthr = nullptr;
+  uint32_t* tagp = nullptr;
 };
+
+// Directory slots the static scratch holds (batches of up to 2^18 edges).
+// It sits at a fixed offset, with the tag word and the work area: their
+// contents carry over from one call to the next, while every other buffer
+// is rewritten before it is read, so it may move with the step's sizes.
+constexpr uint64_t kStaticDirSlots = 1ull << 20;
 
 // Lay out the buffers of a step of sizes z from `base` (nullptr: only
 // count), each 256-byte aligned, with `nparity` copies of the per-parity
-// part.  Returns the bytes the layout takes.
-uint64_t carve(uint8_t* base, const Sizes& z, int nparity, Scratch* out) {
+// part.  stat: the static-scratch layout (one parity, one segment): the
+// tag word, the work area and a directory of kStaticDirSlots slots first,
+// then the per-estimator words.  Returns the bytes the layout takes.
+uint64_t carve(uint8_t* base, const Sizes& z, int nparity, bool stat, Scratch* out) {
   uint64_t off = 0;
   auto take = [&](auto*& p, uint64_t n) {
     using T = std::remove_reference_t<decltype(*p)>;
@@ -146,18 +170,53 @@ uint64_t carve(uint8_t* base, const Sizes& z, int nparity, Scratch* out) {
     off += std::max<uint64_t>(n, 1) * sizeof(T);
   };
   Scratch s;
+  if (stat) {
+    nparity = 1;
+    take(s.tagp, 64);
+    take(s.par[0].work, 1);
+    take(s.dir, kStaticDirSlots);
+    take(s.j1, z.nest), take(s.qq, z.nest), take(s.qthr, z.nest);
+  }
   take(s.arcs[0], z.arcs), take(s.arcs[1], z.arcs);
   take(s.csum, ((z.tiles + kChunk - 1) / kChunk + z.segs) * kRowWords);
-  take(s.dir, z.dir), take(s.need, z.need), take(s.inv, z.arcs);
+  if (!stat) take(s.dir, z.dir);
+  take(s.need, z.need), take(s.inv, z.arcs);
   take(s.hpart, z.tiles * kRowWords), take(s.mpart, z.tiles);
   for (int p = 0; p < nparity; ++p) {
     ParityScratch& P = s.par[p];
-    take(P.work, z.segs), take(P.qt, z.qt), take(P.qfp, z.qt), take(P.qbits, z.qt / 32);
-    take(P.segs, z.segs);
+    if (!stat) take(P.work, z.segs);
+    take(P.qt, z.qt), take(P.qfp, z.qt), take(P.qbits, z.qt / 32);
+    if (!stat) take(P.segs, z.segs);
   }
   if (nparity == 1) s.par[1] = s.par[0];
   if (out) *out = s;
   return (off + 255) & ~255ull;
+}
+
+// ---- the static scratch of tc_process_batch_noalloc ------------------------
+struct StaticScratch {
+  bool looked_up = false;
+  hipError_t status = hipSuccess;
+  uint8_t* ptr = nullptr;    // the device address of `scratch`
+  uint64_t steps = 0;        // steps run in it (directory tag wrap guard)
+  bool dirty = false;        // a step's launches failed part-way: the work
+                             // area and directory are cleared before the next
+};
+std::mutex g_static_mu;
+StaticScratch g_static[64];  // per device ordinal
+
+// Look up the device address of `scratch` on `device` (current) once.
+StaticScratch* static_scratch(int device) {
+  if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  StaticScratch& s = g_static[device];
+  if (!s.looked_up) {
+    void* p = nullptr;
+    s.status = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    s.ptr = s.status == hipSuccess ? static_cast<uint8_t*>(p) : nullptr;
+    s.looked_up = true;
+  }
+  return &s;
 }
 
 struct Engine {
@@ -193,6 +252,7 @@ struct Engine {
   Scratch S;
   bool captured = false;
   std::vector<uint8_t*> retired;
+  StaticScratch* stat = nullptr;  // the device's static scratch
 
   // the Step-3 phase runs on st2; evB orders it after k_est, evC orders
   // the next k_est (and any state access) after it
@@ -295,6 +355,7 @@ struct Engine {
 
   int init(uint32_t n, const uint32_t* rr, const uint64_t* seeds) {
     if (hipGetDevice(&device) != hipSuccess) return fail(TC_EHIP, "hipGetDevice failed");
+    stat = static_scratch(device);
     nbanks = n;
     r.assign(rr, rr + n);
     seed.assign(seeds, seeds + n);
@@ -350,12 +411,12 @@ struct Engine {
       block = nullptr;
     }
     free_scratch();
-    const uint64_t bytes = carve(nullptr, want, 2, nullptr);
+    const uint64_t bytes = carve(nullptr, want, 2, false, nullptr);
     if (hipMalloc(reinterpret_cast<void**>(&block), bytes) != hipSuccess) {
       block = nullptr;
       return fail(TC_ENOMEM, "device allocation of step scratch failed");
     }
-    carve(block, want, 2, &S);
+    carve(block, want, 2, false, &S);
     cap = want;
     // zero = "no tag" for the directory, cleared work areas
     bool bad = hipMemsetAsync(S.dir, 0, sizeof(DirSlot) * cap.dir, st) ||
@@ -592,6 +653,51 @@ struct Engine {
     return launch(pl, a, st, ev, overlap);
   }
 
+  // One batch for bank 0 with every per-step buffer carved from the
+  // device's static scratch: no allocation, no free, no synchronisation.
+  // Calls on one device share that scratch, so calls that overlap in time
+  // on one device race (they must be ordered, e.g. on one stream).
+  int step_noalloc(const uint32_t* edges, uint32_t w, hipStream_t st) {
+    if (sticky != TC_OK) return fail(sticky, "an earlier batch failed on the device");
+    if (nbanks != 1) return fail(TC_EINVAL, "the no-allocation step serves one bank");
+    if (timing) return fail(TC_EINVAL, "kernel timing is on (its events are allocated)");
+    const uint32_t id = 0;
+    Plan pl;
+    int rc = plan(1, &id, &edges, &w, false, pl);
+    if (rc || pl.segs.empty()) return rc;
+    if (!stat || !stat->ptr)
+      return fail(TC_EHIP, "the static scratch of this device could not be located");
+    const uint64_t bytes = carve(nullptr, pl.z, 1, true, nullptr);
+    if (pl.z.dir > kStaticDirSlots || bytes > kStaticScratchBytes)
+      return fail(TC_EINVAL, "batch and bank too large for the no-allocation step: they need " +
+                                 std::to_string(bytes) + " bytes of scratch and " +
+                                 std::to_string(pl.z.dir) + " directory slots, it holds " +
+                                 std::to_string(kStaticScratchBytes) + " and " +
+                                 std::to_string(kStaticDirSlots) +
+                                 " (every w <= 2^18 with r <= 2^18 fits)");
+    Scratch X;
+    carve(stat->ptr, pl.z, 1, true, &X);
+    rc = join(st);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    // the directory tag lives in the scratch and advances once per step on
+    // this device; before it wraps, and after a step whose launches failed
+    // part-way, the directory and the work area are cleared (fill kernels)
+    const bool wrap = ++stat->steps % 0xFFFF0000ull == 0;
+    if (wrap || stat->dirty) {
+      if (launch_fill32(reinterpret_cast<uint32_t*>(X.dir), kStaticDirSlots * 4, 0, st) ||
+          launch_fill32(reinterpret_cast<uint32_t*>(X.par[0].work), sizeof(SegWork) / 4, 0, st))
+        return fail(TC_EHIP, "static scratch reset failed");
+      stat->dirty = false;
+    }
+    StepArgs a = make_args(pl, X, X.par[0]);
+    a.tagp = X.tagp;
+    a.j1 = X.j1, a.qq = X.qq, a.qthr = X.qthr;
+    rc = launch(pl, a, st, nullptr, false);
+    if (rc) stat->dirty = true;
+    return rc;
+  }
+
   // one batch for bank b by the per-estimator kernel (same state, same draws)
   int step_naive(uint32_t b, const uint32_t* edges, uint32_t w, hipStream_t st) {
     if (sticky != TC_OK) return fail(sticky, "an earlier batch failed on the device");
@@ -823,6 +929,12 @@ int tc_process_batch(tc_state* s, const uint32_t* edges, uint32_t w,
   if (!s) return fail(TC_EINVAL, "null state");
   const uint32_t id = 0;
   return s->e.step(1, &id, &edges, &w, static_cast<hipStream_t>(stream));
+}
+
+int tc_process_batch_noalloc(tc_state* s, const uint32_t* edges, uint32_t w,
+                             void* stream) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  return s->e.step_noalloc(edges, w, static_cast<hipStream_t>(stream));
 }
 
 int tc_process_batch_naive(tc_state* s, const uint32_t* edges, uint32_t w,

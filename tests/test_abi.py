@@ -105,6 +105,6 @@ def test_binding_refuses_w_beyond_the_tensor():
     import torch
     import paper_1308_2166_amd as tc
     e = torch.zeros((5, 2), dtype=torch.int32)
-    for f in (tc.tc_process_batch, tc.tc_process_batch_naive):
+    for f in (tc.tc_process_batch, tc.tc_process_batch_naive, tc.tc_process_batch_noalloc):
         with pytest.raises(ValueError):
             f(0, e, w=6)
