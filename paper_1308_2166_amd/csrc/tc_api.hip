@@ -116,17 +116,19 @@ struct Sizes {
   uint64_t arcs = 0;   // arc slots (2 w summed over segments)
   uint64_t tiles = 0;  // radix tiles
   uint64_t dir = 0;    // directory slots
+  uint64_t doff = 0;   // dense-directory words
   uint64_t qt = 0;     // query-table slots
   uint64_t need = 0;   // need bytes
   uint64_t nest = 0;   // estimators (per-estimator step words)
   uint32_t segs = 0;   // segments
   bool fits(const Sizes& z) const {
-    return z.arcs <= arcs && z.tiles <= tiles && z.dir <= dir && z.qt <= qt &&
+    return z.arcs <= arcs && z.tiles <= tiles && z.dir <= dir && z.doff <= doff && z.qt <= qt &&
            z.need <= need && z.nest <= nest && z.segs <= segs;
   }
   void grow(const Sizes& z) {
     arcs = std::max(arcs, z.arcs), tiles = std::max(tiles, z.tiles);
     dir = std::max(dir, z.dir), qt = std::max(qt, z.qt), need = std::max(need, z.need);
+    doff = std::max(doff, z.doff);
     nest = std::max(nest, z.nest), segs = std::max(segs, z.segs);
   }
 };
@@ -136,6 +138,7 @@ struct Scratch {
   uint64_t* arcs[2] = {nullptr, nullptr};
   uint32_t* csum = nullptr;   // radix chunk sums / prefixes
   DirSlot* dir = nullptr;
+  uint32_t* doff = nullptr;  // dense directories (rewritten every step)
   uint8_t* need = nullptr;
   uint32_t* inv = nullptr;
   uint32_t* hpart = nullptr;  // k_hist partial counts (one row per tile)
@@ -180,6 +183,7 @@ uint64_t carve(uint8_t* base, const Sizes& z, int nparity, bool stat, Scratch* o
   take(s.arcs[0], z.arcs), take(s.arcs[1], z.arcs);
   take(s.csum, ((z.tiles + kChunk - 1) / kChunk + z.segs) * kRowWords);
   if (!stat) take(s.dir, z.dir);
+  take(s.doff, z.doff);
   take(s.need, z.need), take(s.inv, z.arcs);
   take(s.hpart, z.tiles * kRowWords), take(s.mpart, z.tiles);
   for (int p = 0; p < nparity; ++p) {
@@ -501,6 +505,7 @@ struct Engine {
       d.gest_off = z.nest;
       d.arc_off = z.arcs;
       d.dir_off = z.dir;
+      d.doff_off = z.doff;
       d.qt_off = z.qt;
       d.w = w[k];
       d.r = r[b];
@@ -520,6 +525,7 @@ struct Engine {
       z.arcs += 2ull * w[k];
       z.tiles += d.ntiles;
       z.dir += 1ull << d.dir_log2;
+      z.doff += (1ull << d.dir_log2) + kDoffPad;
       z.qt += 1ull << d.qt_log2;
       z.nest += r[b];
       pl.segs.push_back(d);
@@ -551,6 +557,7 @@ struct Engine {
     a.csum = X.csum;
     a.nchunk = (uint32_t)pl.chunks;
     a.dir = X.dir;
+    a.doff = X.doff;
     a.qt = P.qt;
     a.qfp = P.qfp;
     a.qbits = pl.big_qt ? P.qbits : nullptr;

@@ -69,7 +69,8 @@ struct SegDesc {
   uint64_t est_off;       // bank's first estimator in the state arrays
   uint64_t gest_off;      // first flat estimator thread of this segment
   uint64_t arc_off;       // first arc slot in the arc buffers (2 * sum w)
-  uint64_t dir_off;       // first directory slot
+  uint64_t dir_off;       // first directory slot (hashed directory)
+  uint64_t doff_off;      // first word of the dense offsets (dense directory)
   uint64_t qt_off;        // first query-table slot
   uint32_t w;             // edges in the chunk
   uint32_t r;             // estimators in the bank
@@ -94,8 +95,13 @@ struct SegWork {
   uint32_t pad;
 };
 
-// vertex directory entry: segment [start, end) of vertex `key` in the
-// sorted arcs, live iff tag == step tag
+// Vertex directory.  Dense (the segment's largest id below 2^dir_log2):
+// CSR offsets, word x = the first sorted arc of a vertex >= x, for every x
+// up to max id + 1, all rewritten every step, so vertex x's arcs are
+// [off[x], off[x + 1]).  Hashed (any 32-bit ids): DirSlot, segment
+// [start, end) of vertex `key` in the sorted arcs, live iff tag == step tag.
+// Words of a dense region: its slot count plus room for the end word.
+constexpr uint32_t kDoffPad = 64;
 struct DirSlot {
   uint32_t key;
   uint32_t tag;
@@ -139,6 +145,7 @@ struct StepArgs {
   uint32_t* csum;         // per radix chunk: kRowWords digit sums
   uint32_t nchunk;        // total radix chunks over segments
   DirSlot* dir;
+  uint32_t* doff;         // dense directories (CSR offsets)
   uint32_t* qt;           // query table: owner per slot
   uint8_t* qfp;           // query table: key fingerprint per slot
   uint32_t* qbits;        // query table: bit s of word s / 32 set iff slot s

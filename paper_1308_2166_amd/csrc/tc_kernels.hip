@@ -878,15 +878,15 @@ __device__ __forceinline__ uint32_t dir_claim(DirSlot* dir, uint32_t mask,
   return kNone;
 }
 
-// [start, end) of x's arcs, or an empty range.  Dense directory: one
-// 16-byte load whose four fields all feed selects, so the load is neither
-// split nor put behind a branch, and two lookups in a row are both in
-// flight before either is used.
-__device__ __forceinline__ uint2 dir_find_dense(const DirSlot* dir, uint32_t mask,
-                                                uint32_t x, uint32_t tag) {
-  const uint4 e = *reinterpret_cast<const uint4*>(&dir[min(x, mask)]);
-  const bool ok = (x <= mask) & (e.y == tag) & (e.x == x);
-  return make_uint2(ok ? e.z : 0u, ok ? e.w : 0u);
+// [start, end) of x's arcs, or an empty range.  Dense directory: two
+// words of the CSR offsets (one line unless x + 1 starts the next), both
+// loads issued before either is used; ids above the largest are absent.
+__device__ __forceinline__ uint2 dir_find_dense(const uint32_t* off, uint32_t maxid,
+                                                uint32_t x) {
+  const uint32_t xc = min(x, maxid);
+  const uint32_t s = off[xc], e = off[xc + 1];
+  const bool ok = x <= maxid;
+  return make_uint2(ok ? s : 0u, ok ? e : 0u);
 }
 
 // hashed directory: linear probing from x's hash to its key or a slot that
@@ -904,7 +904,11 @@ __device__ __forceinline__ uint2 dir_find_hashed(const DirSlot* dir, uint32_t ma
 }
 
 // The block's tile of sorted arcs (plus one arc on each side) is loaded up
-// front into LDS; each arc then finds its neighbours there.
+// front into LDS; each arc then finds its neighbours there.  Dense
+// directory: the tile writes the CSR offsets of the vertex ids from one past
+// the arc before the tile to its last arc's (to max id + 1 for the last
+// tile), each by a binary search of the tile, so every id up to max id + 1
+// is written by exactly one tile and the writes are consecutive words.
 __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
   __shared__ uint64_t s_arc[kTile + 2];  // s_arc[1 + t] = arc base + t
   __shared__ uint32_t s_seg;
@@ -932,11 +936,31 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
     for (int k = 0; k < kItems; ++k) s_arc[1 + k * kBlock + tid] = v[k];
   }
   __syncthreads();
-  DirSlot* dir = a.dir + S.dir_off;
   const bool dense = wk->dense != 0;
+  uint32_t* inv = a.inv + S.arc_off;
+  if (dense) {
+    for (uint32_t t = tid; t < nv; t += kBlock) {
+      const uint32_t id = (uint32_t)s_arc[1 + t];
+      if (id & kNeedFlag) inv[id & kIdMask] = base + t;
+    }
+    uint32_t* off = a.doff + S.doff_off;
+    const uint32_t lo = base == 0 ? 0u : (uint32_t)(s_arc[0] >> 32) + 1u;
+    const uint32_t hi = base + nv == n ? uniform(wk->maxid) + 1u
+                                       : (uint32_t)(s_arc[nv] >> 32);
+    for (uint64_t y = (uint64_t)lo + tid; y <= hi; y += kBlock) {
+      // the tile's first arc of a vertex >= y (nv when there is none)
+      uint32_t l = 0, h = nv;
+      while (l < h) {
+        const uint32_t mid = (l + h) >> 1;
+        if ((uint64_t)(s_arc[1 + mid] >> 32) < y) l = mid + 1; else h = mid;
+      }
+      off[y] = base + l;
+    }
+    return;
+  }
+  DirSlot* dir = a.dir + S.dir_off;
   const uint32_t mask = (1u << S.dir_log2) - 1u;
   const uint32_t tag = uniform(*a.tagp);
-  uint32_t* inv = a.inv + S.arc_off;
   for (uint32_t t = tid; t < nv; t += kBlock) {
     const uint32_t i = base + t;
     const uint64_t e = s_arc[1 + t];
@@ -946,19 +970,6 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
     const bool head = i == 0 || (uint32_t)(s_arc[t] >> 32) != x;
     const bool tail = i + 1 == n || (uint32_t)(s_arc[t + 2] >> 32) != x;
     if (!head && !tail) continue;
-    if (dense) {
-      if (x > mask) continue;  // cannot happen: x <= max id < 2^dir_log2
-      // the head writes key, tag and start (and end too for a one-arc
-      // segment) in one store; a separate tail writes end
-      if (head && tail) {
-        *reinterpret_cast<uint4*>(&dir[x]) = make_uint4(x, tag, i, i + 1);
-      } else if (head) {
-        *reinterpret_cast<uint3*>(&dir[x]) = make_uint3(x, tag, i);
-      } else {
-        dir[x].end = i + 1;
-      }
-      continue;
-    }
     const uint32_t slot = dir_claim(dir, mask, x, tag, a.err);
     if (slot == kNone) continue;
     if (head) dir[slot].start = i;
@@ -998,6 +1009,7 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   const uint32_t jw = a.j1[e];
   const uint32_t fbuf = wk->final_buf;
   const bool dense = wk->dense != 0;
+  const uint32_t maxid = wk->maxid;
   const uint32_t tag = *a.tagp;
   uint64_t c = ccw & kChiMax;
   bool closed = (ccw & kClosed) != 0;
@@ -1018,13 +1030,14 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   const uint32_t u = (uint32_t)(r1 >> 32), v = (uint32_t)r1;
   const uint2 iv2 = *reinterpret_cast<const uint2*>(
       a.inv + S.arc_off + 2ull * (j1 == kNone ? 0u : j1));
-  const DirSlot* dir = a.dir + S.dir_off;
-  const uint32_t dmask = (1u << S.dir_log2) - 1u;
   uint2 su, sv;
   if (dense) {
-    su = dir_find_dense(dir, dmask, u, tag);
-    sv = dir_find_dense(dir, dmask, v, tag);
+    const uint32_t* off = a.doff + S.doff_off;
+    su = dir_find_dense(off, maxid, u);
+    sv = dir_find_dense(off, maxid, v);
   } else {
+    const DirSlot* dir = a.dir + S.dir_off;
+    const uint32_t dmask = (1u << S.dir_log2) - 1u;
     su = dir_find_hashed(dir, dmask, u, tag);
     sv = dir_find_hashed(dir, dmask, v, tag);
   }
