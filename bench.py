@@ -305,59 +305,53 @@ def batched_profile(tc, inputs, K, reps, nstreams=256):
 
 
 def host_fed(tc, G, r, seed, w, nv, reps=2):
-    """The same stream fed from pinned host memory: each batch is copied to
-    one of two device buffers on a copy stream while the previous batch is
-    processed.  Returns the PCIe-inclusive rate (never the headline value)
-    and the copy rate alone."""
+    """The same stream fed from pinned host memory through the library
+    (tc_process_host_stream: each batch is copied to one of two device
+    staging buffers on the library's copy stream while the previous batch
+    is processed).  Returns the PCIe-inclusive rate (never the headline
+    value), the copy rate alone, and whether the state equals the resident
+    stream's."""
+    import numpy as np
     import torch
     m = G.shape[0]
     nb = (m + w - 1) // w
     host = torch.empty(G.shape, dtype=G.dtype, pin_memory=True)
     host.copy_(G)
-    bufs = [torch.empty((w, 2), dtype=G.dtype, device="cuda") for _ in range(2)]
-    main = torch.cuda.current_stream()
-    cp = torch.cuda.Stream()
-    ready = [torch.cuda.Event() for _ in range(2)]
-    free = [torch.cuda.Event() for _ in range(2)]
-    best = None
+    stream = torch.cuda.current_stream()
+    best, state_fed = None, None
     for _ in range(reps):
         b = tc.Bank(r, seed)
         tc.tc_set_vertex_bound(b.h, nv)
         tc.tc_reserve(b.h, w)
+        b.process_host_stream(host[:min(m, w)], w, stream)  # sizes the staging buffers
+        tc.tc_reset(b.h, stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(nb):
-            j = k % 2
-            wk = min(w, m - k * w)
-            with torch.cuda.stream(cp):
-                if k >= 2:
-                    cp.wait_event(free[j])
-                bufs[j][:wk].copy_(host[k * w:k * w + wk], non_blocking=True)
-                ready[j].record(cp)
-            main.wait_event(ready[j])
-            b.process(bufs[j][:wk], main)
-            free[j].record(main)
+        b.process_host_stream(host, w, stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        s_fed = tc.tc_estimate_ex(b.h)[0]
+        state_fed = b.state()
         b.close()
         best = dt if best is None else min(best, dt)
     ref = tc.Bank(r, seed)
     ref.process_stream(G, w)
-    same = tc.tc_estimate_ex(ref.h)[0] == s_fed
+    same = all(np.array_equal(x, y) for x, y in zip(ref.state(), state_fed))
     ref.close()
+    buf = torch.empty((w, 2), dtype=G.dtype, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(nb):
         wk = min(w, m - k * w)
-        bufs[k % 2][:wk].copy_(host[k * w:k * w + wk], non_blocking=True)
+        buf[:wk].copy_(host[k * w:k * w + wk], non_blocking=True)
     torch.cuda.synchronize()
     t_copy = time.perf_counter() - t0
     return {"ms_per_step": best * 1e3 / nb, "value": r * m / best,
             "edges_per_s": m / best, "unit": "estimator-edge updates/s",
-            "h2d_GBs": 8.0 * m / t_copy / 1e9, "same_S_as_resident": bool(same),
-            "note": "batches copied from pinned host memory (double-buffered, "
-                    "overlapped with the steps); PCIe-inclusive, not the headline"}
+            "h2d_GBs": 8.0 * m / t_copy / 1e9, "same_state_as_resident": bool(same),
+            "entry_point": "tc_process_host_stream",
+            "note": "the whole stream from pinned host memory, copied by the library "
+                    "(double-buffered, overlapped with the steps); PCIe-inclusive, "
+                    "not the headline"}
 
 
 def naive_vs_bulk(tc, inputs, shapes=((4096, 2048), (4096, 16384), (65536, 16384),
@@ -604,13 +598,18 @@ def random_gather_ceiling(table_bytes, n_idx=1 << 26, reps=5):
 
 
 def served_comparison(tc, inputs, nstreams=1024, ngraphs=64, r=1 << 16,
-                      loads=(0.5, 0.9), tight_slots=256):
+                      loads=(0.5, 0.9), budget=200 << 30, tight_budget=3 << 30,
+                      max_step_edges=1 << 26, tight_step_edges=1 << 23, plain_group=32):
     """Continuous batching of Poisson-arriving chunks (1K-1M pairs) from
     `nstreams` streams (each replays one of `ngraphs` resident graphs with
-    its own estimator seed); banks of r estimators.  Capacity is measured
-    with every chunk available at time 0; then arrivals are paced at each
-    load fraction of it, and once with a budget of only `tight_slots`
-    resident banks.  Reports ingest latency p50/p99 and throughput."""
+    its own estimator seed); banks of r estimators; steps of at most
+    max_step_edges edges.  Slots are what the device-byte budget allows
+    (banks plus the reserved scratch of the largest step, as the library
+    accounts them).  Capacity is measured with every chunk available at
+    time 0; then arrivals are paced at each load fraction of it, and once
+    under a budget small enough to bind.  Reports ingest latency p50/p99,
+    throughput, the device bytes held, and the plain form (one bank per
+    stream, one call per chunk, same chunks) for comparison."""
     import numpy as np
     import torch
     from paper_1308_2166_amd import serve
@@ -623,49 +622,78 @@ def served_comparison(tc, inputs, nstreams=1024, ngraphs=64, r=1 << 16,
     nchunks = sum(len(c) for c in chunks)
     total_w = sum(int(c.shape[0]) for cs in chunks for c in cs)
     mean_chunk = total_w / nchunks
-    budget = 200 << 30
-    slots = min(nstreams, serve.slots_for_budget(budget, r, reserve_bytes=64 << 30))
     servers = {}
 
-    def run(rate, nslots, seed):
-        srv = servers.get(nslots) or servers.setdefault(
-            nslots, serve.Server(slots=nslots, r=r, vertex_bound=nv))
+    def server(bud, cap_w):
+        if bud not in servers:
+            servers[bud] = serve.Server(r=r, max_step_edges=cap_w, budget_bytes=bud,
+                                        vertex_bound=nv, max_slots=nstreams)
+        return servers[bud]
+
+    def run(rate, bud, seed, cap_w=max_step_edges):
+        srv = server(bud, cap_w)
         lat, res, el, rw = srv.run(serve.poisson_arrivals(chunks, rate, seed), seeds)
         lat = np.array(lat) * 1e3
         return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "value": rw / el, "elapsed_s": el}, res
+                "value": rw / el, "elapsed_s": el, "slots": srv.slots,
+                "device_bytes": srv.device_bytes()}, res
 
     log("[bench]   capacity run")
-    run(0.0, slots, 1)
-    cap, res_cap = run(0.0, slots, 1)
+    run(0.0, budget, 1)
+    cap, res_cap = run(0.0, budget, 1)
     capacity = cap["value"]
     out = {"workload": f"{nstreams} streams replaying {ngraphs} R-MAT/Chung-Lu graphs, "
-                       f"chunks log-uniform in [1e3, 1e6] pairs, Poisson arrivals, r={r}",
-           "chunks": nchunks, "edges": total_w, "budget_bytes": budget, "slots": slots,
+                       f"chunks log-uniform in [1e3, 1e6] pairs, Poisson arrivals, r={r}, "
+                       f"steps of at most {max_step_edges} edges",
+           "chunks": nchunks, "edges": total_w, "budget_bytes": budget,
+           "slots": cap["slots"], "device_bytes": cap["device_bytes"],
            "capacity": capacity, "unit": "estimator-edge updates/s", "loads": []}
     for f in loads:
         rate = f * capacity / (r * mean_chunk)
         log(f"[bench]   load {f:.0%}")
-        d, res = run(rate, slots, 2)
+        d, res = run(rate, budget, 2)
         d["load"] = f
         out["loads"].append(d)
-    log(f"[bench]   tight budget: {tight_slots} slots")
-    run(0.0, tight_slots, 1)  # warm-up of this server's scratch
-    d, res_t = run(0.5 * capacity / (r * mean_chunk), tight_slots, 3)
-    d["load"], d["slots"] = 0.5, tight_slots
+    log(f"[bench]   tight budget: {tight_budget} bytes")
+    run(0.0, tight_budget, 1, tight_step_edges)  # warm-up of this server
+    d, res_t = run(0.5 * capacity / (r * mean_chunk), tight_budget, 3, tight_step_edges)
+    d["load"], d["budget_bytes"], d["max_step_edges"] = 0.5, tight_budget, tight_step_edges
     out["tight_budget"] = d
     same = all((res_cap[s].S, res_cap[s].m) == (res_t[s].S, res_t[s].m) for s in range(nstreams))
-    # a sample of streams alone, through the plain entry point
-    for s in range(0, nstreams, max(1, nstreams // 16)):
-        b = tc.Bank(r, seeds[s])
-        for c in chunks[s]:
-            b.process(c)
-        S, m, _ = tc.tc_estimate_ex(b.h)
-        b.close()
-        same = same and (S, m) == (res_cap[s].S, res_cap[s].m)
-    out["identical_results"] = bool(same)
     for srv in servers.values():
         srv.close()
+    servers.clear()
+    torch.cuda.synchronize()
+    # the plain form on the same chunks: one bank per stream, one
+    # tc_process_batch per chunk, streams in groups whose banks are made
+    # (and their scratch sized) outside the timed region
+    log("[bench]   plain form on the same chunks")
+    t_plain, rw_plain = 0.0, 0
+    stream = torch.cuda.current_stream()
+    for g0 in range(0, nstreams, plain_group):
+        ids = list(range(g0, min(nstreams, g0 + plain_group)))
+        banks = {}
+        for s in ids:
+            b = tc.Bank(r, seeds[s])
+            tc.tc_set_vertex_bound(b.h, nv)
+            tc.tc_reserve(b.h, max(int(c.shape[0]) for c in chunks[s]))
+            banks[s] = b
+        order = [(s, k) for k in range(max(len(chunks[s]) for s in ids))
+                 for s in ids if k < len(chunks[s])]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s, k in order:
+            banks[s].process(chunks[s][k], stream)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        for s in ids:
+            rw_plain += r * sum(int(c.shape[0]) for c in chunks[s])
+            S, m, _ = tc.tc_estimate_ex(banks[s].h)
+            same = same and (S, m) == (res_cap[s].S, res_cap[s].m)
+            banks[s].close()
+    out["plain_value"] = rw_plain / t_plain
+    out["served_vs_plain"] = capacity / out["plain_value"]
+    out["identical_results"] = bool(same)
     return out
 
 

@@ -115,6 +115,25 @@ int tc_process_batch_naive(tc_state *s, const uint32_t *edges, uint32_t w,
 int tc_process_stream(tc_state *s, const uint32_t *edges, uint64_t m,
                       uint32_t w, void *stream);
 
+/* Enqueue a whole stream held in HOST memory (the paper's input path: its
+ * I/O routine reads the edge list from storage while the update runs; Sec.
+ * 5, Table 2's I/O column): host_edges is uint32_t[2*m], cut into
+ * ceil(m/w) batches of w edges exactly as tc_process_stream cuts a resident
+ * stream, with a bit-identical result.  Batch k is copied into one of two
+ * library-owned device staging buffers (2 * 8w bytes, kept and reused by
+ * later calls, freed by tc_destroy) on an internal copy stream while batch
+ * k - 1 is processed on `stream`; each batch's step waits for its copy.
+ * Page-locked host memory (hipHostMalloc, or a pinned torch tensor) gives
+ * asynchronous full-rate copies; pageable memory works too, but its copies
+ * may block the calling thread.  The host array must stay valid and
+ * unchanged until `stream` has passed this call's work.  Not capturable
+ * (TC_EINVAL while `stream` is being captured).  TC_EINVAL for a NULL
+ * state, NULL host_edges with m > 0, w == 0 or w > TC_MAX_BATCH; TC_ENOMEM
+ * if the staging buffers cannot be allocated; on any error the batches
+ * before the failing one stay enqueued. */
+int tc_process_host_stream(tc_state *s, const uint32_t *host_edges,
+                           uint64_t m, uint32_t w, void *stream);
+
 /* Declare that every vertex id of this bank's stream is below n
  * (2 <= n <= 2^32; the default is 2^32).  The grouping sort then runs only
  * as many radix passes as n - 1 needs: its bytes in 8-bit digits, or two
@@ -168,6 +187,33 @@ int tc_estimate_mom(tc_state *s, uint32_t groups, double *tau,
  * function. */
 uint64_t tc_estimators_needed(double eps, double delta, uint64_t m,
                               uint64_t maxdeg, double tau);
+
+/* ---- device memory accounting (admission by memory budget) -------------
+ * tc_bank_bytes: device bytes one bank of r estimators holds for its life
+ * (36 per estimator: f1, f2, the packed chi/closed word and three per-step
+ * words, plus 16 per bank).  tc_step_bytes: the step scratch a step made of
+ * these nchunks chunks (chunk k: a bank of r[k] estimators, w[k] edges)
+ * needs; an object's scratch grows to the largest step it has run and is
+ * then reused.  0 for invalid arguments (w[k] > TC_MAX_BATCH or r[k] == 0).
+ * Pure host functions.  tc_device_bytes / tc_multi_device_bytes: the bytes
+ * the object holds on the device now (banks, step scratch, blocks kept for
+ * captured graphs, host-ingest staging), as requested from hipMalloc
+ * (the allocator may round each allocation up). */
+uint64_t tc_bank_bytes(uint32_t r);
+uint64_t tc_step_bytes(uint32_t nchunks, const uint32_t *r, const uint32_t *w);
+
+/* tc_step_bytes_max: bytes of a step scratch that holds EVERY step of at
+ * most nchunks chunks of banks of at most r_max estimators with at most
+ * total_w edges in all (0 if an argument is 0).  tc_multi_reserve_max
+ * grows the object's scratch to that size (r_max = its largest bank), so
+ * that such steps never allocate afterwards: a server that caps its steps
+ * at nchunks chunks and total_w edges holds at most
+ * sum_b tc_bank_bytes(r_b) + 16 + tc_step_bytes_max(...) bytes of device
+ * memory.  Blocking; TC_EINVAL if nchunks exceeds the banks; TC_ENOMEM. */
+uint64_t tc_step_bytes_max(uint32_t nchunks, uint32_t r_max, uint64_t total_w);
+int tc_multi_reserve_max(tc_multi *s, uint32_t nchunks, uint64_t total_w);
+int tc_device_bytes(const tc_state *s, uint64_t *bytes);
+int tc_multi_device_bytes(const tc_multi *s, uint64_t *bytes);
 
 /* Blocking; copies the bank into caller-owned HOST arrays of length r:
  * f1, f2 (canonical codes), chi and closed (0/1).  Any pointer may be NULL. */

@@ -59,6 +59,13 @@ def lib():
         "tc_create": ([u32, u64], vp),
         "tc_process_batch": ([vp, vp, u32, vp], i32),
         "tc_process_stream": ([vp, vp, u64, u32, vp], i32),
+        "tc_process_host_stream": ([vp, vp, u64, u32, vp], i32),
+        "tc_bank_bytes": ([u32], u64),
+        "tc_step_bytes_max": ([u32, u32, u64], u64),
+        "tc_multi_reserve_max": ([vp, u32, u64], i32),
+        "tc_step_bytes": ([u32, vp, vp], u64),
+        "tc_device_bytes": ([vp, P64], i32),
+        "tc_multi_device_bytes": ([vp, P64], i32),
         "tc_process_batch_naive": ([vp, vp, u32, vp], i32),
         "tc_process_batch_noalloc": ([vp, vp, u32, vp], i32),
         "tc_parse_edges": ([vp, u64, vp, u64, P64, vp], i32),
@@ -115,7 +122,9 @@ EXPORTS = ("tc_create", "tc_process_batch", "tc_process_stream", "tc_estimate", 
            "tc_multi_graph_reserve", "tc_multi_assign", "tc_set_vertex_bound",
            "tc_multi_set_vertex_bound", "tc_estimate_mom", "tc_multi_estimate_mom",
            "tc_estimators_needed", "tc_process_batch_naive", "tc_parse_edges",
-           "tc_process_batch_noalloc")
+           "tc_process_batch_noalloc", "tc_process_host_stream", "tc_bank_bytes",
+           "tc_step_bytes", "tc_device_bytes", "tc_multi_device_bytes",
+           "tc_step_bytes_max", "tc_multi_reserve_max")
 
 
 def _check(rc: int):
@@ -199,6 +208,60 @@ def tc_process_stream(state: int, edges, w: int, stream=None) -> None:
     else:
         ptr, m = _edge_ptr(edges)
     _check(lib().tc_process_stream(state, ptr or None, m, w, _stream_handle(stream)))
+
+
+def tc_process_host_stream(state: int, host_edges, w: int, stream=None) -> None:
+    """All of `host_edges` (an (m, 2) int32/uint32 CPU tensor, ideally
+    pinned, or a numpy array) as consecutive batches of w, copied to the
+    device by the library.  The array must stay alive until `stream` has
+    passed this work."""
+    if isinstance(host_edges, torch.Tensor):
+        if host_edges.is_cuda:
+            raise TypeError("host_edges must be in host memory (use tc_process_stream)")
+        if host_edges.dtype not in (torch.int32, torch.uint32) or host_edges.dim() != 2 \
+                or host_edges.shape[1] != 2 or not host_edges.is_contiguous():
+            raise TypeError("host_edges must be a contiguous (m, 2) int32/uint32 tensor")
+        ptr, m = host_edges.data_ptr(), host_edges.shape[0]
+    else:
+        a = np.asarray(host_edges)
+        if a.dtype not in (np.int32, np.uint32) or a.ndim != 2 or a.shape[1] != 2 \
+                or not a.flags.c_contiguous:
+            raise TypeError("host_edges must be a C-contiguous (m, 2) int32/uint32 array")
+        ptr, m = a.ctypes.data, a.shape[0]
+    _check(lib().tc_process_host_stream(state, (ptr if m else None), m, w,
+                                        _stream_handle(stream)))
+
+
+def tc_bank_bytes(r: int) -> int:
+    return lib().tc_bank_bytes(r)
+
+
+def tc_step_bytes(rs, ws) -> int:
+    r = np.ascontiguousarray(rs, dtype=np.uint32)
+    w = np.ascontiguousarray(ws, dtype=np.uint32)
+    if r.shape != w.shape:
+        raise ValueError("one r and one w per chunk")
+    return lib().tc_step_bytes(len(r), r.ctypes.data, w.ctypes.data)
+
+
+def tc_step_bytes_max(nchunks: int, r_max: int, total_w: int) -> int:
+    return lib().tc_step_bytes_max(nchunks, r_max, total_w)
+
+
+def tc_multi_reserve_max(multi: int, nchunks: int, total_w: int) -> None:
+    _check(lib().tc_multi_reserve_max(multi, nchunks, total_w))
+
+
+def tc_device_bytes(state: int) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().tc_device_bytes(state, ctypes.byref(b)))
+    return b.value
+
+
+def tc_multi_device_bytes(multi: int) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().tc_multi_device_bytes(multi, ctypes.byref(b)))
+    return b.value
 
 
 def tc_estimate_mom(state: int, groups: int):
@@ -412,6 +475,9 @@ class Bank:
 
     def process_stream(self, edges, w: int, stream=None):
         tc_process_stream(self.h, edges, w, stream=stream)
+
+    def process_host_stream(self, host_edges, w: int, stream=None):
+        tc_process_host_stream(self.h, host_edges, w, stream=stream)
 
     def estimate(self) -> float:
         return tc_estimate_ex(self.h)[2]

@@ -72,6 +72,11 @@ uint32_t qt_log2_for(uint32_t r) {
   return std::max<uint32_t>(10, log2_ceil(4ull * r));
 }
 
+// Scratch a step needs for one more chunk of w > 0 edges of a bank of r
+// estimators (the per-segment regions plan() hands out, in the same order).
+struct Sizes;
+void add_chunk(Sizes& z, uint32_t r, uint32_t w);
+
 template <class T>
 hipError_t dalloc(T** p, uint64_t n) {
   *p = nullptr;
@@ -132,6 +137,40 @@ struct Sizes {
     nest = std::max(nest, z.nest), segs = std::max(segs, z.segs);
   }
 };
+
+void add_chunk(Sizes& z, uint32_t r, uint32_t w) {
+  const uint32_t dl = dir_log2_for(w);
+  z.need += (w + 15) / 16 * 16;
+  z.arcs += 2ull * w;
+  z.tiles += (2ull * w + kTile - 1) / kTile;
+  z.dir += 1ull << dl;
+  z.doff += (1ull << dl) + kDoffPad;
+  z.qt += 1ull << qt_log2_for(r);
+  z.nest += r;
+  z.segs += 1;
+}
+
+// Sizes that hold every step of at most n chunks (banks of at most r_max
+// estimators) with at most E edges in all: per field, the largest total
+// add_chunk can reach (2^ceil(log2 x) < 2x bounds the rounded regions).
+Sizes step_bound(uint32_t n, uint32_t r_max, uint64_t E) {
+  Sizes z;
+  if (n == 0 || E == 0) return z;
+  z.arcs = 2 * E;
+  z.tiles = 2 * E / kTile + n;
+  z.dir = 8 * E + 1024ull * n;
+  z.doff = z.dir + (uint64_t)kDoffPad * n;
+  z.qt = (uint64_t)n << qt_log2_for(r_max);
+  z.need = E + 16ull * n;
+  z.nest = (uint64_t)n * r_max;
+  z.segs = n;
+  return z;
+}
+
+// Device bytes a bank of r estimators holds for its life: f1, f2 and the
+// packed chi/closed word (20 B), and the per-estimator step words j1, qq
+// and qthr (16 B).
+constexpr uint64_t kBankBytesPerEst = 8 + 8 + 4 + 4 + 8 + 4;
 
 // The per-step scratch buffers, carved from one block of device memory.
 struct Scratch {
@@ -256,7 +295,18 @@ struct Engine {
   Scratch S;
   bool captured = false;
   std::vector<uint8_t*> retired;
+  uint64_t retired_bytes = 0;
   StaticScratch* stat = nullptr;  // the device's static scratch
+
+  // host ingest (tc_process_host_stream): two device staging buffers of
+  // hbuf_w edges, filled on the copy stream stc while the previous batch is
+  // processed; h_ready[b] marks buffer b copied, h_free[b] its last reader
+  // done (h_used[b]: h_free[b] has been recorded)
+  hipStream_t stc = nullptr;
+  uint32_t* hbuf[2] = {nullptr, nullptr};
+  uint64_t hbuf_w = 0;
+  hipEvent_t h_ready[2] = {nullptr, nullptr}, h_free[2] = {nullptr, nullptr};
+  bool h_used[2] = {false, false};
 
   // the Step-3 phase runs on st2; evB orders it after k_est, evC orders
   // the next k_est (and any state access) after it
@@ -322,6 +372,17 @@ struct Engine {
     ev_free.clear();
     dfree(R1), dfree(R2), dfree(CC), dfree(J1), dfree(QQ), dfree(QT), dfree(bank_off);
     dfree(sums), dfree(err), dfree(tagp), dfree(gsums);
+    if (stc) (void)hipStreamSynchronize(stc);
+    for (int b = 0; b < 2; ++b) {
+      dfree(hbuf[b]);
+      if (h_ready[b]) (void)hipEventDestroy(h_ready[b]);
+      if (h_free[b]) (void)hipEventDestroy(h_free[b]);
+      h_ready[b] = h_free[b] = nullptr;
+      h_used[b] = false;
+    }
+    hbuf_w = 0;
+    if (stc) (void)hipStreamDestroy(stc);
+    stc = nullptr;
     if (h_gsums) (void)hipHostFree(h_gsums);
     h_gsums = nullptr;
     cap_groups = 0;
@@ -355,6 +416,7 @@ struct Engine {
   void free_retired() {
     for (uint8_t* b : retired) (void)hipFree(b);
     retired.clear();
+    retired_bytes = 0;
   }
 
   int init(uint32_t n, const uint32_t* rr, const uint64_t* seeds) {
@@ -412,6 +474,7 @@ struct Engine {
     want.grow(z);
     if (captured && block) {
       retired.push_back(block);
+      retired_bytes += carve(nullptr, cap, 2, false, nullptr);
       block = nullptr;
     }
     free_scratch();
@@ -521,13 +584,7 @@ struct Engine {
       d.qt_log2 = qt_log2_for(r[b]);
       pl.big_qt = pl.big_qt || d.qt_log2 > kBitmapMinLog2;
       d.need_off = (uint32_t)z.need;
-      z.need += (w[k] + 15) / 16 * 16;
-      z.arcs += 2ull * w[k];
-      z.tiles += d.ntiles;
-      z.dir += 1ull << d.dir_log2;
-      z.doff += (1ull << d.dir_log2) + kDoffPad;
-      z.qt += 1ull << d.qt_log2;
-      z.nest += r[b];
+      add_chunk(z, r[b], w[k]);
       pl.segs.push_back(d);
       pl.bank.push_back(b);
     }
@@ -703,6 +760,79 @@ struct Engine {
     rc = launch(pl, a, st, nullptr, false);
     if (rc) stat->dirty = true;
     return rc;
+  }
+
+  // device bytes this object holds now (as requested from hipMalloc)
+  uint64_t device_bytes() const {
+    uint64_t b = kBankBytesPerEst * total + 8ull * (nbanks + 1) + 8ull * nbanks + 8 +
+                 8ull * cap_groups;
+    if (block) b += carve(nullptr, cap, 2, false, nullptr);
+    return b + retired_bytes + 16ull * hbuf_w;
+  }
+
+  // A stream in host memory: batch k is copied into staging buffer k & 1 on
+  // the copy stream (after that buffer's previous batch is done with it)
+  // while batch k - 1 is processed on st; each step waits for its copy.
+  int host_stream(const uint32_t* host, uint64_t mm, uint32_t w, hipStream_t st) {
+    if (sticky != TC_OK) return fail(sticky, "an earlier batch failed on the device");
+    if (nbanks != 1) return fail(TC_EINVAL, "host ingest serves one bank");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess)
+      return fail(TC_EHIP, "hipStreamIsCapturing failed");
+    if (cs == hipStreamCaptureStatusActive)
+      return fail(TC_EINVAL, "host ingest cannot be captured (it copies from host memory)");
+    const uint64_t need_w = std::min<uint64_t>(w, mm);
+    if (!stc && hipStreamCreateWithFlags(&stc, hipStreamNonBlocking) != hipSuccess)
+      return fail(TC_EHIP, "copy stream creation failed");
+    for (int b = 0; b < 2; ++b)
+      if ((!h_ready[b] && hipEventCreateWithFlags(&h_ready[b], hipEventDisableTiming)) ||
+          (!h_free[b] && hipEventCreateWithFlags(&h_free[b], hipEventDisableTiming)))
+        return fail(TC_EHIP, "hipEventCreate failed");
+    if (need_w > hbuf_w) {
+      // the old buffers may still be read by enqueued steps
+      wait_all();
+      if (st) (void)hipStreamSynchronize(st);
+      (void)hipStreamSynchronize(stc);
+      for (int b = 0; b < 2; ++b) {
+        dfree(hbuf[b]);
+        h_used[b] = false;
+      }
+      hbuf_w = 0;
+      if (dalloc(&hbuf[0], 2 * need_w) || dalloc(&hbuf[1], 2 * need_w)) {
+        dfree(hbuf[0]), dfree(hbuf[1]);
+        return fail(TC_ENOMEM, "device staging buffers for host ingest");
+      }
+      hbuf_w = need_w;
+    }
+    const uint32_t id = 0;
+    uint64_t k = 0;
+    for (uint64_t j = 0; j < mm; j += w, ++k) {
+      const int b = (int)(k & 1);
+      const uint32_t wk = (uint32_t)std::min<uint64_t>(w, mm - j);
+      if ((h_used[b] && hipStreamWaitEvent(stc, h_free[b], 0) != hipSuccess) ||
+          hipMemcpyAsync(hbuf[b], host + 2 * j, 8ull * wk, hipMemcpyHostToDevice, stc) !=
+              hipSuccess ||
+          hipEventRecord(h_ready[b], stc) != hipSuccess ||
+          hipStreamWaitEvent(st, h_ready[b], 0) != hipSuccess) {
+        (void)join(st);
+        return fail(TC_EHIP, "host-to-device copy of a batch failed");
+      }
+      // Step 3 of a batch may overlap the next batch's grouping (as in
+      // tc_process_stream); its last reader of the buffer is then on st2
+      const bool more = j + w < mm && w <= (1u << 20);
+      const uint32_t* ek = hbuf[b];
+      int rc = step(1, &id, &ek, &wk, st, false, more);
+      if (rc) {
+        (void)join(st);
+        return rc;
+      }
+      if (hipEventRecord(h_free[b], c_pending ? st2 : st) != hipSuccess) {
+        (void)join(st);
+        return fail(TC_EHIP, "hipEventRecord failed");
+      }
+      h_used[b] = true;
+    }
+    return TC_OK;
   }
 
   // one batch for bank b by the per-estimator kernel (same state, same draws)
@@ -971,6 +1101,55 @@ int tc_process_stream(tc_state* s, const uint32_t* edges, uint64_t m,
       return rc;
     }
   }
+  return TC_OK;
+}
+
+int tc_process_host_stream(tc_state* s, const uint32_t* host_edges, uint64_t m,
+                           uint32_t w, void* stream) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  if (w == 0 || w > TC_MAX_BATCH) return fail(TC_EINVAL, "w must be in [1, TC_MAX_BATCH]");
+  if (m == 0) return TC_OK;
+  if (!host_edges) return fail(TC_EINVAL, "null edge pointer with m > 0");
+  return s->e.host_stream(host_edges, m, w, static_cast<hipStream_t>(stream));
+}
+
+uint64_t tc_step_bytes_max(uint32_t nchunks, uint32_t r_max, uint64_t total_w) {
+  if (nchunks == 0 || total_w == 0 || r_max == 0) return 0;
+  return carve(nullptr, step_bound(nchunks, r_max, total_w), 2, false, nullptr);
+}
+
+int tc_multi_reserve_max(tc_multi* s, uint32_t nchunks, uint64_t total_w) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  if (nchunks == 0 || total_w == 0) return TC_OK;
+  if (nchunks > s->e.nbanks) return fail(TC_EINVAL, "more chunks than banks");
+  const uint32_t r_max = *std::max_element(s->e.r.begin(), s->e.r.end());
+  return s->e.ensure_scratch(step_bound(nchunks, r_max, total_w), nullptr);
+}
+
+uint64_t tc_bank_bytes(uint32_t r) {
+  // one bank's share of the per-bank words (offset, sum) included
+  return kBankBytesPerEst * r + 16;
+}
+
+uint64_t tc_step_bytes(uint32_t nchunks, const uint32_t* r, const uint32_t* w) {
+  if (nchunks && (!r || !w)) return 0;
+  Sizes z;
+  for (uint32_t k = 0; k < nchunks; ++k) {
+    if (w[k] > TC_MAX_BATCH || r[k] == 0) return 0;
+    if (w[k]) add_chunk(z, r[k], w[k]);
+  }
+  return z.segs ? carve(nullptr, z, 2, false, nullptr) : 0;
+}
+
+int tc_device_bytes(const tc_state* s, uint64_t* bytes) {
+  if (!s || !bytes) return fail(TC_EINVAL, "null argument");
+  *bytes = s->e.device_bytes();
+  return TC_OK;
+}
+
+int tc_multi_device_bytes(const tc_multi* s, uint64_t* bytes) {
+  if (!s || !bytes) return fail(TC_EINVAL, "null argument");
+  *bytes = s->e.device_bytes();
   return TC_OK;
 }
 

@@ -4,12 +4,17 @@ A request is one chunk of one stream: a batch of that stream's edges,
 already resident in device memory.  The loop
 
 * admits a stream (gives it a bank slot of r estimators) when its first
-  chunk arrives and the memory budget has a free slot; later streams wait;
+  chunk arrives and a slot is free; the number of slots is what a device
+  memory budget allows: the banks' bytes plus the step scratch of the
+  largest step the loop launches (at most one chunk per slot and at most
+  `max_step_edges` edges), both as the library accounts them
+  (tc_bank_bytes, tc_step_bytes_max), and that scratch is reserved up
+  front, so serving never allocates; later streams wait;
 * keeps every admitted stream's estimator state resident in HBM;
 * whenever fewer than `depth` steps are in flight, launches one step that
-  takes the oldest waiting chunk of every admitted stream that has one
-  (never two chunks of a stream in one step: a chunk is a batch, and the
-  random key depends on the batch index);
+  takes the oldest waiting chunk of admitted streams, oldest first, up to
+  `max_step_edges` edges (never two chunks of a stream in one step: a
+  chunk is a batch, and the random key depends on the batch index);
 * records each step's completion with a GPU event, so a chunk's ingest
   latency is its step's completion time minus its arrival time;
 * frees a stream's slot once its last chunk is done and its estimate read.
@@ -26,8 +31,9 @@ import time
 
 import torch
 
-from . import (MultiBank, tc_multi_assign, tc_multi_estimate, tc_multi_reserve,
-               tc_multi_set_vertex_bound)
+from . import (MultiBank, tc_bank_bytes, tc_multi_assign, tc_multi_device_bytes,
+               tc_multi_estimate, tc_multi_reserve_max, tc_multi_set_vertex_bound,
+               tc_step_bytes_max)
 
 
 @dataclasses.dataclass
@@ -45,14 +51,24 @@ class Result:
     tau: float
 
 
-def bank_bytes(r: int) -> int:
-    """Device bytes of one resident bank (f1, f2, packed chi/closed)."""
-    return 20 * r
+def server_bytes(slots: int, r: int, max_step_edges: int) -> int:
+    """Device bytes of a server with `slots` banks of r estimators whose
+    steps hold at most `slots` chunks and `max_step_edges` edges."""
+    return slots * tc_bank_bytes(r) + 16 + tc_step_bytes_max(slots, r, max_step_edges)
 
 
-def slots_for_budget(budget_bytes: int, r: int, reserve_bytes: int) -> int:
-    """Bank slots that fit the budget after the step scratch reservation."""
-    return max(0, (budget_bytes - reserve_bytes) // bank_bytes(r))
+def slots_for_budget(budget_bytes: int, r: int, max_step_edges: int,
+                     most: int = 1 << 20) -> int:
+    """The largest number of bank slots (at most `most`) whose server fits
+    the budget (0 if not even one does)."""
+    lo, hi = 0, most
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if server_bytes(mid, r, max_step_edges) <= budget_bytes:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
 
 
 def poisson_arrivals(chunks_per_stream, rate_per_s: float, seed: int):
@@ -85,26 +101,36 @@ def poisson_arrivals(chunks_per_stream, rate_per_s: float, seed: int):
 class Server:
     """Admission, continuous batching and latency bookkeeping."""
 
-    def __init__(self, slots: int, r: int, depth: int = 2,
+    def __init__(self, r: int, max_step_edges: int, slots: int | None = None,
+                 budget_bytes: int | None = None, depth: int = 2,
                  stream: torch.cuda.Stream | None = None,
-                 vertex_bound: int | None = None):
-        """`slots` resident banks of r estimators.  Step scratch grows to
-        the largest step seen (the first run is a warm-up) and is reused;
-        every run reassigns the slots it uses, so a Server serves many runs.
-        vertex_bound: every vertex id of every stream is below it (fewer
-        radix passes; an id at or above it fails the run)."""
+                 vertex_bound: int | None = None, max_slots: int = 1 << 20):
+        """Banks of r estimators; every step holds at most max_step_edges
+        edges (no chunk may be larger).  The slot count is `slots`, or the
+        most that `budget_bytes` of device memory allows (at most
+        max_slots).  The step scratch is reserved here for the largest
+        step, so serving allocates nothing; every run reassigns the slots it
+        uses, so a Server serves many runs.  vertex_bound: every vertex id
+        of every stream is below it (fewer radix passes; an id at or above
+        it fails the run)."""
+        if slots is None:
+            if budget_bytes is None:
+                raise ValueError("give slots or budget_bytes")
+            slots = slots_for_budget(budget_bytes, r, max_step_edges, max_slots)
         if slots < 1:
             raise ValueError("the memory budget leaves no bank slot")
         self.slots, self.r, self.depth = slots, r, depth
+        self.max_step_edges = max_step_edges
+        self.budget_bytes = budget_bytes
         self.bank = MultiBank([r] * slots, [0] * slots)
         if vertex_bound is not None:
             tc_multi_set_vertex_bound(self.bank.h, vertex_bound)
+        tc_multi_reserve_max(self.bank.h, slots, max_step_edges)
         self.stream = stream or torch.cuda.current_stream()
 
-    def reserve(self, chunk_sizes) -> None:
-        """Pre-size the step scratch for one step with these chunk sizes."""
-        n = min(len(chunk_sizes), self.slots)
-        tc_multi_reserve(self.bank.h, list(range(n)), list(chunk_sizes)[:n])
+    def device_bytes(self) -> int:
+        """Device bytes the server's banks and scratch hold now."""
+        return tc_multi_device_bytes(self.bank.h)
 
     def run(self, arrivals, seeds, spin_s: float = 2e-5):
         """arrivals: list of Chunk sorted by time.  Returns (latencies in
@@ -150,13 +176,21 @@ class Server:
                 slot_of[sid] = b
             if len(inflight) < self.depth:
                 ids, chunks, items = [], [], []
-                for sid, b in slot_of.items():
-                    if ready[sid]:
-                        c = ready[sid].popleft()
-                        ids.append(b)
-                        chunks.append(c.edges)
-                        items.append(c)
-                        rw += self.r * c.edges.shape[0]
+                # oldest waiting chunks first, up to the step's edge cap
+                heads = sorted((ready[sid][0].t, sid) for sid in slot_of if ready[sid])
+                room = self.max_step_edges
+                for _, sid in heads:
+                    w = int(ready[sid][0].edges.shape[0])
+                    if w > self.max_step_edges:
+                        raise ValueError(f"a chunk of {w} edges exceeds the step cap")
+                    if w > room:
+                        continue
+                    room -= w
+                    c = ready[sid].popleft()
+                    ids.append(slot_of[sid])
+                    chunks.append(c.edges)
+                    items.append(c)
+                    rw += self.r * w
                 if ids:
                     self.bank.process(ids, chunks, st)
                     ev = torch.cuda.Event(enable_timing=True)

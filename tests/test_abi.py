@@ -108,3 +108,36 @@ def test_binding_refuses_w_beyond_the_tensor():
     for f in (tc.tc_process_batch, tc.tc_process_batch_naive, tc.tc_process_batch_noalloc):
         with pytest.raises(ValueError):
             f(0, e, w=6)
+
+
+def test_step_bytes_bound_holds():
+    # the serving admission bound: any step of at most n chunks and E edges
+    # in all needs no more scratch than tc_step_bytes_max(n, r_max, E)
+    # (pure host functions of the library, no GPU)
+    import numpy as np
+    import paper_1308_2166_amd as tc
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        n = int(rng.integers(1, 40))
+        ws = [int(x) for x in np.exp(rng.uniform(0, np.log(3e6), n)).astype(np.int64) + 1]
+        if rng.random() < 0.3:  # just above powers of two: the most rounding
+            ws = [(1 << int(rng.integers(0, 22))) + 1 for _ in range(n)]
+        rs = [int(x) for x in rng.integers(1, 1 << 18, n)]
+        got = tc.tc_step_bytes(rs, ws)
+        bound = tc.tc_step_bytes_max(n, max(rs), sum(ws))
+        assert 0 < got <= bound, (ws, rs)
+        # and the bound is not loose by more than the rounding it covers
+        assert bound <= 4 * got + (64 << 20), (got, bound)
+    assert tc.tc_step_bytes([5], [(1 << 28) + 1]) == 0
+    assert tc.tc_step_bytes_max(0, 5, 5) == 0
+
+
+def test_slots_for_budget_is_the_largest_fit():
+    import paper_1308_2166_amd as tc
+    from paper_1308_2166_amd import serve
+    r, cap = 1 << 16, 1 << 23
+    assert tc.tc_bank_bytes(r) == 36 * r + 16
+    for budget in (1 << 30, 2 << 30, 3 << 30, 7 << 30):
+        s = serve.slots_for_budget(budget, r, cap)
+        assert s == 0 or serve.server_bytes(s, r, cap) <= budget
+        assert serve.server_bytes(s + 1, r, cap) > budget

@@ -319,10 +319,12 @@ def test_rmat20_full_stream(tc):
 @pytest.mark.slow
 @pytest.mark.timeout(900)
 def test_rmat24_first_batches(tc):
-    # R-MAT scale 24 shape: r = 2^22, w = 2^24, first two batches, full state
+    # R-MAT scale 24 shape: r = 2^22, w = 2^24, the first four batches (up to
+    # |E| = 2^26, so Step 1 draws from bounds m + w up to 2^26), full state
+    # after every batch
     say("  generating rmat24 on the GPU")
     G, r, w, seed = inputs.workload("rmat24", device="cuda")
-    E = np_edges(G[:2 * w])
+    E = np_edges(G[:4 * w])
     del G
     torch.cuda.empty_cache()
     run_both(tc, E, r, seed, w)
@@ -522,7 +524,7 @@ def test_served_streams_equal_their_alone_runs(tc):
     chunks = serve.chunk_streams(graphs, seed=3, lo=200, hi=5000)
     seeds = [1000 + s for s in range(nstreams)]
     arrivals = serve.poisson_arrivals(chunks, rate_per_s=20000.0, seed=4)
-    srv = serve.Server(slots=7, r=r)  # tight: streams wait for slots
+    srv = serve.Server(r=r, max_step_edges=20000, slots=7)  # streams wait for slots
     lat, results, elapsed, rw = srv.run(arrivals, seeds)
     srv.close()
     assert len(lat) == sum(len(c) for c in chunks) and len(results) == nstreams
@@ -539,6 +541,37 @@ def test_served_streams_equal_their_alone_runs(tc):
                 o.process(np_edges(c))
             assert_same(alone.state(), o.state(), f"stream {s}")
             assert S == o.sum()
+
+
+def test_served_under_a_byte_budget(tc):
+    # admission by device bytes: the budget fixes the slot count, the
+    # library's allocations stay under it, and results equal the alone runs
+    from paper_1308_2166_amd import serve
+    nstreams, r, cap = 40, 5000, 30000
+    graphs = [inputs.rmat(11 + s % 3, 3000 + 400 * s, seed=300 + s, device="cuda")
+              for s in range(nstreams)]
+    chunks = serve.chunk_streams(graphs, seed=9, lo=300, hi=8000)
+    seeds = [7000 + s for s in range(nstreams)]
+    budget = serve.server_bytes(9, r, cap) + 12345  # room for 9 slots, not 10
+    assert serve.slots_for_budget(budget, r, cap) == 9
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    srv = serve.Server(r=r, max_step_edges=cap, budget_bytes=budget)
+    assert srv.slots == 9
+    lat, results, _, _ = srv.run(serve.poisson_arrivals(chunks, 5e4, seed=2), seeds)
+    torch.cuda.synchronize()
+    held = srv.device_bytes()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    assert held <= budget, (held, budget)
+    assert used <= budget + (64 << 20), (used, budget)  # allocator rounding
+    srv.close()
+    assert len(results) == nstreams
+    for s in range(0, nstreams, 5):
+        alone = tc.Bank(r, seeds[s])
+        for c in chunks[s]:
+            alone.process(c)
+        S, m, _ = tc.tc_estimate_ex(alone.h)
+        assert (results[s].S, results[s].m) == (S, m), s
 
 
 # -- a resident stream in one call (Step 3 of batch k overlaps batch k+1) -------
@@ -604,6 +637,99 @@ def test_process_stream_arguments(tc):
         assert ei.value.code == tc.TC_EINVAL
     g.process_stream(dev[:0], 10)  # empty stream: nothing happens
     assert g.m == 0 and g.batch == 0
+
+
+# -- a stream in host memory, copied by the library (double-buffered) ------------
+
+@pytest.mark.parametrize("m,w,r,pinned", [(20000, 2048, 4096, True), (60000, 9001, 20000, True),
+                                          (4999, 5000, 3000, False), (3001, 1000, 2000, False),
+                                          (700, 1, 50, True)])
+def test_host_stream_equals_oracle(tc, m, w, r, pinned):
+    n = max(60, m // 8)
+    E = np_edges(inputs.gnm(n, m, seed=m + 3 * w))
+    say(f"  host stream m={m} w={w} r={r} pinned={pinned}")
+    host = torch.from_numpy(E.view(np.int32).copy())
+    if pinned:
+        host = host.pin_memory()
+    g = tc.Bank(r, 23)
+    g.process_host_stream(host, w)
+    o = O.run_stream(E, r, 23, w)
+    assert_same(g.state(), o.state(), "host stream")
+    S, mm, tau = tc.tc_estimate_ex(g.h)
+    assert S == o.sum() and mm == m and g.batch == o.batch == -(-m // w)
+    # a second call (from a numpy array) continues the bank with larger batches
+    E2 = np_edges(inputs.gnm(n + 50, 3 * w + 5, seed=m + 1)) + np.uint32(n + 100)
+    g.process_host_stream(np.ascontiguousarray(E2), 2 * w)
+    for j in range(0, len(E2), 2 * w):
+        assert o.process(E2[j:j + 2 * w], "bulk") == O.OK
+    assert_same(g.state(), o.state(), "second call")
+
+
+def test_host_stream_rmat20_equals_resident(tc):
+    # the R-MAT scale-20 stream (four batches of 2^22) from pinned host
+    # memory: the same state as the resident stream, and the oracle's after
+    # the first two batches
+    G, r, w, seed = inputs.workload("rmat20", device="cuda")
+    host = G.cpu().pin_memory()
+    g = tc.Bank(r, seed)
+    tc.tc_set_vertex_bound(g.h, inputs.vertex_count("rmat20"))
+    g.process_host_stream(host[:2 * w], w)
+    o = O.run_stream(np_edges(G[:2 * w]), r, seed, w)
+    assert_same(g.state(), o.state(), "host stream, two batches")
+    g.process_host_stream(host[2 * w:], w)
+    ref = tc.Bank(r, seed)
+    ref.process_stream(G, w)
+    assert_same(g.state(), ref.state(), "host stream vs resident stream")
+    assert tc.tc_estimate_ex(g.h) == tc.tc_estimate_ex(ref.h)
+
+
+def test_host_stream_arguments(tc):
+    g = tc.Bank(100, 1)
+    host = torch.from_numpy(np_edges(inputs.gnm(50, 200, seed=1)).view(np.int32).copy())
+    for w in (0, (1 << 28) + 1):
+        with pytest.raises(tc.TcError) as ei:
+            g.process_host_stream(host, w)
+        assert ei.value.code == tc.TC_EINVAL
+    with pytest.raises(TypeError):
+        g.process_host_stream(host.cuda(), 10)
+    g.process_host_stream(host[:0], 10)  # empty stream: nothing happens
+    assert g.m == 0 and g.batch == 0
+    # not capturable: refused before anything is enqueued
+    tc.tc_reserve(g.h, 64)
+    gr = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    with pytest.raises(tc.TcError) as ei:
+        with torch.cuda.graph(gr, stream=cs):
+            g.process_host_stream(host, 64, cs)
+    assert ei.value.code == tc.TC_EINVAL
+    torch.cuda.synchronize()
+    assert g.m == 0
+    g.process_host_stream(host, 64)
+    assert g.m == 200 and g.batch == 4
+
+
+# -- device memory accounting ------------------------------------------------------
+
+def test_device_bytes_match_the_allocations(tc):
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    r, w = 1 << 20, 1 << 21
+    g = tc.Bank(r, 5)
+    tc.tc_reserve(g.h, w)
+    torch.cuda.synchronize()
+    held = tc.tc_device_bytes(g.h)
+    # one bank, the step scratch, and 16 bytes of per-object words
+    assert held == tc.tc_bank_bytes(r) + tc.tc_step_bytes([r], [w]) + 16
+    # what the device lost: no more than reported, up to the allocator's
+    # rounding of each of the ~20 allocations (at most 2 MiB each)
+    used = free0 - torch.cuda.mem_get_info()[0]
+    assert used <= held + (64 << 20), (held, used)
+    # host-ingest staging is counted too
+    host = torch.zeros((3000, 2), dtype=torch.int32).pin_memory()
+    host[:, 1] = 1
+    g.process_host_stream(host, 3000)
+    assert tc.tc_device_bytes(g.h) == held + 16 * 3000
+    g.close()
 
 
 # -- declared vertex bound: fewer radix passes, same results ----------------------
