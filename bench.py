@@ -72,10 +72,15 @@ def alg_bytes(kernel: str, w: int, r: int, nontrivial: list) -> float:
         return r * 4.0
     if kernel == "k_est":
         return r * (20.0 + 4.0 + 12.0 + 12.0)
-    if kernel == "k_post":
-        return r * 8.0
-    if kernel == "k_probe":
-        return 8.0 * w
+    # Step 3: the join's partition passes read W and the closing edges,
+    # write one 8-byte record per edge and per estimator at most, and the
+    # join reads them back
+    if kernel == "k_pcnt":
+        return 8.0 * w + 8.0 * r
+    if kernel == "k_pscat":
+        return 16.0 * w + 16.0 * r
+    if kernel == "k_pjoin":
+        return 8.0 * w + 8.0 * r
     return 0.0
 
 
@@ -435,7 +440,7 @@ def kernel_source_hash() -> str:
 STEP_ORDER = (["k_hist", "k_fold_step1", "k_cscan<0>", "k_scat<0>"]
               + [f"{k}<{p}>" for p in range(1, 4)
                  for k in ("k_cnt", "k_csum", "k_cscan", "k_scat")]
-              + ["k_dir", "k_est", "k_post", "k_qbits", "k_probe"])
+              + ["k_dir", "k_est", "k_pcnt", "k_pscan", "k_pscat", "k_pjoin"])
 
 
 def _short(name: str) -> str:

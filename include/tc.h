@@ -76,7 +76,7 @@ int tc_process_batch(tc_state *s, const uint32_t *edges, uint32_t w,
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * bulk update as tc_process_batch, with the same kernels and a bit-identical
  * result, but every per-step buffer (arcs, radix counts, directory, Step-3
- * query table, per-estimator step words) is carved from a static device
+ * join partitions, per-estimator step words) is carved from a static device
  * array of the library, 64 MiB on each device, held from the first
  * tc_create on that device until the process ends.  The call allocates
  * and frees nothing, never synchronises, and only enqueues kernels on

@@ -66,10 +66,16 @@ uint32_t log2_ceil(uint64_t x) {
 uint32_t dir_log2_for(uint32_t w) {
   return std::max<uint32_t>(10, log2_ceil(4ull * w));
 }
-// query-table slots for a bank of r estimators: at most r queries, so the
-// load stays at or below 1/4
-uint32_t qt_log2_for(uint32_t r) {
-  return std::max<uint32_t>(10, log2_ceil(4ull * r));
+// Step-3 join of a bank of r estimators: partitions of about kPartQ
+// waiting estimators each (at most 2^kMaxPartLog2), tiles of kPTile
+// elements, and join slices of about kJoinEdges batch edges
+uint32_t part_log2_for(uint32_t r) {
+  return std::min<uint32_t>(kMaxPartLog2, log2_ceil((r + kPartQ - 1) / kPartQ));
+}
+uint32_t ptiles_for(uint64_t n) { return (uint32_t)((n + kPTile - 1) / kPTile); }
+uint32_t jslices_for(uint32_t w, uint32_t pbits) {
+  const uint64_t per = (uint64_t)kJoinEdges << pbits;
+  return (uint32_t)std::max<uint64_t>(1, (w + per - 1) / per);
 }
 
 // Scratch a step needs for one more chunk of w > 0 edges of a bank of r
@@ -92,15 +98,13 @@ void dfree(T*& p) {
 
 // kernels (bit k = launch k of a step) that a step with npass radix passes
 // launches: the four kernels of each pass at or above npass are skipped,
-// every pass's k_cscan when the step's segments are single chunks, and
-// k_qbits when the step's query tables go without the bitmap
-uint32_t launched_kernels(uint32_t npass, bool single_chunk, bool bitmap) {
+// and every pass's k_cscan when the step's segments are single chunks
+uint32_t launched_kernels(uint32_t npass, bool single_chunk) {
   uint32_t m = (1u << kNumKernels) - 1u;
   for (uint32_t p = npass < 1 ? 1 : npass; p < (uint32_t)kPasses; ++p)
     m &= ~(15u << (4 + 4 * (p - 1)));
   if (single_chunk)
     for (uint32_t p = 0; p < (uint32_t)kPasses; ++p) m &= ~(1u << (2 + 4 * p));
-  if (!bitmap) m &= ~(1u << (kNumKernels - 2));
   return m;
 }
 
@@ -110,9 +114,6 @@ uint32_t launched_kernels(uint32_t npass, bool single_chunk, bool bitmap) {
 // phases touch exists twice and step s uses copy s & 1.
 struct ParityScratch {
   SegWork* work = nullptr;    // per-segment histograms, counters, modes
-  uint32_t* qt = nullptr;     // Step-3 query tables (owners)
-  uint8_t* qfp = nullptr;
-  uint32_t* qbits = nullptr;  // occupancy bitmap of the query tables
   SegDesc* segs = nullptr;    // device copy of the step's descriptors
 };
 
@@ -122,17 +123,20 @@ struct Sizes {
   uint64_t tiles = 0;  // radix tiles
   uint64_t dir = 0;    // directory slots
   uint64_t doff = 0;   // dense-directory words
-  uint64_t qt = 0;     // query-table slots
+  uint64_t prow = 0;   // Step-3 partition-count row words
+  uint64_t parts = 0;  // Step-3 partitions
   uint64_t need = 0;   // need bytes
   uint64_t nest = 0;   // estimators (per-estimator step words)
   uint32_t segs = 0;   // segments
   bool fits(const Sizes& z) const {
-    return z.arcs <= arcs && z.tiles <= tiles && z.dir <= dir && z.doff <= doff && z.qt <= qt &&
+    return z.arcs <= arcs && z.tiles <= tiles && z.dir <= dir && z.doff <= doff &&
+           z.prow <= prow && z.parts <= parts &&
            z.need <= need && z.nest <= nest && z.segs <= segs;
   }
   void grow(const Sizes& z) {
     arcs = std::max(arcs, z.arcs), tiles = std::max(tiles, z.tiles);
-    dir = std::max(dir, z.dir), qt = std::max(qt, z.qt), need = std::max(need, z.need);
+    dir = std::max(dir, z.dir), need = std::max(need, z.need);
+    prow = std::max(prow, z.prow), parts = std::max(parts, z.parts);
     doff = std::max(doff, z.doff);
     nest = std::max(nest, z.nest), segs = std::max(segs, z.segs);
   }
@@ -145,7 +149,9 @@ void add_chunk(Sizes& z, uint32_t r, uint32_t w) {
   z.tiles += (2ull * w + kTile - 1) / kTile;
   z.dir += 1ull << dl;
   z.doff += (1ull << dl) + kDoffPad;
-  z.qt += 1ull << qt_log2_for(r);
+  const uint32_t pb = part_log2_for(r);
+  z.prow += (uint64_t)(ptiles_for(w) + ptiles_for(r)) << pb;
+  z.parts += 1ull << pb;
   z.nest += r;
   z.segs += 1;
 }
@@ -160,7 +166,9 @@ Sizes step_bound(uint32_t n, uint32_t r_max, uint64_t E) {
   z.tiles = 2 * E / kTile + n;
   z.dir = 8 * E + 1024ull * n;
   z.doff = z.dir + (uint64_t)kDoffPad * n;
-  z.qt = (uint64_t)n << qt_log2_for(r_max);
+  const uint32_t pb = part_log2_for(r_max);  // grows with r
+  z.prow = (E / kPTile + n + (uint64_t)n * ptiles_for(r_max)) << pb;
+  z.parts = (uint64_t)n << pb;
   z.need = E + 16ull * n;
   z.nest = (uint64_t)n * r_max;
   z.segs = n;
@@ -180,6 +188,11 @@ struct Scratch {
   uint32_t* doff = nullptr;  // dense directories (rewritten every step)
   uint8_t* need = nullptr;
   uint32_t* inv = nullptr;
+  uint32_t* prow = nullptr;   // Step-3 join: partition-count rows,
+  uint32_t* ptot = nullptr;   // partition totals and starts (two sides),
+  uint32_t* pstart = nullptr;
+  uint64_t* erec = nullptr;   // and the partitioned records
+  uint64_t* qrec = nullptr;
   uint32_t* hpart = nullptr;  // k_hist partial counts (one row per tile)
   uint32_t* mpart = nullptr;  // k_hist partial max ids
   ParityScratch par[2];
@@ -225,10 +238,12 @@ uint64_t carve(uint8_t* base, const Sizes& z, int nparity, bool stat, Scratch* o
   take(s.doff, z.doff);
   take(s.need, z.need), take(s.inv, z.arcs);
   take(s.hpart, z.tiles * kRowWords), take(s.mpart, z.tiles);
+  // (one copy: the join runs only while no other step's join does)
+  take(s.prow, z.prow), take(s.ptot, 2 * z.parts), take(s.pstart, 2 * z.parts);
+  take(s.erec, z.arcs / 2), take(s.qrec, z.nest);
   for (int p = 0; p < nparity; ++p) {
     ParityScratch& P = s.par[p];
     if (!stat) take(P.work, z.segs);
-    take(P.qt, z.qt), take(P.qfp, z.qt), take(P.qbits, z.qt / 32);
     if (!stat) take(P.segs, z.segs);
   }
   if (nparity == 1) s.par[1] = s.par[0];
@@ -489,9 +504,7 @@ struct Engine {
     bool bad = hipMemsetAsync(S.dir, 0, sizeof(DirSlot) * cap.dir, st) ||
                hipMemsetAsync(S.need, 0, cap.need, st);
     for (ParityScratch& p : S.par)
-      bad = bad || hipMemsetAsync(p.work, 0, sizeof(SegWork) * cap.segs, st) ||
-            hipMemsetAsync(p.qt, 0xFF, sizeof(uint32_t) * cap.qt, st) ||
-            hipMemsetAsync(p.qfp, 0, cap.qt, st);
+      bad = bad || hipMemsetAsync(p.work, 0, sizeof(SegWork) * cap.segs, st);
     if (bad || hipStreamSynchronize(st))
       return fail(TC_EHIP, "clearing step scratch failed");
     return TC_OK;
@@ -541,7 +554,7 @@ struct Engine {
     std::vector<uint32_t> bank;  // bank of each segment
     Sizes z;
     uint64_t hblks = 0, chunks = 0;
-    bool big_qt = false;  // some segment's query table gets the bitmap
+    uint64_t ptiles = 0, pscans = 0, jblks = 0;  // Step-3 grids
   };
 
   int plan(uint32_t nchunks, const uint32_t* ids, const uint32_t* const* edges,
@@ -569,7 +582,6 @@ struct Engine {
       d.arc_off = z.arcs;
       d.dir_off = z.dir;
       d.doff_off = z.doff;
-      d.qt_off = z.qt;
       d.w = w[k];
       d.r = r[b];
       d.tile_off = (uint32_t)z.tiles;
@@ -581,15 +593,26 @@ struct Engine {
       d.nchunks = (d.ntiles + kChunk - 1) / kChunk;
       pl.chunks += d.nchunks;
       d.dir_log2 = dir_log2_for(w[k]);
-      d.qt_log2 = qt_log2_for(r[b]);
-      pl.big_qt = pl.big_qt || d.qt_log2 > kBitmapMinLog2;
       d.need_off = (uint32_t)z.need;
+      d.prow_off = z.prow;
+      d.pbits = part_log2_for(r[b]);
+      d.ptile_off = (uint32_t)pl.ptiles;
+      d.netile = ptiles_for(w[k]);
+      d.nqtile = ptiles_for(r[b]);
+      pl.ptiles += d.netile + d.nqtile;
+      d.part_off = (uint32_t)(z.parts);
+      d.pscan_off = (uint32_t)pl.pscans;
+      pl.pscans += 2ull * (((1ull << d.pbits) + 63) / 64);
+      d.jslices = jslices_for(w[k], d.pbits);
+      d.jblk_off = (uint32_t)pl.jblks;
+      pl.jblks += (uint64_t)d.jslices << d.pbits;
       add_chunk(z, r[b], w[k]);
       pl.segs.push_back(d);
       pl.bank.push_back(b);
     }
     z.segs = (uint32_t)pl.segs.size();
-    if (z.tiles >= 0x7FFFFFFFull || z.need >= 0xFFFFFFFFull)
+    if (z.tiles >= 0x7FFFFFFFull || z.need >= 0xFFFFFFFFull || pl.ptiles >= 0x7FFFFFFFull ||
+        pl.jblks >= 0x7FFFFFFFull || z.parts >= 0x7FFFFFFFull)
       return fail(TC_EINVAL, "step too large");
     return TC_OK;
   }
@@ -615,10 +638,11 @@ struct Engine {
     a.nchunk = (uint32_t)pl.chunks;
     a.dir = X.dir;
     a.doff = X.doff;
-    a.qt = P.qt;
-    a.qfp = P.qfp;
-    a.qbits = pl.big_qt ? P.qbits : nullptr;
-    a.qt_slots = z.qt;
+    a.prow = X.prow, a.ptot = X.ptot, a.pstart = X.pstart;
+    a.erec = X.erec, a.qrec = X.qrec;
+    a.nptile = (uint32_t)pl.ptiles;
+    a.npscan = (uint32_t)pl.pscans;
+    a.njblk = (uint32_t)pl.jblks;
     a.j1 = J1;
     a.qq = QQ;
     a.qthr = QT;
@@ -712,7 +736,7 @@ struct Engine {
               return fail(TC_EHIP, "hipEventCreate failed");
       }
       ev_pending.push_back(ev);
-      ev_launched.push_back(launched_kernels(npass, a.single_chunk != 0, a.qbits != nullptr));
+      ev_launched.push_back(launched_kernels(npass, a.single_chunk != 0));
     }
     return launch(pl, a, st, ev, overlap);
   }
@@ -1215,7 +1239,7 @@ static const char* const kKernelNames[kNumKernels] = {
     "k_cnt<1>", "k_csum<1>", "k_cscan<1>", "k_scat<1>",
     "k_cnt<2>", "k_csum<2>", "k_cscan<2>", "k_scat<2>",
     "k_cnt<3>", "k_csum<3>", "k_cscan<3>", "k_scat<3>",
-    "k_dir", "k_est", "k_post", "k_qbits", "k_probe"};
+    "k_dir", "k_est", "k_pcnt", "k_pscan", "k_pscat", "k_pjoin"};
 
 static int set_timing(Engine& e, uint32_t mask) {
   int rc = e.collect_times();

@@ -28,7 +28,7 @@ constexpr int kWidePasses = 2;           // passes of wide digits
 // passes: pass P's counts start at word P << D
 constexpr int kRowWords = kWidePasses << kWideBits;
 static_assert(kRowWords >= kPasses << 8, "a row holds every 8-bit pass");
-constexpr int kNumKernels = 21;  // launches per step (k_hist .. k_probe)
+constexpr int kNumKernels = 22;  // launches per step (k_hist .. k_pjoin)
 constexpr int kHistTiles = 1;   // tiles per k_hist block (one: its counts are
                                 // the per-tile counts of the first radix pass)
 constexpr uint32_t kChunk = 32;  // tiles per chunk of the radix scans (and
@@ -71,7 +71,6 @@ struct SegDesc {
   uint64_t arc_off;       // first arc slot in the arc buffers (2 * sum w)
   uint64_t dir_off;       // first directory slot (hashed directory)
   uint64_t doff_off;      // first word of the dense offsets (dense directory)
-  uint64_t qt_off;        // first query-table slot
   uint32_t w;             // edges in the chunk
   uint32_t r;             // estimators in the bank
   uint32_t tile_off;      // first global tile of the segment
@@ -81,8 +80,20 @@ struct SegDesc {
   uint32_t chunk_off;     // first global radix chunk of the segment
   uint32_t nchunks;       // ceil(ntiles / kChunk)
   uint32_t dir_log2;      // log2 of the directory region (slots)
-  uint32_t qt_log2;       // log2 of the query-table region (slots)
   uint32_t need_off;      // first byte of the "position needed" bytes (w bytes)
+  // Step 3 (partitioned join): the segment's edges and waiting estimators
+  // go to 2^pbits partitions; k_pcnt / k_pscat blocks take partition tiles
+  // (netile of edges, then nqtile of estimators), k_pscan blocks 64
+  // partitions of one side, k_pjoin blocks one slice of one partition
+  uint64_t prow_off;      // first word of the segment's partition-count rows
+  uint32_t pbits;         // log2 of the partitions
+  uint32_t ptile_off;     // first partition tile (global)
+  uint32_t netile;        // edge tiles: ceil(w / kPTile)
+  uint32_t nqtile;        // estimator tiles: ceil(r / kPTile)
+  uint32_t part_off;      // first partition (global)
+  uint32_t pscan_off;     // first k_pscan block (global)
+  uint32_t jslices;       // k_pjoin blocks per partition
+  uint32_t jblk_off;      // first k_pjoin block (global)
 };
 
 // per-segment values produced during a step (device)
@@ -109,19 +120,23 @@ struct DirSlot {
   uint32_t end;
 };
 
-// A segment's query table of more than 2^kBitmapMinLog2 slots (one
-// fingerprint byte each) is probed through an occupancy bitmap: smaller
-// ones mostly stay in a 4 MB XCD L2 anyway.
-constexpr uint32_t kBitmapMinLog2 = 22;
-
-// Step-3 query table (one region per segment, linear probing): slot s
-// holds qt[s], the estimator that owns it (kNone = free), and qfp[s], a
-// nonzero 8-bit fingerprint of the hash of the closing edge that estimator
-// waits for (0 = free), which is what a probe scans.  The edge itself and
-// the first batch position that closes it are the owner's qq and qthr
-// entries.  Every waiting estimator owns one slot (equal edges share a
-// probe cluster).  Owners and fingerprints are reset by k_hist at the
-// start of every step.
+// Step 3 (Sec. 4.4) as a partitioned hash join.  Every waiting
+// estimator's closing edge q and every batch edge are sent by the top
+// pbits bits of h = mix64(q) (a bijection) to one of 2^pbits partitions,
+// as 8-byte records (top 32 bits of h) << 32 | (batch position, or the
+// estimator's state index), grouped by partition by a count / scan /
+// scatter over tiles of kPTile elements.  One join block per slice of a
+// partition loads the partition's waiting estimators into an LDS hash
+// table (rounds of kJoinQ) and streams the slice's edges through it; equal
+// high words are checked against the edge itself and the estimator's
+// closing edge and position limit.
+constexpr uint32_t kPTile = 16384;     // elements per partition tile (the
+                                       // scatter stages a tile in LDS)
+constexpr uint32_t kPartQ = 2048;      // estimators per partition aimed at
+constexpr uint32_t kMaxPartLog2 = 11;  // at most 2048 partitions per segment
+constexpr uint32_t kJoinQ = 4096;      // query records per join round (LDS)
+constexpr uint32_t kJoinSlots = 8192;  // LDS hash slots (load <= 1/2)
+constexpr uint32_t kJoinEdges = 8192;  // edges per join slice aimed at
 
 struct StepArgs {
   const SegDesc* segs;    // device copy of all segment descriptors
@@ -146,13 +161,17 @@ struct StepArgs {
   uint32_t nchunk;        // total radix chunks over segments
   DirSlot* dir;
   uint32_t* doff;         // dense directories (CSR offsets)
-  uint32_t* qt;           // query table: owner per slot
-  uint8_t* qfp;           // query table: key fingerprint per slot
-  uint32_t* qbits;        // query table: bit s of word s / 32 set iff slot s
-                          // is taken (built from qfp after k_post); null
-                          // when no segment's table has more than
-                          // 2^kBitmapMinLog2 slots (no bitmap)
-  uint64_t qt_slots;      // query-table slots over all segments
+  // Step-3 join: per partition tile a row of 2^pbits counts (then in-side
+  // prefixes); per global partition g and side s (0 edges, 1 estimators)
+  // the total ptot[2g + s] and the start pstart[2g + s] of its records
+  uint32_t* prow;
+  uint32_t* ptot;
+  uint32_t* pstart;
+  uint64_t* erec;         // edge records, a segment's at arc_off / 2
+  uint64_t* qrec;         // estimator records, a segment's at gest_off
+  uint32_t nptile;        // partition tiles over segments
+  uint32_t npscan;        // k_pscan blocks over segments
+  uint32_t njblk;         // k_pjoin blocks over segments
   uint32_t* j1;           // per estimator: Step-1 replacement (see kSideV)
   uint64_t* qq;           // per estimator: closing edge it waits for, or kEmpty
   uint32_t* qthr;         // per estimator: first batch position that closes it

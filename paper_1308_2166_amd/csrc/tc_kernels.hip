@@ -2,8 +2,8 @@
 // Tirthapura, Sec. 4: bulkUpdateAll) for gfx950.
 //
 // One step = k_hist -> k_fold_step1 -> k_cscan<0> -> k_scat<0> -> up to
-// 3 x (k_cnt -> k_csum -> k_cscan -> k_scat) -> k_dir -> k_est -> k_post ->
-// k_qbits -> k_probe.
+// 3 x (k_cnt -> k_csum -> k_cscan -> k_scat) -> k_dir -> k_est -> k_pcnt ->
+// k_pscan -> k_pscat -> k_pjoin.
 //
 //  k_hist   per-tile counts of digit 0 of the 2w arcs (+ max id, self-loop
 //           check)
@@ -24,12 +24,15 @@
 //           every arc of a segment (above its largest id) is skipped on the
 //           device, and passes above a declared vertex bound are not
 //           launched.
-//  k_dir    vertex -> [start, end) of its arcs (tag-versioned directory),
-//           and the sorted index of the arcs of positions Step 1 picked
+//  k_dir    vertex -> [start, end) of its arcs (CSR offsets, or a
+//           tag-versioned hashed directory for sparse ids), and the sorted
+//           index of the arcs of positions Step 1 picked
 //  k_est    Step 2 for every estimator; records its Step-3 closing edge
-//  k_post   Step 3 queries into a hash table with a fingerprint byte per slot
-//  k_qbits  the table's occupancy bitmap (one bit per slot, from the bytes)
-//  k_probe  Step 3: one pass over W closes the estimators waiting for it
+//  k_pcnt, k_pscan, k_pscat
+//           Step 3: batch edges and waiting estimators counted, offset and
+//           scattered into hash partitions of their (closing) edge
+//  k_pjoin  Step 3: per partition, the waiting estimators in an LDS hash
+//           table, the partition's batch edges streamed through it
 #include <algorithm>
 
 #include "tc_internal.h"
@@ -208,18 +211,6 @@ __device__ __forceinline__ void st_bins(uint32_t* p, const uint32_t (&v)[N]) {
   }
 }
 
-// Blocks [0, nb) of a launch empty the Step-3 query tables (first used by
-// k_est of this step); slot counts are multiples of 1024, so whole uint4s
-// cover them.  Run by k_hist, whose stores overlap its reads of W.
-__device__ void clear_qtables(const StepArgs& a, uint32_t b, uint32_t nb) {
-  const uint64_t t0 = (uint64_t)b * kBlock + threadIdx.x, step = (uint64_t)nb * kBlock;
-  uint4* o4 = reinterpret_cast<uint4*>(a.qt);
-  const uint4 none = make_uint4(kNone, kNone, kNone, kNone);
-  for (uint64_t t = t0; t < a.qt_slots / 4; t += step) o4[t] = none;
-  uint4* f4 = reinterpret_cast<uint4*>(a.qfp);
-  for (uint64_t t = t0; t < a.qt_slots / 16; t += step) f4[t] = make_uint4(0, 0, 0, 0);
-}
-
 // ---------------------------------------------------------------------------
 // k_hist: per-tile counts of digit 0 of the arc keys
 // ---------------------------------------------------------------------------
@@ -286,9 +277,8 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
     }
     xs[it] = x;
   }
-  // clear the query tables and the need bytes (Step 1 marks them next)
-  // while the loads above are in flight
-  clear_qtables(a, hb, a.nhblk);
+  // clear the need bytes (Step 1 marks them next) while the loads above
+  // are in flight
   {
     uint4* n4 = reinterpret_cast<uint4*>(a.need);
     for (uint64_t t = (uint64_t)hb * kBlock + tid; t < a.need_bytes / 16;
@@ -980,15 +970,6 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
 // ---------------------------------------------------------------------------
 // k_est: Steps 1 and 2 per estimator, Step-3 query posted
 // ---------------------------------------------------------------------------
-// query-table home slot and fingerprint of a closing edge (independent
-// bits of one hash)
-__device__ __forceinline__ uint32_t q_home(uint64_t hq, uint32_t mask) {
-  return (uint32_t)hq & mask;
-}
-__device__ __forceinline__ uint8_t q_fp(uint64_t hq) {
-  return (uint8_t)(1u + (uint32_t)(hq >> 56) % 255u);  // never 0 (free)
-}
-
 __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (gid >= a.nest) return;
@@ -1091,138 +1072,385 @@ __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   uint64_t q = kEmpty;
   if (r2 != kEmpty && !closed) q = closing(r1, r2);
   a.qq[e] = q;
-  // first claim on the query's home slot: a plain store (among racing
-  // stores one value lands whole); k_post checks which estimator won and
-  // moves the others on, so the common case needs no atomic
-  if (q != kEmpty)
-    a.qt[S.qt_off + q_home(mix64(q), (1u << S.qt_log2) - 1u)] = (uint32_t)e;
   a.qthr[e] = (p2 == kNone) ? 0u : p2 + 1;  // closes at a position >= this
   a.r2[e] = r2;
   a.cc[e] = (uint32_t)c | (closed ? kClosed : 0u);
 }
 
 // ---------------------------------------------------------------------------
-// k_post: every waiting estimator owns a slot of its segment's query table:
-// the home slot if its claim there stood, else the first free slot after
-// it, taken with a CAS (a slot once owned stays owned, so the slots
-// between a key's home and its slot are all occupied); then the slot's
-// fingerprint
+// Step 3 (Sec. 4.4): which waiting estimators' closing edges occur in W at
+// or after their position limit.  A hash join: the batch edges and the
+// waiting estimators are grouped by partition of their (closing) edge's
+// hash, then each partition's estimators go into an LDS hash table that the
+// partition's edges are streamed through.  Closed flags are an OR over the
+// matches, so the order of records inside a partition does not matter.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_post(StepArgs a) {
-  const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (gid >= a.nest) return;
-  if (*a.err & kErrFatal) return;
-  const uint32_t sidx = seg_of_est(a, gid);
-  const SegDesc S = seg_desc(a, sidx);
-  const uint64_t e = S.est_off + (gid - S.gest_off);
-  const uint64_t q = a.qq[e];
-  if (q == kEmpty) return;
-  const uint32_t mask = (1u << S.qt_log2) - 1u;
-  const uint64_t hq = mix64(q);
-  uint32_t* qt = a.qt + S.qt_off;
-  uint32_t s = q_home(hq, mask);
-  if (qt[s] != (uint32_t)e) {
-    uint32_t probe = 0;
-    do {
-      s = (s + 1) & mask;
-      if (++probe > mask) {  // cannot happen: at most a quarter of the slots are used
-        atomicOr(a.err, kErrProbe);
-        return;
-      }
-    } while (atomicCAS(&qt[s], kNone, (uint32_t)e) != kNone);
+
+// segment of block b of a launch whose segments' blocks start at `off`
+template <uint32_t SegDesc::*Off>
+__device__ __forceinline__ uint32_t seg_of_block(const StepArgs& a, uint32_t b) {
+  if (a.nseg == 1) return 0;
+  uint32_t lo = 0, hi = a.nseg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (a.segs[mid].*Off <= b) lo = mid; else hi = mid - 1;
   }
-  a.qfp[S.qt_off + s] = q_fp(hq);
+  return lo;
 }
 
-// ---------------------------------------------------------------------------
-// k_probe: Step 3, stream W once; every batch edge that some estimators
-// wait for closes those whose level-2 edge came earlier
-// ---------------------------------------------------------------------------
-constexpr int kProbeEdges = kTile / 2 / kBlock;  // edges per thread
-
-// k_qbits: one bit per query-table slot, set iff its fingerprint byte is
-// nonzero (the slot is taken).  At load <= 1/4 most probes start at a free
-// slot; the bitmap (an eighth of the fingerprint table: 0.5 MB at r = 2^20,
-// 2 MB at r = 2^22) stays in each XCD's L2 where the fingerprints do not.
-// One thread per 32 slots: two 16-byte loads, one word stored, every word
-// of the map rewritten each step.
-__device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t x) {
-  // bit i (i = 0..3) set iff byte i of x is nonzero
-  const uint32_t h = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;  // top bit per byte
-  const uint32_t t = (h >> 7) & 0x01010101u;
-  return (t | (t >> 7) | (t >> 14) | (t >> 21)) & 0xFu;
+__device__ __forceinline__ uint32_t part_of(uint64_t h, uint32_t pbits) {
+  return pbits ? (uint32_t)(h >> (64u - pbits)) : 0u;
 }
 
-__global__ __launch_bounds__(kBlock) void k_qbits(StepArgs a) {
-  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= a.qt_slots / 32) return;
-  const uint4* f = reinterpret_cast<const uint4*>(a.qfp) + 2 * t;
-  const uint4 x = f[0], y = f[1];
-  const uint32_t b = nonzero_bytes4(x.x) | nonzero_bytes4(x.y) << 4 |
-                     nonzero_bytes4(x.z) << 8 | nonzero_bytes4(x.w) << 12 |
-                     nonzero_bytes4(y.x) << 16 | nonzero_bytes4(y.y) << 20 |
-                     nonzero_bytes4(y.z) << 24 | nonzero_bytes4(y.w) << 28;
-  a.qbits[t] = b;
+// The partition kernels run 1024-thread blocks (sixteen waves) over tiles
+// of kPTile elements: enough waves per CU to keep their loads in flight.
+constexpr int kPThreads = 1024;
+constexpr int kPWaves = kPThreads / 64;
+
+// exclusive scan of one value per thread over a kPThreads block
+__device__ __forceinline__ uint32_t pblock_excl_scan(uint32_t v, uint32_t* s_tmp,
+                                                     uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_tmp[wave] = x;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kPWaves; ++w) {
+    const uint32_t t = s_tmp[w];
+    off += (w < wave) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_probe(StepArgs a) {
+// Up to kPTile elements of one side of a partition tile: edges of W
+// (side 0) or estimators (side 1, waiting ones only).  f(h, id, valid) is
+// called by every thread for each of its elements, in rounds of kPRound
+// loads issued together; h = mix64 of the (closing) edge, id its batch
+// position or state index.  Every lane of a wave makes the same calls.
+constexpr uint32_t kPRound = 8;
+
+template <class F>
+__device__ __forceinline__ void for_tile(const StepArgs& a, const SegDesc& S, uint32_t t,
+                                         F&& f) {
+  const int tid = threadIdx.x;
+  if (t < S.netile) {
+    const uint2* W = reinterpret_cast<const uint2*>(S.edges);
+    const uint32_t j0 = t * kPTile, j1 = min(j0 + kPTile, S.w);
+    for (uint32_t b = j0; b < j1; b += kPRound * kPThreads) {
+      uint2 ed[kPRound];
+#pragma unroll
+      for (uint32_t k = 0; k < kPRound; ++k)
+        ed[k] = W[min(b + k * kPThreads + tid, j1 - 1)];
+#pragma unroll
+      for (uint32_t k = 0; k < kPRound; ++k) {
+        const uint32_t j = b + k * kPThreads + tid;
+        f(mix64(canon(ed[k].x, ed[k].y)), j, j < j1);
+      }
+    }
+  } else {
+    const uint32_t i0 = (t - S.netile) * kPTile, i1 = min(i0 + kPTile, S.r);
+    const uint64_t* qq = a.qq + S.est_off;
+    for (uint32_t b = i0; b < i1; b += kPRound * kPThreads) {
+      uint64_t q[kPRound];
+#pragma unroll
+      for (uint32_t k = 0; k < kPRound; ++k) q[k] = qq[min(b + k * kPThreads + tid, i1 - 1)];
+#pragma unroll
+      for (uint32_t k = 0; k < kPRound; ++k) {
+        const uint32_t i = b + k * kPThreads + tid;
+        f(mix64(q[k]), (uint32_t)S.est_off + i, i < i1 && q[k] != kEmpty);
+      }
+    }
+  }
+}
+
+// Lanes of the wave whose partitions are equal (nbits low bits compared):
+// one ballot and one three-input bit operation per bit and mask half.
+__device__ __forceinline__ uint64_t match_lanes(uint32_t p, bool valid, uint32_t nbits) {
+  const uint64_t vm = __ballot(valid);
+  uint32_t lo = (uint32_t)vm, hi = (uint32_t)(vm >> 32);
+  for (uint32_t b = 0; b < nbits; ++b) {
+    const uint32_t t = (uint32_t)((int32_t)(p << (31 - b)) >> 31);
+    const uint64_t bb = __ballot(t != 0u);
+    lo = __builtin_amdgcn_bitop3_b32(lo, t, (uint32_t)bb, 0x90);
+    hi = __builtin_amdgcn_bitop3_b32(hi, t, (uint32_t)(bb >> 32), 0x90);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// With few partitions (pbits <= kAggBits) a wave's equal partitions are
+// counted or ranked once per group (one LDS atomic per distinct partition);
+// with more, one LDS atomic per element (they rarely collide).
+constexpr uint32_t kAggBits = 4;
+
+// Tiles of one segment and side land on the XCDs in runs of eight (as in the
+// radix passes): neighbouring tiles' runs of a partition then mostly meet in
+// one L2 before they are written back.
+__device__ __forceinline__ uint32_t ptile_block(uint32_t b) {
+  return xcd_block(b, gridDim.x);
+}
+
+// k_pcnt: per partition tile, the count of its elements in each partition
+__global__ __launch_bounds__(kPThreads) void k_pcnt(StepArgs a) {
+  __shared__ uint32_t s_h[1u << kMaxPartLog2];
+  __shared__ uint32_t s_seg;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const uint32_t blk = ptile_block(blockIdx.x);
+  if (tid == 0) s_seg = seg_of_block<&SegDesc::ptile_off>(a, blk);
+  for (uint32_t p = tid; p < (1u << kMaxPartLog2); p += kPThreads) s_h[p] = 0;
+  __syncthreads();
+  if (*a.err & kErrFatal) return;
+  const SegDesc S = seg_desc(a, uniform(s_seg));
+  const uint32_t P = 1u << S.pbits, t = blk - S.ptile_off;
+  const bool agg = S.pbits <= kAggBits;
+  for_tile(a, S, t, [&](uint64_t h, uint32_t, bool valid) {
+    const uint32_t p = part_of(h, S.pbits);
+    if (agg) {
+      const uint64_t mm = match_lanes(p, valid, S.pbits);
+      if (valid && __popcll(mm & ((1ull << lane) - 1ull)) == 0)
+        atomicAdd(&s_h[p], (uint32_t)__popcll(mm));
+    } else if (valid) {
+      atomicAdd(&s_h[p], 1u);
+    }
+  });
+  __syncthreads();
+  uint32_t* row = a.prow + S.prow_off + (uint64_t)t * P;
+  for (uint32_t p = tid; p < P; p += kPThreads) row[p] = s_h[p];
+}
+
+// k_pscan: per (segment, side, 64 partitions), each partition's count rows
+// over the side's tiles become exclusive prefixes, and its total is kept.
+// Wave w of the sixteen takes the w-th sixteenth of the tiles, loaded in
+// batches.
+constexpr uint32_t kPScanBatch = 16;
+
+__global__ __launch_bounds__(kPThreads) void k_pscan(StepArgs a) {
+  __shared__ uint32_t s_part[kPWaves][64];
+  __shared__ uint32_t s_seg;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_seg = seg_of_block<&SegDesc::pscan_off>(a, blockIdx.x);
+  __syncthreads();
+  if (*a.err & kErrFatal) return;
+  const SegDesc S = seg_desc(a, uniform(s_seg));
+  const uint32_t P = 1u << S.pbits, ngroups = (P + 63) / 64;
+  const uint32_t b = blockIdx.x - S.pscan_off, side = b / ngroups;
+  const uint32_t p = (b % ngroups) * 64 + lane;
+  const bool valid = p < P;
+  const uint32_t t0 = side ? S.netile : 0u, nt = side ? S.nqtile : S.netile;
+  const uint32_t per = (nt + kPWaves - 1) / kPWaves;
+  const uint32_t lo = min((uint32_t)wave * per, nt), hi = min(lo + per, nt);
+  uint32_t* col = a.prow + S.prow_off + (uint64_t)t0 * P + (valid ? p : 0u);
+  uint32_t sum = 0;
+  for (uint32_t c = lo; c < hi; c += kPScanBatch) {
+    uint32_t v[kPScanBatch];
+#pragma unroll
+    for (uint32_t i = 0; i < kPScanBatch; ++i)
+      v[i] = valid && c + i < hi ? col[(uint64_t)(c + i) * P] : 0u;
+#pragma unroll
+    for (uint32_t i = 0; i < kPScanBatch; ++i) sum += v[i];
+  }
+  s_part[wave][lane] = sum;
+  __syncthreads();
+  uint32_t run = 0, total = 0;
+#pragma unroll
+  for (int k = 0; k < kPWaves; ++k) {
+    run += k < wave ? s_part[k][lane] : 0u;
+    total += s_part[k][lane];
+  }
+  for (uint32_t c = lo; c < hi; c += kPScanBatch) {
+    uint32_t v[kPScanBatch];
+#pragma unroll
+    for (uint32_t i = 0; i < kPScanBatch; ++i)
+      v[i] = valid && c + i < hi ? col[(uint64_t)(c + i) * P] : 0u;
+#pragma unroll
+    for (uint32_t i = 0; i < kPScanBatch; ++i) {
+      if (valid && c + i < hi) col[(uint64_t)(c + i) * P] = run;
+      run += v[i];
+    }
+  }
+  if (wave == 0 && valid) a.ptot[2ull * (S.part_off + p) + side] = total;
+}
+
+// A record: the top 32 bits of h (the partition in their top pbits bits,
+// the LDS table index and fingerprint below) over the element's id.
+__device__ __forceinline__ uint64_t part_rec(uint64_t h, uint32_t id) {
+  return (h & 0xFFFFFFFF00000000ull) | id;
+}
+
+// k_pscat: per partition tile, the records of its elements in partition
+// order.  Each element takes a place among its partition's records of the
+// tile (an LDS atomic: the order inside a partition does not matter) in a
+// tile-sized LDS staging array laid out by partition; the staged records
+// then go out in order, consecutive lanes writing consecutive records, to
+// the partition's start (a scan of the side's totals) plus the tile's
+// prefix.  The first tile of each side also stores the starts for the join.
+__global__ __launch_bounds__(kPThreads) void k_pscat(StepArgs a) {
+  constexpr uint32_t kPer = (1u << kMaxPartLog2) / kPThreads;  // partitions per thread
+  __shared__ uint64_t s_el[kPTile];
+  __shared__ uint32_t s_base[1u << kMaxPartLog2];  // global slot of the tile's first
+  __shared__ uint32_t s_loc[(1u << kMaxPartLog2) + 1];  // staging offsets, then cursors
+  __shared__ uint32_t s_tmp[kPWaves];
+  __shared__ uint32_t s_seg;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const uint32_t blk = ptile_block(blockIdx.x);
+  if (tid == 0) s_seg = seg_of_block<&SegDesc::ptile_off>(a, blk);
+  __syncthreads();
+  if (*a.err & kErrFatal) return;
+  const SegDesc S = seg_desc(a, uniform(s_seg));
+  const uint32_t P = 1u << S.pbits, t = blk - S.ptile_off;
+  const uint32_t side = t < S.netile ? 0u : 1u;
+  const bool first = t == 0 || t == S.netile;
+  const bool last = t + 1 == S.netile || t + 1 == S.netile + S.nqtile;
+  // thread tid holds partitions [kPer tid, kPer tid + kPer): their starts
+  // (scan of the totals), the tile's prefix and its own count (the next
+  // tile's prefix, or the total, minus this one's)
+  const uint32_t* tot = a.ptot + 2ull * S.part_off + side;
+  const uint32_t* row = a.prow + S.prow_off + (uint64_t)t * P;
+  uint32_t v[kPer], pre[kPer], cnt[kPer], sum = 0, csum = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t p = kPer * tid + k;
+    v[k] = p < P ? tot[2ull * p] : 0u;
+    pre[k] = p < P ? row[p] : 0u;
+    const uint32_t nxt = p < P ? (last ? v[k] : row[P + p]) : 0u;
+    cnt[k] = nxt - pre[k];
+    sum += v[k];
+    csum += cnt[k];
+  }
+  uint32_t all, n;
+  uint32_t run = pblock_excl_scan(sum, s_tmp, &all);
+  uint32_t loc = pblock_excl_scan(csum, s_tmp, &n);
+  uint32_t* st = a.pstart + 2ull * S.part_off + side;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t p = kPer * tid + k;
+    if (p < P) {
+      if (first) st[2ull * p] = run;
+      s_base[p] = run + pre[k];
+      s_loc[p] = loc;
+    }
+    run += v[k];
+    loc += cnt[k];
+  }
+  if (tid == 0) s_loc[P] = n;
+  __syncthreads();
+  // staging offsets of the partitions, kept for the write-out below
+  uint32_t lo[kPer];
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) lo[k] = kPer * tid + k < P ? s_loc[kPer * tid + k] : 0u;
+  const bool agg = S.pbits <= kAggBits;
+  for_tile(a, S, t, [&](uint64_t h, uint32_t id, bool valid) {
+    const uint32_t p = part_of(h, S.pbits);
+    uint32_t slot;
+    if (agg) {
+      const uint64_t mm = match_lanes(p, valid, S.pbits);
+      const uint32_t below = __popcll(mm & ((1ull << lane) - 1ull));
+      uint32_t bse = 0;
+      if (valid && below == 0) bse = atomicAdd(&s_loc[p], (uint32_t)__popcll(mm));
+      slot = __shfl(bse, (int)(((uint32_t)__ffsll((long long)mm) - 1u) & 63u)) + below;
+    } else {
+      slot = valid ? atomicAdd(&s_loc[p], 1u) : 0u;
+    }
+    if (valid) s_el[slot] = part_rec(h, id);
+  });
+  __syncthreads();
+  // the cursors ran to the next partition's offset: restore the offsets
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k)
+    if (kPer * tid + k < P) s_loc[kPer * tid + k] = lo[k];
+  __syncthreads();
+  uint64_t* out = side ? a.qrec + S.gest_off : a.erec + S.arc_off / 2;
+  for (uint32_t i = tid; i < n; i += kPThreads) {
+    const uint64_t rec = s_el[i];
+    const uint32_t p = part_of(rec, S.pbits);
+    out[s_base[p] + (i - s_loc[p])] = rec;
+  }
+}
+
+// k_pjoin: block (p, slice): the waiting estimators of partition p (in
+// rounds of kJoinQ) in an LDS open-addressing table of their records,
+// indexed by the low bits of the record's high word, and the slice's edges
+// probed against it, kJoinRound loads in flight per thread.  A record whose
+// high word equals the edge's closes its estimator iff the edge is the
+// estimator's closing edge and comes at or after its limit.  Also resets
+// the per-segment work area (the step's last kernel).
+constexpr int kJoinThreads = 512;
+constexpr uint32_t kJoinRound = 8;
+constexpr uint64_t kFreeRec = ~0ull;  // no record: ids stay below 2^31
+
+__global__ __launch_bounds__(kJoinThreads) void k_pjoin(StepArgs a) {
+  __shared__ uint64_t s_tab[kJoinSlots];
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
-  const uint32_t gtile = blockIdx.x;
-  if (tid == 0) s_seg = seg_of_tile(a, gtile);
+  if (tid == 0) s_seg = seg_of_block<&SegDesc::jblk_off>(a, blockIdx.x);
   __syncthreads();
-  const uint32_t sidx = uniform(s_seg);
-  const SegDesc S = seg_desc(a, sidx);
+  const SegDesc S = seg_desc(a, uniform(s_seg));
   if ((*a.err & kErrFatal) == 0) {
-    const uint32_t ebase = (gtile - S.tile_off) * (kTile / 2);
+    const uint32_t b = blockIdx.x - S.jblk_off, p = b / S.jslices, sl = b % S.jslices;
+    const uint64_t g2 = 2ull * (S.part_off + p);
+    const uint32_t qs = a.pstart[g2 + 1], qc = a.ptot[g2 + 1];
+    const uint32_t es = a.pstart[g2], ec = a.ptot[g2];
+    const uint32_t e_lo = es + (uint32_t)((uint64_t)ec * sl / S.jslices);
+    const uint32_t e_hi = es + (uint32_t)((uint64_t)ec * (sl + 1) / S.jslices);
+    const uint64_t* qrec = a.qrec + S.gest_off;
+    const uint64_t* erec = a.erec + S.arc_off / 2;
     const uint2* W = reinterpret_cast<const uint2*>(S.edges);
-    const uint32_t mask = (1u << S.qt_log2) - 1u;
-    const uint8_t* fp = a.qfp + S.qt_off;
-    const uint32_t* qt = a.qt + S.qt_off;
-    // occupancy bitmap, for a segment with a table too large for L2
-    // (qt_off: a multiple of 1024)
-    const uint32_t* qb =
-        a.qbits && S.qt_log2 > kBitmapMinLog2 ? a.qbits + S.qt_off / 32 : nullptr;
-    constexpr uint64_t k01 = 0x0101010101010101ull, k80 = 0x8080808080808080ull;
-    for (int k = 0; k < kProbeEdges; ++k) {
-      const uint32_t j = ebase + k * kBlock + tid;
-      if (j >= S.w) break;
-      const uint2 ed = W[j];
-      const uint64_t q = canon(ed.x, ed.y);
-      const uint64_t hq = mix64(q);
-      const uint64_t fx = k01 * q_fp(hq);
-      // the fingerprints (one byte per slot) rule out nearly every other
-      // edge; they are read eight at a time (aligned words):
-      // the scan ends at the first free slot (zero byte), and a byte equal
-      // to the edge's fingerprint before it is checked against the edge
-      // its owner waits for
-      uint32_t sl = q_home(hq, mask);
-      // a free home slot (most edges) ends the probe at the bitmap
-      if (qb && ((qb[sl >> 5] >> (sl & 31u)) & 1u) == 0u) continue;
-      for (uint32_t probe = 0; probe <= mask + 8; probe += 8) {
-        const uint32_t b8 = sl & ~7u;
-        const uint64_t wd = *reinterpret_cast<const uint64_t*>(fp + b8);
-        const uint64_t ign = (k01 << (8u * (sl & 7u))) ^ k01;  // 0x01 below sl
-        const uint64_t v = wd | ign;
-        const uint64_t z = (v - k01) & ~v & k80;  // lowest bit: first free slot
-        const uint64_t x = (wd ^ fx) | ign;
-        uint64_t mt = (x - k01) & ~x & k80;       // matches (extra bits are
-        if (z) mt &= (z & (~z + 1)) - 1;          // only ever rechecked)
-        while (mt) {
-          const uint32_t at = b8 + ((uint32_t)__ffsll((long long)mt) - 1u) / 8u;
-          const uint32_t own = qt[at];
-          if (a.qq[own] == q && j >= a.qthr[own]) atomicOr(&a.cc[own], kClosed);
-          mt &= mt - 1;
+    constexpr uint32_t kMask = kJoinSlots - 1;
+    for (uint32_t r0 = 0; e_hi > e_lo && r0 < qc; r0 += kJoinQ) {
+      const uint32_t nq = min(kJoinQ, qc - r0);
+      for (uint32_t i = tid; i < kJoinSlots; i += kJoinThreads) s_tab[i] = kFreeRec;
+      __syncthreads();
+      for (uint32_t i0 = 0; i0 < nq; i0 += kJoinRound * kJoinThreads) {
+        uint64_t rec[kJoinRound];
+#pragma unroll
+        for (uint32_t k = 0; k < kJoinRound; ++k)
+          rec[k] = qrec[qs + r0 + min(i0 + k * kJoinThreads + tid, nq - 1)];
+#pragma unroll
+        for (uint32_t k = 0; k < kJoinRound; ++k) {
+          if (i0 + k * kJoinThreads + tid >= nq) continue;
+          uint32_t slot = (uint32_t)(rec[k] >> 32) & kMask;
+          while (atomicCAS(reinterpret_cast<unsigned long long*>(&s_tab[slot]),
+                           (unsigned long long)kFreeRec,
+                           (unsigned long long)rec[k]) != kFreeRec)
+            slot = (slot + 1) & kMask;
         }
-        if (z) break;
-        sl = (b8 + 8) & mask;
       }
+      __syncthreads();
+      for (uint32_t j0 = e_lo; j0 < e_hi; j0 += kJoinRound * kJoinThreads) {
+        uint64_t er[kJoinRound];
+#pragma unroll
+        for (uint32_t k = 0; k < kJoinRound; ++k)
+          er[k] = erec[min(j0 + k * kJoinThreads + tid, e_hi - 1)];
+#pragma unroll
+        for (uint32_t k = 0; k < kJoinRound; ++k) {
+          if (j0 + k * kJoinThreads + tid >= e_hi) continue;
+          const uint32_t f = (uint32_t)(er[k] >> 32), pos = (uint32_t)er[k];
+          for (uint32_t slot = f & kMask;; slot = (slot + 1) & kMask) {
+            const uint64_t qr = s_tab[slot];
+            if (qr == kFreeRec) break;
+            if ((uint32_t)(qr >> 32) != f) continue;
+            const uint32_t e = (uint32_t)qr;
+            const uint2 ed = W[pos];
+            if (canon(ed.x, ed.y) == a.qq[e] && pos >= a.qthr[e])
+              atomicOr(&a.cc[e], kClosed);
+          }
+        }
+      }
+      __syncthreads();
     }
   }
   // this step no longer needs the per-segment work area: reset it
   const uint32_t words = a.nseg * (uint32_t)(sizeof(SegWork) / 4);
   uint32_t* wz = reinterpret_cast<uint32_t*>(a.work);
-  for (uint32_t t = gtile * kBlock + tid; t < words; t += a.ntiles * kBlock)
+  for (uint32_t t = blockIdx.x * kJoinThreads + tid; t < words; t += a.njblk * kJoinThreads)
     wz[t] = 0;
 }
 
@@ -1499,7 +1727,7 @@ __global__ __launch_bounds__(kBlock) void k_fill32(uint32_t* p, uint64_t n,
 // host-side launchers
 // ---------------------------------------------------------------------------
 // The step runs in three phases (see the engine): A groups the batch
-// (k_hist .. k_dir), B is k_est, C is Step 3 (k_post, k_probe) and may run
+// (k_hist .. k_dir), B is k_est, C is Step 3 (k_pcnt .. k_pjoin) and may run
 // on another stream, overlapping the next step's phase A.  ev: optional
 // 2 * kNumKernels events; kernel k is bracketed by ev[2k] and ev[2k+1]
 // when those are non-null (untimed kernels get no event).
@@ -1554,15 +1782,15 @@ hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st,
     } else {
       launch_sort<8>(a, st, run);
     }
-    run(kNumKernels - 5, [&] { hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a); });
+    run(kNumKernels - 6, [&] { hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a); });
   } else if (phase == 1) {
-    run(kNumKernels - 4, [&] { hipLaunchKernelGGL(k_est, ests, blk, 0, st, a); });
+    run(kNumKernels - 5, [&] { hipLaunchKernelGGL(k_est, ests, blk, 0, st, a); });
   } else {
-    const dim3 qwords((uint32_t)((a.qt_slots / 32 + kBlock - 1) / kBlock));
-    run(kNumKernels - 3, [&] { hipLaunchKernelGGL(k_post, ests, blk, 0, st, a); });
-    if (a.qbits)
-      run(kNumKernels - 2, [&] { hipLaunchKernelGGL(k_qbits, qwords, blk, 0, st, a); });
-    run(kNumKernels - 1, [&] { hipLaunchKernelGGL(k_probe, tiles, blk, 0, st, a); });
+    const dim3 pblk(kPThreads), jblk(kJoinThreads);
+    run(kNumKernels - 4, [&] { hipLaunchKernelGGL(k_pcnt, dim3(a.nptile), pblk, 0, st, a); });
+    run(kNumKernels - 3, [&] { hipLaunchKernelGGL(k_pscan, dim3(a.npscan), pblk, 0, st, a); });
+    run(kNumKernels - 2, [&] { hipLaunchKernelGGL(k_pscat, dim3(a.nptile), pblk, 0, st, a); });
+    run(kNumKernels - 1, [&] { hipLaunchKernelGGL(k_pjoin, dim3(a.njblk), jblk, 0, st, a); });
   }
   return hipGetLastError();
 }

@@ -94,5 +94,5 @@ def test_profile_names_map_to_launch_names():
     assert short("void tc::k_hist<10>(tc::StepArgs)") == "k_hist"
     assert short("void tc::k_fold_step1<8>(tc::StepArgs)") == "k_fold_step1"
     assert short("void tc::k_cscan<2, 8>(tc::StepArgs)") == "k_cscan<2>"
-    assert short("tc::k_qbits(tc::StepArgs)") == "k_qbits"
+    assert short("tc::k_pjoin(tc::StepArgs)") == "k_pjoin"
     assert short("tc::k_est(tc::StepArgs)") == "k_est"

@@ -448,10 +448,10 @@ def test_graph_replay_single_bank(tc):
         _ = torch.ones(1000, device="cuda").sum().item()
 
 
-def test_graph_replay_wide_digits_and_bitmap(tc):
+def test_graph_replay_wide_digits_many_partitions(tc):
     # the captured step runs both 10-bit passes with their chunk scans
-    # (100 000-edge batches: two radix chunks) and probes through the
-    # occupancy bitmap (r = 2^20 + 1: 2^23 query slots)
+    # (100 000-edge batches: two radix chunks) and a Step-3 join over 1024
+    # partitions (r = 2^20 + 1)
     r, seed, w = (1 << 20) + 1, 41, 100000
     E = _spread_ids(np_edges(inputs.rmat(16, 300000, seed=16)), 1 << 20, 16)
     dev = to_dev(E)
@@ -928,10 +928,10 @@ def test_wide_digit_bound_violation(tc, bound, bad_id):
     assert ei.value.code == tc.TC_EINVAL
 
 
-# -- query tables above 2^22 slots: probes start at the occupancy bitmap ----------
+# -- large banks: the Step-3 join over many partitions ------------------------------
 
-def test_query_bitmap_one_bank(tc):
-    # r = 2^20 + 1: 4r rounds up to 2^23 slots
+def test_join_large_bank(tc):
+    # r = 2^20 + 1: 1024 partitions of the waiting estimators
     E = np_edges(inputs.rmat(16, 300000, seed=12))
     r, w = (1 << 20) + 1, 100000
     g = tc.Bank(r, 8)
@@ -941,9 +941,9 @@ def test_query_bitmap_one_bank(tc):
     assert tc.tc_estimate_ex(g.h)[0] == o.sum()
 
 
-def test_query_bitmap_batched(tc):
-    # the second bank's table (2^23 slots, at a nonzero offset) is probed
-    # through the bitmap, the others' (2^20 and less) byte by byte
+def test_join_large_bank_batched(tc):
+    # banks with 1 to 1024 partitions in one step, the largest at a nonzero
+    # partition offset
     rs, seeds, w = [1 << 18, (1 << 20) + 1, 5000, 1 << 18, 1], [21, 22, 23, 24, 25], 30000
     Es = [np_edges(inputs.gnm(3000 + 500 * b, 90000, seed=70 + b)) for b in range(5)]
     mb = tc.MultiBank(rs, seeds)
@@ -953,13 +953,46 @@ def test_query_bitmap_batched(tc):
         assert_same(mb.state(b), O.run_stream(Es[b], rs[b], seeds[b], w).state(), f"bank {b}")
 
 
+# -- Step 3's partitioned join: crowded partitions, slices, few partitions ---------
+
+def _two_hubs(n: int, seed: int) -> np.ndarray:
+    """K_{2,n}: hubs 0 and 1 joined to leaves 2..n+1 in seeded order, then the
+    edge between the hubs: every wedge leaf-centred between the hubs waits
+    for that one closing edge."""
+    rng = np.random.default_rng(seed)
+    leaves = np.arange(2, n + 2, dtype=np.uint32)
+    E = np.concatenate([np.stack([np.zeros(n, np.uint32), leaves], 1),
+                        np.stack([np.ones(n, np.uint32), leaves], 1)])
+    E = E[rng.permutation(len(E))]
+    return np.concatenate([E, np.array([[1, 0]], np.uint32)])
+
+
+@pytest.mark.parametrize("n,r,w", [(6000, 40000, 4001), (3000, 9000, 100000), (500, 3, 77)])
+def test_join_many_estimators_wait_for_one_edge(tc, n, r, w):
+    # thousands of estimators wait for the same closing edge: one partition
+    # holds more than a round of the join's LDS table
+    E = _two_hubs(n, seed=n)
+    g, o = run_both(tc, E, r, seed=n + r, w=w)
+    closed = o.state()[3]
+    say(f"  closed estimators: {int(closed.sum())}")
+
+
+def test_join_slices_and_partition_counts(tc):
+    # few estimators against large batches (several join slices per
+    # partition, one or two partitions), then many estimators against a
+    # small batch (many partitions, most slices without edges)
+    E = np_edges(inputs.rmat(15, 400000, seed=44))
+    for r, w in ((1, 200000), (2049, 150000), (4097, 33333), (300000, 5000)):
+        run_both(tc, E[:min(len(E), 2 * w + 17)], r, seed=r, w=w, every=False)
+
+
 # -- random mixes of digit widths, chunk counts and table sizes -------------------
 
 def _mix_case(k):
     """A seeded configuration drawn over the choices the step makes by
     itself: 8- or 10-bit digits (bounds of 17 to 20 bits with ids spread
-    over them), one or several radix chunks, query tables above or below
-    2^22 slots (r > 2^20), dense or hashed directory."""
+    over them), one or several radix chunks, one to 1024 Step-3 partitions
+    (r above 2^20 now and then), dense or hashed directory."""
     rng = np.random.default_rng(9000 + k)
     fam = int(rng.integers(0, 3))
     m = int(rng.integers(1000, 250000))
