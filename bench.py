@@ -150,10 +150,14 @@ def batched_comparison(tc, inputs, nstreams=256, ks=(1, 2, 4, 8, 16), replays=3)
     """Plain (one bank per stream, one launch set per chunk) against batched
     (every stream's chunk in one launch set per step) and graph replay of the
     batched steps, on independent streams of uneven length.  Each stream is
-    cut into K batches (w_s = ceil(m_s / K)); K is tuned over `ks` on the
-    batched form.  Returns a dict for the JSON line."""
+    cut into K batches (w_s = ceil(m_s / K)).  At every K the launch shapes
+    of the batched steps are tuned (paper_1308_2166_amd.tune: coordinate
+    descent, cached by architecture, w and r buckets and key bits) and the
+    plain form is timed too; the K with the best batched rate is the
+    reported one.  Returns a dict for the JSON line."""
     import numpy as np
     import torch
+    from paper_1308_2166_amd import tune
     log(f"[bench] generating {nstreams} independent streams on the GPU")
     streams = inputs.many_streams(nstreams, device="cuda")
     rs = [s["r"] for s in streams]
@@ -176,6 +180,7 @@ def batched_comparison(tc, inputs, nstreams=256, ks=(1, 2, 4, 8, 16), replays=3)
         return steps
 
     nv = max(st["n"] for st in streams)  # every stream's ids lie below this
+    key_bits = (nv - 1).bit_length()
     mb = tc.MultiBank(rs, seeds)
     tc.tc_multi_set_vertex_bound(mb.h, nv)
 
@@ -184,20 +189,58 @@ def batched_comparison(tc, inputs, nstreams=256, ks=(1, 2, 4, 8, 16), replays=3)
         for ids, chunks in steps:
             mb.process(ids, chunks, stream)
 
-    tune = {}
+    def time_plain(steps, K, reps=1):
+        banks = []
+        for b in range(nstreams):
+            bk = tc.Bank(rs[b], seeds[b])
+            tc.tc_set_vertex_bound(bk.h, streams[b]["n"])
+            tc.tc_reserve(bk.h, (ms[b] + K - 1) // K)
+            banks.append(bk)
+
+        def run_plain():
+            for bk in banks:
+                tc.tc_reset(bk.h, stream)
+            for ids, chunks in steps:
+                for b, c in zip(ids, chunks):
+                    banks[b].process(c, stream)
+
+        run_plain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run_plain()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        return dt, banks
+
+    per_k, cache = {}, {}
+    arch = tune.arch()
     for K in ks:
         steps = plan(K)
         tc.tc_multi_reserve(mb.h, steps[0][0], [c.shape[0] for c in steps[0][1]])
-        run_batched(steps)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run_batched(steps)
-        torch.cuda.synchronize()
-        tune[K] = rm_total / (time.perf_counter() - t0)
-        log(f"[bench]   K={K}: batched {tune[K]:.3e} r*m/s")
-    K = max(tune, key=tune.get)
+        nchunk = sum(len(ids) for ids, _ in steps)
+        k_ = tune.key(arch, sum(ms) / nchunk, sum(rs) / nstreams, key_bits)
+        best, t_b, trials = tune.tune(lambda: run_batched(steps),
+                                      lambda cfg: tc.tc_multi_set_tuning(mb.h, cfg), repeats=1)
+        default = trials[json.dumps(dict(tc.DEFAULT_TUNING), sort_keys=True)]
+        t_p, banks = time_plain(steps, K)
+        for bk in banks:
+            bk.close()
+        per_k[str(K)] = {"batched_value": rm_total / t_b, "plain_value": rm_total / t_p,
+                         "batched_vs_plain": t_p / t_b, "batched_default_shapes_value":
+                         rm_total / default, "tuning": best, "key": k_,
+                         "configs_timed": len(trials)}
+        cache[k_] = {"tuning": best, "ms_per_step": t_b * 1e3 / K}
+        log(f"[bench]   K={K}: batched {rm_total / t_b:.3e} (default shapes "
+            f"{rm_total / default:.3e}), plain {rm_total / t_p:.3e} r*m/s, tuning {best}")
+    try:
+        cache_path = tune.save(cache)
+    except OSError:
+        cache_path = None
+    K = int(max(per_k, key=lambda k_: per_k[k_]["batched_value"]))
     steps = plan(K)
     tc.tc_multi_reserve(mb.h, steps[0][0], [c.shape[0] for c in steps[0][1]])
+    tc.tc_multi_set_tuning(mb.h, per_k[str(K)]["tuning"])
 
     # batched (eager launches)
     run_batched(steps)
@@ -228,28 +271,8 @@ def batched_comparison(tc, inputs, nstreams=256, ks=(1, 2, 4, 8, 16), replays=3)
     graph_same = all(all(np.array_equal(x, y) for x, y in zip(mb.state(b), st_batched[b]))
                      for b in range(nstreams))
 
-    # plain: one bank per stream, one launch set per chunk
-    banks = []
-    for b in range(nstreams):
-        bk = tc.Bank(rs[b], seeds[b])
-        tc.tc_set_vertex_bound(bk.h, streams[b]["n"])
-        tc.tc_reserve(bk.h, (ms[b] + K - 1) // K)
-        banks.append(bk)
-
-    def run_plain():
-        for bk in banks:
-            tc.tc_reset(bk.h, stream)
-        for ids, chunks in steps:
-            for b, c in zip(ids, chunks):
-                banks[b].process(c, stream)
-
-    run_plain()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(replays):
-        run_plain()
-    torch.cuda.synchronize()
-    t_plain = (time.perf_counter() - t0) / replays
+    # plain at the chosen K (default shapes): same states
+    t_plain, banks = time_plain(steps, K, reps=replays)
     plain_same = all(all(np.array_equal(x, y) for x, y in zip(banks[b].state(), st_batched[b]))
                      for b in range(nstreams))
     for bk in banks:
@@ -260,7 +283,7 @@ def batched_comparison(tc, inputs, nstreams=256, ks=(1, 2, 4, 8, 16), replays=3)
                     "(median 3e5), even R-MAT scale 16-22, odd Chung-Lu n=m/8 "
                     "gamma=2.1, r=2^14..2^18 per stream",
         "total_edges": int(sum(ms)), "total_estimators": int(sum(rs)),
-        "batches_per_stream": K, "tuned": {str(k): v for k, v in tune.items()},
+        "batches_per_stream": K, "per_k": per_k, "tuning_cache": cache_path,
         "plain_value": rm_total / t_plain, "batched_value": rm_total / t_batched,
         "graph_value": rm_total / t_graph, "unit": "estimator-edge updates/s",
         "batched_vs_plain": t_plain / t_batched, "graph_vs_plain": t_plain / t_graph,

@@ -144,6 +144,32 @@ int tc_process_host_stream(tc_state *s, const uint32_t *host_edges,
  * TC_EINVAL for n out of range. */
 int tc_set_vertex_bound(tc_state *s, uint64_t n);
 
+/* ---- launch shapes (batched-form tuning) ---------------------------------
+ * Shapes of the step's kernels that a tuner may choose; none of them
+ * changes any result (the state stays bit-identical, as the tests check).
+ *   digit_bits      0: radix digits from the declared vertex bound (two
+ *                   passes of 10-bit digits for bounds of 17 to 20 bits,
+ *                   else 8-bit digits; the default); 8: always 8-bit
+ *   chunk_tiles     radix tiles (of 4096 arcs) per chunk of the reduce-then-
+ *                   scan: 8, 16 or 32 (default 32)
+ *   part_estimators Step-3 join: waiting estimators per hash partition aimed
+ *                   at, a power of two in [512, 8192] (default 2048; at
+ *                   most 2048 partitions per bank)
+ *   join_edges      Step-3 join: batch edges per join block aimed at, a
+ *                   power of two in [1024, 65536] (default 8192)
+ * Applies to steps enqueued afterwards; TC_EINVAL for values out of range.
+ * tc_step_bytes_max and tc_multi_reserve_max hold for every tuning. */
+typedef struct tc_tuning {
+  uint32_t digit_bits;
+  uint32_t chunk_tiles;
+  uint32_t part_estimators;
+  uint32_t join_edges;
+} tc_tuning;
+int tc_set_tuning(tc_state *s, const tc_tuning *t);
+int tc_get_tuning(const tc_state *s, tc_tuning *t);
+int tc_multi_set_tuning(tc_multi *s, const tc_tuning *t);
+int tc_multi_get_tuning(const tc_multi *s, tc_tuning *t);
+
 /* Pre-size the bank's step scratch for batches of up to max_w edges so that
  * later tc_process_batch calls with w <= max_w allocate nothing (needed
  * before capturing them into a HIP graph: a captured step that needs more

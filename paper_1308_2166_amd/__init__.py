@@ -36,6 +36,16 @@ class TcError(RuntimeError):
         self.code = code
 
 
+class TcTuning(ctypes.Structure):
+    """tc_tuning: launch shapes that do not change results."""
+    _fields_ = [("digit_bits", ctypes.c_uint32), ("chunk_tiles", ctypes.c_uint32),
+                ("part_estimators", ctypes.c_uint32), ("join_edges", ctypes.c_uint32)]
+
+
+TUNING_FIELDS = tuple(f for f, _ in TcTuning._fields_)
+DEFAULT_TUNING = {"digit_bits": 0, "chunk_tiles": 32, "part_estimators": 2048,
+                  "join_edges": 8192}
+
 _lib = None
 
 
@@ -61,6 +71,10 @@ def lib():
         "tc_process_stream": ([vp, vp, u64, u32, vp], i32),
         "tc_process_host_stream": ([vp, vp, u64, u32, vp], i32),
         "tc_bank_bytes": ([u32], u64),
+        "tc_set_tuning": ([vp, ctypes.POINTER(TcTuning)], i32),
+        "tc_get_tuning": ([vp, ctypes.POINTER(TcTuning)], i32),
+        "tc_multi_set_tuning": ([vp, ctypes.POINTER(TcTuning)], i32),
+        "tc_multi_get_tuning": ([vp, ctypes.POINTER(TcTuning)], i32),
         "tc_step_bytes_max": ([u32, u32, u64], u64),
         "tc_multi_reserve_max": ([vp, u32, u64], i32),
         "tc_step_bytes": ([u32, vp, vp], u64),
@@ -124,7 +138,8 @@ EXPORTS = ("tc_create", "tc_process_batch", "tc_process_stream", "tc_estimate", 
            "tc_estimators_needed", "tc_process_batch_naive", "tc_parse_edges",
            "tc_process_batch_noalloc", "tc_process_host_stream", "tc_bank_bytes",
            "tc_step_bytes", "tc_device_bytes", "tc_multi_device_bytes",
-           "tc_step_bytes_max", "tc_multi_reserve_max")
+           "tc_step_bytes_max", "tc_multi_reserve_max", "tc_set_tuning", "tc_get_tuning",
+           "tc_multi_set_tuning", "tc_multi_get_tuning")
 
 
 def _check(rc: int):
@@ -230,6 +245,36 @@ def tc_process_host_stream(state: int, host_edges, w: int, stream=None) -> None:
         ptr, m = a.ctypes.data, a.shape[0]
     _check(lib().tc_process_host_stream(state, (ptr if m else None), m, w,
                                         _stream_handle(stream)))
+
+
+def _tuning(t: dict) -> TcTuning:
+    unknown = set(t) - set(TUNING_FIELDS)
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    full = dict(DEFAULT_TUNING)
+    full.update(t)
+    return TcTuning(*(int(full[f]) for f in TUNING_FIELDS))
+
+
+def tc_set_tuning(state: int, tuning: dict) -> None:
+    """Set launch shapes (fields of tc_tuning; missing ones take defaults)."""
+    _check(lib().tc_set_tuning(state, ctypes.byref(_tuning(tuning))))
+
+
+def tc_get_tuning(state: int) -> dict:
+    t = TcTuning()
+    _check(lib().tc_get_tuning(state, ctypes.byref(t)))
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+
+def tc_multi_set_tuning(multi: int, tuning: dict) -> None:
+    _check(lib().tc_multi_set_tuning(multi, ctypes.byref(_tuning(tuning))))
+
+
+def tc_multi_get_tuning(multi: int) -> dict:
+    t = TcTuning()
+    _check(lib().tc_multi_get_tuning(multi, ctypes.byref(t)))
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
 
 
 def tc_bank_bytes(r: int) -> int:

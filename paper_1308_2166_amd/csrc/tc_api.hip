@@ -66,22 +66,32 @@ uint32_t log2_ceil(uint64_t x) {
 uint32_t dir_log2_for(uint32_t w) {
   return std::max<uint32_t>(10, log2_ceil(4ull * w));
 }
-// Step-3 join of a bank of r estimators: partitions of about kPartQ
+// Launch shapes a caller may tune (tc_set_tuning); none changes a result.
+struct Tuning {
+  uint32_t digits8 = 0;           // 1: 8-bit radix digits whatever the bound
+  uint32_t chunk_log2 = 5;        // radix tiles per chunk of the scans: 8..kChunk
+  uint32_t part_q = kPartQ;       // Step-3 estimators per partition aimed at
+  uint32_t join_edges = kJoinEdges;  // Step-3 batch edges per join slice aimed at
+};
+constexpr uint32_t kMinChunkLog2 = 3;
+constexpr uint32_t kMinPartQ = 512;
+
+// Step-3 join of a bank of r estimators: partitions of about part_q
 // waiting estimators each (at most 2^kMaxPartLog2), tiles of kPTile
-// elements, and join slices of about kJoinEdges batch edges
-uint32_t part_log2_for(uint32_t r) {
-  return std::min<uint32_t>(kMaxPartLog2, log2_ceil((r + kPartQ - 1) / kPartQ));
+// elements, and join slices of about join_edges batch edges
+uint32_t part_log2_for(uint32_t r, uint32_t part_q = kPartQ) {
+  return std::min<uint32_t>(kMaxPartLog2, log2_ceil((r + part_q - 1) / part_q));
 }
 uint32_t ptiles_for(uint64_t n) { return (uint32_t)((n + kPTile - 1) / kPTile); }
-uint32_t jslices_for(uint32_t w, uint32_t pbits) {
-  const uint64_t per = (uint64_t)kJoinEdges << pbits;
+uint32_t jslices_for(uint32_t w, uint32_t pbits, uint32_t join_edges = kJoinEdges) {
+  const uint64_t per = (uint64_t)join_edges << pbits;
   return (uint32_t)std::max<uint64_t>(1, (w + per - 1) / per);
 }
 
 // Scratch a step needs for one more chunk of w > 0 edges of a bank of r
 // estimators (the per-segment regions plan() hands out, in the same order).
 struct Sizes;
-void add_chunk(Sizes& z, uint32_t r, uint32_t w);
+void add_chunk(Sizes& z, uint32_t r, uint32_t w, uint32_t part_q = kPartQ);
 
 template <class T>
 hipError_t dalloc(T** p, uint64_t n) {
@@ -142,14 +152,14 @@ struct Sizes {
   }
 };
 
-void add_chunk(Sizes& z, uint32_t r, uint32_t w) {
+void add_chunk(Sizes& z, uint32_t r, uint32_t w, uint32_t part_q) {
   const uint32_t dl = dir_log2_for(w);
   z.need += (w + 15) / 16 * 16;
   z.arcs += 2ull * w;
   z.tiles += (2ull * w + kTile - 1) / kTile;
   z.dir += 1ull << dl;
   z.doff += (1ull << dl) + kDoffPad;
-  const uint32_t pb = part_log2_for(r);
+  const uint32_t pb = part_log2_for(r, part_q);
   z.prow += (uint64_t)(ptiles_for(w) + ptiles_for(r)) << pb;
   z.parts += 1ull << pb;
   z.nest += r;
@@ -157,8 +167,9 @@ void add_chunk(Sizes& z, uint32_t r, uint32_t w) {
 }
 
 // Sizes that hold every step of at most n chunks (banks of at most r_max
-// estimators) with at most E edges in all: per field, the largest total
-// add_chunk can reach (2^ceil(log2 x) < 2x bounds the rounded regions).
+// estimators) with at most E edges in all, under any tuning: per field, the
+// largest total add_chunk can reach (2^ceil(log2 x) < 2x bounds the rounded
+// regions; the most partitions come with the fewest estimators per one).
 Sizes step_bound(uint32_t n, uint32_t r_max, uint64_t E) {
   Sizes z;
   if (n == 0 || E == 0) return z;
@@ -166,7 +177,7 @@ Sizes step_bound(uint32_t n, uint32_t r_max, uint64_t E) {
   z.tiles = 2 * E / kTile + n;
   z.dir = 8 * E + 1024ull * n;
   z.doff = z.dir + (uint64_t)kDoffPad * n;
-  const uint32_t pb = part_log2_for(r_max);  // grows with r
+  const uint32_t pb = part_log2_for(r_max, kMinPartQ);  // grows with r
   z.prow = (E / kPTile + n + (uint64_t)n * ptiles_for(r_max)) << pb;
   z.parts = (uint64_t)n << pb;
   z.need = E + 16ull * n;
@@ -233,7 +244,8 @@ uint64_t carve(uint8_t* base, const Sizes& z, int nparity, bool stat, Scratch* o
     take(s.j1, z.nest), take(s.qq, z.nest), take(s.qthr, z.nest);
   }
   take(s.arcs[0], z.arcs), take(s.arcs[1], z.arcs);
-  take(s.csum, ((z.tiles + kChunk - 1) / kChunk + z.segs) * kRowWords);
+  // (chunks of at least 2^kMinChunkLog2 tiles, plus one ragged per segment)
+  take(s.csum, ((z.tiles >> kMinChunkLog2) + z.segs) * kRowWords);
   if (!stat) take(s.dir, z.dir);
   take(s.doff, z.doff);
   take(s.need, z.need), take(s.inv, z.arcs);
@@ -344,6 +356,7 @@ struct Engine {
   std::vector<SegDesc*> graph_stage;
   size_t graph_next = 0;
   int sticky = TC_OK;
+  Tuning tune;
   uint32_t id_limit = 0xFFFFFFFFu;  // declared vertex bound - 1
   uint32_t npass = kPasses;
   uint32_t dbits = 8;  // radix digit width for that bound
@@ -590,12 +603,12 @@ struct Engine {
       d.nhblk = (d.ntiles + kHistTiles - 1) / kHistTiles;
       pl.hblks += d.nhblk;
       d.chunk_off = (uint32_t)pl.chunks;
-      d.nchunks = (d.ntiles + kChunk - 1) / kChunk;
+      d.nchunks = (d.ntiles + (1u << tune.chunk_log2) - 1) >> tune.chunk_log2;
       pl.chunks += d.nchunks;
       d.dir_log2 = dir_log2_for(w[k]);
       d.need_off = (uint32_t)z.need;
       d.prow_off = z.prow;
-      d.pbits = part_log2_for(r[b]);
+      d.pbits = part_log2_for(r[b], tune.part_q);
       d.ptile_off = (uint32_t)pl.ptiles;
       d.netile = ptiles_for(w[k]);
       d.nqtile = ptiles_for(r[b]);
@@ -603,10 +616,10 @@ struct Engine {
       d.part_off = (uint32_t)(z.parts);
       d.pscan_off = (uint32_t)pl.pscans;
       pl.pscans += 2ull * (((1ull << d.pbits) + 63) / 64);
-      d.jslices = jslices_for(w[k], d.pbits);
+      d.jslices = jslices_for(w[k], d.pbits, tune.join_edges);
       d.jblk_off = (uint32_t)pl.jblks;
       pl.jblks += (uint64_t)d.jslices << d.pbits;
-      add_chunk(z, r[b], w[k]);
+      add_chunk(z, r[b], w[k], tune.part_q);
       pl.segs.push_back(d);
       pl.bank.push_back(b);
     }
@@ -653,6 +666,7 @@ struct Engine {
     a.id_limit = id_limit;
     a.npass = npass;
     a.dbits = dbits;
+    a.chunk_log2 = tune.chunk_log2;
     a.single_chunk = dbits == 8 && pl.chunks == pl.segs.size() ? 1u : 0u;
     return a;
   }
@@ -916,9 +930,26 @@ struct Engine {
   int set_bound(uint64_t n) {
     if (n < 2 || n > (1ull << 32)) return fail(TC_EINVAL, "vertex bound must be in [2, 2^32]");
     id_limit = (uint32_t)(n - 1);
-    const uint32_t bits = 32u - (uint32_t)__builtin_clz(id_limit);
-    dbits = bits > 16 && bits <= (uint32_t)(kWidePasses * kWideBits) ? (uint32_t)kWideBits : 8u;
+    digits();
+    return TC_OK;
+  }
+
+  // digit width and passes for the declared bound (and the tuning)
+  void digits() {
+    const uint32_t bits = 32u - (uint32_t)__builtin_clz(id_limit | 1u);
+    const bool wide = !tune.digits8 && bits > 16 && bits <= (uint32_t)(kWidePasses * kWideBits);
+    dbits = wide ? (uint32_t)kWideBits : 8u;
     npass = (bits + dbits - 1) / dbits;
+  }
+
+  int set_tuning(const Tuning& t) {
+    auto pow2 = [](uint32_t x) { return x && !(x & (x - 1)); };
+    if (t.digits8 > 1 || t.chunk_log2 < kMinChunkLog2 || (1u << t.chunk_log2) > kChunk ||
+        !pow2(t.part_q) || t.part_q < kMinPartQ || t.part_q > 8192 || !pow2(t.join_edges) ||
+        t.join_edges < 1024 || t.join_edges > 65536)
+      return fail(TC_EINVAL, "tuning out of range");
+    tune = t;
+    digits();
     return TC_OK;
   }
 
@@ -1174,6 +1205,48 @@ int tc_device_bytes(const tc_state* s, uint64_t* bytes) {
 int tc_multi_device_bytes(const tc_multi* s, uint64_t* bytes) {
   if (!s || !bytes) return fail(TC_EINVAL, "null argument");
   *bytes = s->e.device_bytes();
+  return TC_OK;
+}
+
+static int set_tuning_from(Engine& e, const tc_tuning* t) {
+  if (!t) return fail(TC_EINVAL, "null tuning");
+  Tuning u;
+  if (t->digit_bits != 0 && t->digit_bits != 8) return fail(TC_EINVAL, "digit_bits must be 0 or 8");
+  u.digits8 = t->digit_bits == 8 ? 1u : 0u;
+  u.chunk_log2 = t->chunk_tiles ? (uint32_t)__builtin_ctz(t->chunk_tiles) : 0u;
+  if (t->chunk_tiles == 0 || (t->chunk_tiles & (t->chunk_tiles - 1)))
+    return fail(TC_EINVAL, "chunk_tiles must be 8, 16 or 32");
+  u.part_q = t->part_estimators;
+  u.join_edges = t->join_edges;
+  return e.set_tuning(u);
+}
+
+static void get_tuning_from(const Engine& e, tc_tuning* t) {
+  t->digit_bits = e.tune.digits8 ? 8u : 0u;
+  t->chunk_tiles = 1u << e.tune.chunk_log2;
+  t->part_estimators = e.tune.part_q;
+  t->join_edges = e.tune.join_edges;
+}
+
+int tc_set_tuning(tc_state* s, const tc_tuning* t) {
+  if (!s) return fail(TC_EINVAL, "null state");
+  return set_tuning_from(s->e, t);
+}
+
+int tc_multi_set_tuning(tc_multi* s, const tc_tuning* t) {
+  if (!s) return fail(TC_EINVAL, "null object");
+  return set_tuning_from(s->e, t);
+}
+
+int tc_get_tuning(const tc_state* s, tc_tuning* t) {
+  if (!s || !t) return fail(TC_EINVAL, "null argument");
+  get_tuning_from(s->e, t);
+  return TC_OK;
+}
+
+int tc_multi_get_tuning(const tc_multi* s, tc_tuning* t) {
+  if (!s || !t) return fail(TC_EINVAL, "null argument");
+  get_tuning_from(s->e, t);
   return TC_OK;
 }
 

@@ -31,8 +31,9 @@ static_assert(kRowWords >= kPasses << 8, "a row holds every 8-bit pass");
 constexpr int kNumKernels = 22;  // launches per step (k_hist .. k_pjoin)
 constexpr int kHistTiles = 1;   // tiles per k_hist block (one: its counts are
                                 // the per-tile counts of the first radix pass)
-constexpr uint32_t kChunk = 32;  // tiles per chunk of the radix scans (and
-                                 // k_hist rows summed per k_fold block)
+constexpr uint32_t kChunk = 32;  // most tiles per chunk of the radix scans (and
+                                 // k_hist rows summed per k_fold block); a
+                                 // step uses 2^chunk_log2 <= kChunk of them
 
 // j1[] word: kNone, or the replacement position with kSideV set when the
 // smaller endpoint u of W[j1] is its second vertex
@@ -78,7 +79,7 @@ struct SegDesc {
   uint32_t hblk_off;      // first k_hist block of the segment
   uint32_t nhblk;         // ceil(ntiles / kHistTiles)
   uint32_t chunk_off;     // first global radix chunk of the segment
-  uint32_t nchunks;       // ceil(ntiles / kChunk)
+  uint32_t nchunks;       // ceil(ntiles / 2^chunk_log2)
   uint32_t dir_log2;      // log2 of the directory region (slots)
   uint32_t need_off;      // first byte of the "position needed" bytes (w bytes)
   // Step 3 (partitioned join): the segment's edges and waiting estimators
@@ -185,6 +186,7 @@ struct StepArgs {
   uint32_t npass;         // radix passes launched: the number of D-bit
                           // digits of the bound (1..kPasses)
   uint32_t dbits;         // digit width D: 8 or kWideBits
+  uint32_t chunk_log2;    // log2 of the tiles per radix chunk (<= kChunk)
   uint32_t single_chunk;  // 1: every segment is one radix chunk and D = 8;
                           // the count sums then write each chunk's bin
                           // starts as its bases and no k_cscan runs

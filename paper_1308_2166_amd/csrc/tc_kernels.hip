@@ -391,8 +391,8 @@ __device__ void fold_chunk(const StepArgs& a, uint32_t b) {
   __syncthreads();
   const uint32_t sidx = uniform(s_seg);
   const SegDesc S = seg_desc(a, sidx);
-  const uint32_t r0 = S.hblk_off + (c - S.chunk_off) * kChunk;
-  const uint32_t r1 = min(r0 + kChunk, S.hblk_off + S.nhblk);
+  const uint32_t r0 = S.hblk_off + ((c - S.chunk_off) << a.chunk_log2);
+  const uint32_t r1 = min(r0 + (1u << a.chunk_log2), S.hblk_off + S.nhblk);
   const uint32_t d = q * kBlock + tid;
   const uint32_t tot = chunk_prefix(a.hpart, r0, r1, d);
   if (q == 0 && (uint32_t)tid < r1 - r0) atomicMax(&s_max, a.mpart[r0 + tid]);
@@ -406,7 +406,7 @@ __device__ void fold_chunk(const StepArgs& a, uint32_t b) {
 // ---------------------------------------------------------------------------
 // Radix passes.  Pass P orders the arcs stably by bits DP..DP+D-1 of the
 // vertex id (LSD), by reduce-then-scan: k_cnt<P> counts the digits of every
-// tile, k_csum<P> sums the counts of every chunk of kChunk tiles (and the
+// tile, k_csum<P> sums the counts of every chunk of tiles (and the
 // segment's digit histogram) and turns each tile's counts into the prefix
 // of its chunk's earlier tiles, k_cscan<P> turns the chunk sums into chunk
 // bases, and k_scat<P> adds its two offset rows and moves its arcs.  No
@@ -521,8 +521,8 @@ __global__ __launch_bounds__(kBlock) void k_csum(StepArgs a) {
   const SegDesc S = seg_desc(a, sidx);
   SegWork* wk = a.work + sidx;
   if (!pass_runs<D>(uniform(wk->maxid), P)) return;
-  const uint32_t t0 = S.tile_off + (c - S.chunk_off) * kChunk;
-  const uint32_t t1 = min(t0 + kChunk, S.tile_off + S.ntiles);
+  const uint32_t t0 = S.tile_off + ((c - S.chunk_off) << a.chunk_log2);
+  const uint32_t t1 = min(t0 + (1u << a.chunk_log2), S.tile_off + S.ntiles);
   const uint32_t d = q * kBlock + tid;
   const uint32_t tot = chunk_prefix(cnt_row<D>(a, 0, P), t0, t1, d);
   csum_row<D>(a, c, P)[d] = single_chunk_base<D>(a, tot);
@@ -686,7 +686,7 @@ __device__ __forceinline__ void scat_body(const StepArgs& a) {
   // chunk's base for the digit (bin start + the segment's earlier chunks)
   // + the chunk's earlier tiles (both loads overlap the ranking below)
   uint32_t off[kPer], pre_t[kPer];
-  ld_bins(csum_row<D>(a, S.chunk_off + ltile / kChunk, P), off);
+  ld_bins(csum_row<D>(a, S.chunk_off + (ltile >> a.chunk_log2), P), off);
   ld_bins(cnt_row<D>(a, S.tile_off + ltile, P), pre_t);
 #pragma unroll
   for (int j = 0; j < kPer; ++j) off[j] += pre_t[j];

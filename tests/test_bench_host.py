@@ -96,3 +96,22 @@ def test_profile_names_map_to_launch_names():
     assert short("void tc::k_cscan<2, 8>(tc::StepArgs)") == "k_cscan<2>"
     assert short("tc::k_pjoin(tc::StepArgs)") == "k_pjoin"
     assert short("tc::k_est(tc::StepArgs)") == "k_est"
+
+
+def test_tuning_cache_round_trip(tmp_path):
+    # the tuner's JSON cache: keys by architecture, w and r buckets and key
+    # bits; entries merge; a malformed entry is not returned (no GPU)
+    from paper_1308_2166_amd import tune
+    import paper_1308_2166_amd as tc
+    k = tune.key("gfx950", 3 * 2**18, 2**16 + 5, 22)
+    assert k == "gfx950|w2^19|r2^16|b22"
+    path = str(tmp_path / "t.json")
+    assert tune.lookup(k, path) is None
+    cfg = dict(tc.DEFAULT_TUNING, chunk_tiles=16)
+    tune.save({k: {"tuning": cfg, "ms_per_step": 1.0}}, path)
+    tune.save({"other": {"tuning": {"chunk_tiles": 8}}}, path)
+    assert tune.lookup(k, path) == cfg
+    assert tune.lookup("other", path) is None
+    assert set(tune.CANDIDATES) == set(tc.TUNING_FIELDS)
+    for f, vals in tune.CANDIDATES.items():
+        assert tc.DEFAULT_TUNING[f] in vals

@@ -986,6 +986,65 @@ def test_join_slices_and_partition_counts(tc):
         run_both(tc, E[:min(len(E), 2 * w + 17)], r, seed=r, w=w, every=False)
 
 
+# -- launch shapes (tc_tuning): no choice changes a result --------------------------
+
+def _tuning_workload():
+    # banks from one to many partitions, batches of one to several radix
+    # chunks (ids of up to 18 bits under a declared bound of 2^18, so the
+    # digit width is a choice), repeated across three steps
+    rs, seeds = [1, 3000, 70000, (1 << 19) + 5, 9000], [31, 32, 33, 34, 35]
+    Es = [_spread_ids(np_edges(inputs.gnm(3000 + 900 * b, 90000 + 40000 * b, seed=60 + b)),
+                      1 << 18, 60 + b) for b in range(5)]
+    return rs, seeds, Es, [1700, 50000, 140000, 63000, 9000]
+
+
+def test_every_tuning_choice_leaves_identical_state(tc):
+    from paper_1308_2166_amd import tune
+    rs, seeds, Es, ws = _tuning_workload()
+    want = [O.run_stream(Es[b], rs[b], seeds[b], ws[b]).state() for b in range(5)]
+    configs = [dict(tc.DEFAULT_TUNING)]
+    for field, values in tune.CANDIDATES.items():
+        for v in values:
+            if v != tc.DEFAULT_TUNING[field]:
+                c = dict(tc.DEFAULT_TUNING)
+                c[field] = v
+                configs.append(c)
+    configs.append({"digit_bits": 8, "chunk_tiles": 8, "part_estimators": 512,
+                    "join_edges": 1024})
+    configs.append({"digit_bits": 0, "chunk_tiles": 16, "part_estimators": 8192,
+                    "join_edges": 65536})
+    devs = [to_dev(E) for E in Es]
+    for cfg in configs:
+        say(f"  tuning {cfg}")
+        mb = tc.MultiBank(rs, seeds)
+        tc.tc_multi_set_vertex_bound(mb.h, 1 << 18)
+        tc.tc_multi_set_tuning(mb.h, cfg)
+        assert tc.tc_multi_get_tuning(mb.h) == cfg
+        for t in range(max(-(-len(E) // w) for E, w in zip(Es, ws))):
+            ids = [b for b in range(5) if t * ws[b] < len(Es[b])]
+            mb.process(ids, [devs[b][t * ws[b]:(t + 1) * ws[b]] for b in ids])
+        for b in range(5):
+            assert_same(mb.state(b), want[b], f"bank {b}, tuning {cfg}")
+        mb.close()
+    # one bank too
+    g = tc.Bank(20000, 9)
+    tc.tc_set_tuning(g.h, {"chunk_tiles": 8, "part_estimators": 512, "join_edges": 1024})
+    E = np_edges(inputs.rmat(15, 300000, seed=9))
+    g.process_stream(to_dev(E), 140000)
+    assert_same(g.state(), O.run_stream(E, 20000, 9, 140000).state(), "single bank, tuned")
+
+
+def test_tuning_arguments(tc):
+    g = tc.Bank(10, 1)
+    for bad in ({"digit_bits": 10}, {"chunk_tiles": 4}, {"chunk_tiles": 24},
+                {"chunk_tiles": 64}, {"part_estimators": 256}, {"part_estimators": 3000},
+                {"join_edges": 512}, {"join_edges": 1 << 17}):
+        with pytest.raises(tc.TcError) as ei:
+            tc.tc_set_tuning(g.h, bad)
+        assert ei.value.code == tc.TC_EINVAL
+    assert tc.tc_get_tuning(g.h) == tc.DEFAULT_TUNING
+
+
 # -- random mixes of digit widths, chunk counts and table sizes -------------------
 
 def _mix_case(k):
