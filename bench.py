@@ -440,7 +440,7 @@ def traffic_json(workload: str) -> str:
 
 
 PROFILE_TITLES = {
-    "batched": "C4 batched form (256 streams, one batch per stream)",
+    "batched": "C4 (256 streams, one batch per stream)",
     "rmat20": "R-MAT scale 20 (r=2^20, w=2^22)",
     "rmat24": "R-MAT scale 24 (r=2^22, w=2^24)",
     "gnm-2k": "G(2000, 20000) (r=4096, w=2048)",
@@ -542,7 +542,8 @@ def summarize(trace_dir, fetch_dir, write_dir, calib_mib, out_dir, command, time
     with open(os.path.join(out_dir, f"traffic_{workload}.json"), "w") as f:
         json.dump(rec, f, indent=1)
     with open(os.path.join(out_dir, f"step_kernels_{workload}.md"), "w") as f:
-        f.write(f"# Step kernels, {PROFILE_TITLES[workload]}, plain form\n\n")
+        form = "batched form" if workload == "batched" else "plain form"
+        f.write(f"# Step kernels, {PROFILE_TITLES[workload]}, {form}\n\n")
         f.write("Commands (run from the repository root on one MI355X):\n\n```\n"
                 + command + "\n```\n\n")
         f.write(f"Calibration: a {calib_mib} MiB device copy (`__amd_rocclr_copyBuffer`) "

@@ -82,10 +82,23 @@ constexpr uint32_t kMinPartQ = 512;
 uint32_t part_log2_for(uint32_t r, uint32_t part_q = kPartQ) {
   return std::min<uint32_t>(kMaxPartLog2, log2_ceil((r + part_q - 1) / part_q));
 }
-uint32_t ptiles_for(uint64_t n) { return (uint32_t)((n + kPTile - 1) / kPTile); }
+// partition tiles of a chunk: about 32 per side (at least 2^kMinPTileLog2
+// elements each, at most kPTile), so that small steps still spread over
+// the GPU; and tiles of n elements at that size
+uint32_t ptile_log2_for(uint32_t r, uint32_t w) {
+  const uint32_t n = std::max(r, w) / 32;
+  const uint32_t l = n ? 31u - (uint32_t)__builtin_clz(n) : 0u;
+  return std::min<uint32_t>(log2_ceil(kPTile), std::max(kMinPTileLog2, l));
+}
+uint32_t ptiles_for(uint64_t n, uint32_t ptl) { return (uint32_t)((n + (1ull << ptl) - 1) >> ptl); }
+// join slices of a partition: about join_edges batch edges each, and for a
+// small chunk enough of them for about 64 join blocks (of at least 256
+// edges each)
 uint32_t jslices_for(uint32_t w, uint32_t pbits, uint32_t join_edges = kJoinEdges) {
   const uint64_t per = (uint64_t)join_edges << pbits;
-  return (uint32_t)std::max<uint64_t>(1, (w + per - 1) / per);
+  const uint64_t by_size = (w + per - 1) / per;
+  const uint64_t spread = std::min<uint64_t>((64u >> pbits) + 1, (w + (256ull << pbits) - 1) >> (8 + pbits));
+  return (uint32_t)std::max<uint64_t>(1, std::max(by_size, spread));
 }
 
 // Scratch a step needs for one more chunk of w > 0 edges of a bank of r
@@ -159,8 +172,8 @@ void add_chunk(Sizes& z, uint32_t r, uint32_t w, uint32_t part_q) {
   z.tiles += (2ull * w + kTile - 1) / kTile;
   z.dir += 1ull << dl;
   z.doff += (1ull << dl) + kDoffPad;
-  const uint32_t pb = part_log2_for(r, part_q);
-  z.prow += (uint64_t)(ptiles_for(w) + ptiles_for(r)) << pb;
+  const uint32_t pb = part_log2_for(r, part_q), ptl = ptile_log2_for(r, w);
+  z.prow += (uint64_t)(ptiles_for(w, ptl) + ptiles_for(r, ptl)) << pb;
   z.parts += 1ull << pb;
   z.nest += r;
   z.segs += 1;
@@ -178,7 +191,7 @@ Sizes step_bound(uint32_t n, uint32_t r_max, uint64_t E) {
   z.dir = 8 * E + 1024ull * n;
   z.doff = z.dir + (uint64_t)kDoffPad * n;
   const uint32_t pb = part_log2_for(r_max, kMinPartQ);  // grows with r
-  z.prow = (E / kPTile + n + (uint64_t)n * ptiles_for(r_max)) << pb;
+  z.prow = ((E >> kMinPTileLog2) + n + (uint64_t)n * ptiles_for(r_max, kMinPTileLog2)) << pb;
   z.parts = (uint64_t)n << pb;
   z.need = E + 16ull * n;
   z.nest = (uint64_t)n * r_max;
@@ -610,8 +623,9 @@ struct Engine {
       d.prow_off = z.prow;
       d.pbits = part_log2_for(r[b], tune.part_q);
       d.ptile_off = (uint32_t)pl.ptiles;
-      d.netile = ptiles_for(w[k]);
-      d.nqtile = ptiles_for(r[b]);
+      d.ptile_log2 = ptile_log2_for(r[b], w[k]);
+      d.netile = ptiles_for(w[k], d.ptile_log2);
+      d.nqtile = ptiles_for(r[b], d.ptile_log2);
       pl.ptiles += d.netile + d.nqtile;
       d.part_off = (uint32_t)(z.parts);
       d.pscan_off = (uint32_t)pl.pscans;

@@ -89,8 +89,9 @@ struct SegDesc {
   uint64_t prow_off;      // first word of the segment's partition-count rows
   uint32_t pbits;         // log2 of the partitions
   uint32_t ptile_off;     // first partition tile (global)
-  uint32_t netile;        // edge tiles: ceil(w / kPTile)
-  uint32_t nqtile;        // estimator tiles: ceil(r / kPTile)
+  uint32_t ptile_log2;    // log2 of the elements per partition tile
+  uint32_t netile;        // edge tiles: ceil(w / 2^ptile_log2)
+  uint32_t nqtile;        // estimator tiles: ceil(r / 2^ptile_log2)
   uint32_t part_off;      // first partition (global)
   uint32_t pscan_off;     // first k_pscan block (global)
   uint32_t jslices;       // k_pjoin blocks per partition
@@ -126,13 +127,14 @@ struct DirSlot {
 // pbits bits of h = mix64(q) (a bijection) to one of 2^pbits partitions,
 // as 8-byte records (top 32 bits of h) << 32 | (batch position, or the
 // estimator's state index), grouped by partition by a count / scan /
-// scatter over tiles of kPTile elements.  One join block per slice of a
+// scatter over tiles of up to kPTile elements.  One join block per slice of a
 // partition loads the partition's waiting estimators into an LDS hash
 // table (rounds of kJoinQ) and streams the slice's edges through it; equal
 // high words are checked against the edge itself and the estimator's
 // closing edge and position limit.
-constexpr uint32_t kPTile = 16384;     // elements per partition tile (the
+constexpr uint32_t kPTile = 16384;     // most elements per partition tile (the
                                        // scatter stages a tile in LDS)
+constexpr uint32_t kMinPTileLog2 = 10; // fewest: small steps get more tiles
 constexpr uint32_t kPartQ = 2048;      // estimators per partition aimed at
 constexpr uint32_t kMaxPartLog2 = 11;  // at most 2048 partitions per segment
 constexpr uint32_t kJoinQ = 4096;      // query records per join round (LDS)

@@ -1131,7 +1131,7 @@ __device__ __forceinline__ uint32_t pblock_excl_scan(uint32_t v, uint32_t* s_tmp
   return off + x - v;
 }
 
-// Up to kPTile elements of one side of a partition tile: edges of W
+// Up to 2^ptile_log2 elements of one side of a partition tile: edges of W
 // (side 0) or estimators (side 1, waiting ones only).  f(h, id, valid) is
 // called by every thread for each of its elements, in rounds of kPRound
 // loads issued together; h = mix64 of the (closing) edge, id its batch
@@ -1144,7 +1144,7 @@ __device__ __forceinline__ void for_tile(const StepArgs& a, const SegDesc& S, ui
   const int tid = threadIdx.x;
   if (t < S.netile) {
     const uint2* W = reinterpret_cast<const uint2*>(S.edges);
-    const uint32_t j0 = t * kPTile, j1 = min(j0 + kPTile, S.w);
+    const uint32_t j0 = t << S.ptile_log2, j1 = min(j0 + (1u << S.ptile_log2), S.w);
     for (uint32_t b = j0; b < j1; b += kPRound * kPThreads) {
       uint2 ed[kPRound];
 #pragma unroll
@@ -1157,7 +1157,8 @@ __device__ __forceinline__ void for_tile(const StepArgs& a, const SegDesc& S, ui
       }
     }
   } else {
-    const uint32_t i0 = (t - S.netile) * kPTile, i1 = min(i0 + kPTile, S.r);
+    const uint32_t i0 = (t - S.netile) << S.ptile_log2;
+    const uint32_t i1 = min(i0 + (1u << S.ptile_log2), S.r);
     const uint64_t* qq = a.qq + S.est_off;
     for (uint32_t b = i0; b < i1; b += kPRound * kPThreads) {
       uint64_t q[kPRound];
@@ -1403,10 +1404,14 @@ __global__ __launch_bounds__(kJoinThreads) void k_pjoin(StepArgs a) {
     const uint64_t* qrec = a.qrec + S.gest_off;
     const uint64_t* erec = a.erec + S.arc_off / 2;
     const uint2* W = reinterpret_cast<const uint2*>(S.edges);
-    constexpr uint32_t kMask = kJoinSlots - 1;
     for (uint32_t r0 = 0; e_hi > e_lo && r0 < qc; r0 += kJoinQ) {
       const uint32_t nq = min(kJoinQ, qc - r0);
-      for (uint32_t i = tid; i < kJoinSlots; i += kJoinThreads) s_tab[i] = kFreeRec;
+      // a table of four times the round's records (load <= 1/4; at most
+      // kJoinSlots, so a full round of kJoinQ loads it to 1/2): the probes'
+      // chains of LDS reads are the join's critical path
+      const uint32_t cl = nq > 1 ? 32u - (uint32_t)__clz(nq - 1) : 0u;
+      const uint32_t mask = min(kJoinSlots, max(512u, 4u << cl)) - 1u;
+      for (uint32_t i = tid; i <= mask; i += kJoinThreads) s_tab[i] = kFreeRec;
       __syncthreads();
       for (uint32_t i0 = 0; i0 < nq; i0 += kJoinRound * kJoinThreads) {
         uint64_t rec[kJoinRound];
@@ -1416,11 +1421,11 @@ __global__ __launch_bounds__(kJoinThreads) void k_pjoin(StepArgs a) {
 #pragma unroll
         for (uint32_t k = 0; k < kJoinRound; ++k) {
           if (i0 + k * kJoinThreads + tid >= nq) continue;
-          uint32_t slot = (uint32_t)(rec[k] >> 32) & kMask;
+          uint32_t slot = (uint32_t)(rec[k] >> 32) & mask;
           while (atomicCAS(reinterpret_cast<unsigned long long*>(&s_tab[slot]),
                            (unsigned long long)kFreeRec,
                            (unsigned long long)rec[k]) != kFreeRec)
-            slot = (slot + 1) & kMask;
+            slot = (slot + 1) & mask;
         }
       }
       __syncthreads();
@@ -1433,7 +1438,7 @@ __global__ __launch_bounds__(kJoinThreads) void k_pjoin(StepArgs a) {
         for (uint32_t k = 0; k < kJoinRound; ++k) {
           if (j0 + k * kJoinThreads + tid >= e_hi) continue;
           const uint32_t f = (uint32_t)(er[k] >> 32), pos = (uint32_t)er[k];
-          for (uint32_t slot = f & kMask;; slot = (slot + 1) & kMask) {
+          for (uint32_t slot = f & mask;; slot = (slot + 1) & mask) {
             const uint64_t qr = s_tab[slot];
             if (qr == kFreeRec) break;
             if ((uint32_t)(qr >> 32) != f) continue;
