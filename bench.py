@@ -81,6 +81,8 @@ def alg_bytes(kernel: str, w: int, r: int, nontrivial: list) -> float:
         return 16.0 * w + 16.0 * r
     if kernel == "k_pjoin":
         return 8.0 * w + 8.0 * r
+    if kernel == "k_small":  # the whole step of a small chunk: W once, the state
+        return 8.0 * w + 40.0 * r
     return 0.0
 
 
@@ -146,7 +148,7 @@ def cpu_baseline_all_cores(E_host, r, seed, w, nb, workers):
                       f"variant, slowest process {worst:.1f} s"}
 
 
-def batched_comparison(tc, inputs, nstreams=256, ks=(1, 2, 4, 8, 16), replays=3):
+def batched_comparison(tc, inputs, nstreams=256, ks=(1, 2, 4, 8, 16, 64), replays=3):
     """Plain (one bank per stream, one launch set per chunk) against batched
     (every stream's chunk in one launch set per step) and graph replay of the
     batched steps, on independent streams of uneven length.  Each stream is
@@ -463,7 +465,7 @@ def kernel_source_hash() -> str:
 STEP_ORDER = (["k_hist", "k_fold_step1", "k_cscan<0>", "k_scat<0>"]
               + [f"{k}<{p}>" for p in range(1, 4)
                  for k in ("k_cnt", "k_csum", "k_cscan", "k_scat")]
-              + ["k_dir", "k_est", "k_pcnt", "k_pscan", "k_pscat", "k_pjoin"])
+              + ["k_dir", "k_est", "k_pcnt", "k_pscan", "k_pscat", "k_pjoin", "k_small"])
 
 
 def _short(name: str) -> str:

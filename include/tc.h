@@ -157,6 +157,10 @@ int tc_set_vertex_bound(tc_state *s, uint64_t n);
  *                   most 2048 partitions per bank)
  *   join_edges      Step-3 join: batch edges per join block aimed at, a
  *                   power of two in [1024, 65536] (default 8192)
+ *   fused_edges     chunks of at most this many edges (0..2048; default
+ *                   2048) run the whole step in one fused launch, in LDS,
+ *                   with no scratch (not while the stream is being
+ *                   captured, where every chunk takes the chain of kernels)
  * Applies to steps enqueued afterwards; TC_EINVAL for values out of range.
  * tc_step_bytes_max and tc_multi_reserve_max hold for every tuning. */
 typedef struct tc_tuning {
@@ -164,6 +168,7 @@ typedef struct tc_tuning {
   uint32_t chunk_tiles;
   uint32_t part_estimators;
   uint32_t join_edges;
+  uint32_t fused_edges;
 } tc_tuning;
 int tc_set_tuning(tc_state *s, const tc_tuning *t);
 int tc_get_tuning(const tc_state *s, tc_tuning *t);

@@ -39,12 +39,13 @@ class TcError(RuntimeError):
 class TcTuning(ctypes.Structure):
     """tc_tuning: launch shapes that do not change results."""
     _fields_ = [("digit_bits", ctypes.c_uint32), ("chunk_tiles", ctypes.c_uint32),
-                ("part_estimators", ctypes.c_uint32), ("join_edges", ctypes.c_uint32)]
+                ("part_estimators", ctypes.c_uint32), ("join_edges", ctypes.c_uint32),
+                ("fused_edges", ctypes.c_uint32)]
 
 
 TUNING_FIELDS = tuple(f for f, _ in TcTuning._fields_)
 DEFAULT_TUNING = {"digit_bits": 0, "chunk_tiles": 32, "part_estimators": 2048,
-                  "join_edges": 8192}
+                  "join_edges": 8192, "fused_edges": 2048}
 
 _lib = None
 

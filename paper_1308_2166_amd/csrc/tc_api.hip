@@ -36,6 +36,7 @@ hipError_t launch_gsum(const uint32_t* cc, uint64_t e0, uint64_t n,
 hipError_t launch_fill64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
 hipError_t launch_naive(const NaiveArgs& a, hipStream_t st);
 hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_small(const SmallArgs& a, hipStream_t st, hipEvent_t* ev);
 }  // namespace tc
 
 namespace {
@@ -72,6 +73,8 @@ struct Tuning {
   uint32_t chunk_log2 = 5;        // radix tiles per chunk of the scans: 8..kChunk
   uint32_t part_q = kPartQ;       // Step-3 estimators per partition aimed at
   uint32_t join_edges = kJoinEdges;  // Step-3 batch edges per join slice aimed at
+  uint32_t fused_edges = kSmallW;    // chunks of at most this many edges take the
+                                     // fused single-launch step (0: none)
 };
 constexpr uint32_t kMinChunkLog2 = 3;
 constexpr uint32_t kMinPartQ = 512;
@@ -82,29 +85,32 @@ constexpr uint32_t kMinPartQ = 512;
 uint32_t part_log2_for(uint32_t r, uint32_t part_q = kPartQ) {
   return std::min<uint32_t>(kMaxPartLog2, log2_ceil((r + part_q - 1) / part_q));
 }
-// partition tiles of a chunk: about 32 per side (at least 2^kMinPTileLog2
-// elements each, at most kPTile), so that small steps still spread over
-// the GPU; and tiles of n elements at that size
-uint32_t ptile_log2_for(uint32_t r, uint32_t w) {
-  const uint32_t n = std::max(r, w) / 32;
-  const uint32_t l = n ? 31u - (uint32_t)__builtin_clz(n) : 0u;
+// partition tiles of a chunk in a step of nseg chunks: about 32 per side
+// over the step (at least 2^kMinPTileLog2 elements each, at most kPTile), so
+// that a small step still spreads over the GPU; and tiles of n elements at
+// that size
+uint32_t ptile_log2_for(uint32_t r, uint32_t w, uint32_t nseg = 1) {
+  const uint64_t n = (uint64_t)std::max(r, w) * nseg / 32;
+  const uint32_t l = n ? 63u - (uint32_t)__builtin_clzll(n) : 0u;
   return std::min<uint32_t>(log2_ceil(kPTile), std::max(kMinPTileLog2, l));
 }
 uint32_t ptiles_for(uint64_t n, uint32_t ptl) { return (uint32_t)((n + (1ull << ptl) - 1) >> ptl); }
 // join slices of a partition: about join_edges batch edges each, and for a
-// small chunk enough of them for about 64 join blocks (of at least 256
-// edges each)
-uint32_t jslices_for(uint32_t w, uint32_t pbits, uint32_t join_edges = kJoinEdges) {
+// small step enough of them for about 64 join blocks over the step (of at
+// least 256 edges each)
+uint32_t jslices_for(uint32_t w, uint32_t pbits, uint32_t join_edges = kJoinEdges,
+                     uint32_t nseg = 1) {
   const uint64_t per = (uint64_t)join_edges << pbits;
   const uint64_t by_size = (w + per - 1) / per;
-  const uint64_t spread = std::min<uint64_t>((64u >> pbits) + 1, (w + (256ull << pbits) - 1) >> (8 + pbits));
+  const uint64_t spread = std::min<uint64_t>(((64u / std::max(1u, nseg)) >> pbits) + 1,
+                                             (w + (256ull << pbits) - 1) >> (8 + pbits));
   return (uint32_t)std::max<uint64_t>(1, std::max(by_size, spread));
 }
 
 // Scratch a step needs for one more chunk of w > 0 edges of a bank of r
 // estimators (the per-segment regions plan() hands out, in the same order).
 struct Sizes;
-void add_chunk(Sizes& z, uint32_t r, uint32_t w, uint32_t part_q = kPartQ);
+void add_chunk(Sizes& z, uint32_t r, uint32_t w, uint32_t part_q = kPartQ, uint32_t nseg = 1);
 
 template <class T>
 hipError_t dalloc(T** p, uint64_t n) {
@@ -119,11 +125,13 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
-// kernels (bit k = launch k of a step) that a step with npass radix passes
-// launches: the four kernels of each pass at or above npass are skipped,
-// and every pass's k_cscan when the step's segments are single chunks
+// kernels (bit k = launch k of a step) that the chain of a step with npass
+// radix passes launches: the four kernels of each pass at or above npass are
+// skipped, and every pass's k_cscan when the step's segments are single
+// chunks (k_small, the fused step, is not part of the chain)
 uint32_t launched_kernels(uint32_t npass, bool single_chunk) {
-  uint32_t m = (1u << kNumKernels) - 1u;
+  static_assert(kSmallKernel == kNumKernels - 1, "the chain's kernels come first");
+  uint32_t m = (1u << kSmallKernel) - 1u;
   for (uint32_t p = npass < 1 ? 1 : npass; p < (uint32_t)kPasses; ++p)
     m &= ~(15u << (4 + 4 * (p - 1)));
   if (single_chunk)
@@ -165,14 +173,14 @@ struct Sizes {
   }
 };
 
-void add_chunk(Sizes& z, uint32_t r, uint32_t w, uint32_t part_q) {
+void add_chunk(Sizes& z, uint32_t r, uint32_t w, uint32_t part_q, uint32_t nseg) {
   const uint32_t dl = dir_log2_for(w);
   z.need += (w + 15) / 16 * 16;
   z.arcs += 2ull * w;
   z.tiles += (2ull * w + kTile - 1) / kTile;
   z.dir += 1ull << dl;
   z.doff += (1ull << dl) + kDoffPad;
-  const uint32_t pb = part_log2_for(r, part_q), ptl = ptile_log2_for(r, w);
+  const uint32_t pb = part_log2_for(r, part_q), ptl = ptile_log2_for(r, w, nseg);
   z.prow += (uint64_t)(ptiles_for(w, ptl) + ptiles_for(r, ptl)) << pb;
   z.parts += 1ull << pb;
   z.nest += r;
@@ -317,6 +325,7 @@ struct Engine {
   uint64_t* QQ = nullptr;  // closing edge each estimator waits for
   uint32_t* QT = nullptr;  // its first closing batch position
   uint64_t* bank_off = nullptr;  // device copy of est_off
+  SmallDesc* sdesc = nullptr;    // device copy of a fused step's descriptors
   unsigned long long* sums = nullptr;
   unsigned long long* gsums = nullptr;  // median-of-means group sums
   uint64_t* h_gsums = nullptr;          // pinned
@@ -412,6 +421,7 @@ struct Engine {
     ev_pending.clear();
     ev_free.clear();
     dfree(R1), dfree(R2), dfree(CC), dfree(J1), dfree(QQ), dfree(QT), dfree(bank_off);
+    dfree(sdesc);
     dfree(sums), dfree(err), dfree(tagp), dfree(gsums);
     if (stc) (void)hipStreamSynchronize(stc);
     for (int b = 0; b < 2; ++b) {
@@ -486,7 +496,7 @@ struct Engine {
       return fail(TC_EHIP, "stream or event creation failed");
     if (dalloc(&R1, total) || dalloc(&R2, total) || dalloc(&CC, total) ||
         dalloc(&J1, total) || dalloc(&QQ, total) || dalloc(&QT, total) ||
-        dalloc(&bank_off, n + 1) ||
+        dalloc(&bank_off, n + 1) || dalloc(&sdesc, n) ||
         dalloc(&sums, n) || dalloc(&err, 1) || dalloc(&tagp, 1))
       return fail(TC_ENOMEM, "device allocation of the estimator banks failed");
     if (hipHostMalloc(reinterpret_cast<void**>(&h_sums), sizeof(uint64_t) * n) ||
@@ -538,14 +548,21 @@ struct Engine {
 
   int stage_descs(const std::vector<SegDesc>& segs, SegDesc* dst,
                   hipStream_t st, bool capturing) {
-    const uint32_t n = (uint32_t)segs.size();
+    return stage_bytes(segs.data(), (uint32_t)segs.size(), sizeof(SegDesc), dst, st, capturing);
+  }
+
+  // n items of `item` bytes (at most sizeof(SegDesc) each) to the device
+  // buffer dst on st, through a pinned staging ring (or, under capture, the
+  // captured step's own pinned buffer)
+  int stage_bytes(const void* src, uint32_t n, size_t item, void* dst, hipStream_t st,
+                  bool capturing) {
     if (capturing) {
       if (graph_next >= graph_stage.size())
         return fail(TC_EINVAL, "more captured steps than tc_multi_graph_reserve allowed");
       if (n > nbanks) return fail(TC_EINVAL, "too many chunks");
       SegDesc* buf = graph_stage[graph_next++];
-      std::memcpy(buf, segs.data(), sizeof(SegDesc) * n);
-      if (hipMemcpyAsync(dst, buf, sizeof(SegDesc) * n, hipMemcpyHostToDevice, st))
+      std::memcpy(buf, src, item * n);
+      if (hipMemcpyAsync(dst, buf, item * n, hipMemcpyHostToDevice, st))
         return fail(TC_EHIP, "descriptor upload failed");
       return TC_OK;
     }
@@ -565,8 +582,8 @@ struct Engine {
     const int k = ring;
     ring = (ring + 1) % kRing;
     if (stage_used[k]) (void)hipEventSynchronize(stage_ev[k]);
-    std::memcpy(stage[k], segs.data(), sizeof(SegDesc) * n);
-    if (hipMemcpyAsync(dst, stage[k], sizeof(SegDesc) * n, hipMemcpyHostToDevice, st) ||
+    std::memcpy(stage[k], src, item * n);
+    if (hipMemcpyAsync(dst, stage[k], item * n, hipMemcpyHostToDevice, st) ||
         hipEventRecord(stage_ev[k], st))
       return fail(TC_EHIP, "descriptor upload failed");
     stage_used[k] = true;
@@ -588,6 +605,8 @@ struct Engine {
     pl.segs.reserve(nchunks);
     std::vector<char> seen(nbanks, 0);
     Sizes& z = pl.z;
+    uint32_t nseg = 0;  // chunks with edges: the step's segments
+    for (uint32_t k = 0; k < nchunks; ++k) nseg += w[k] != 0 && w[k] <= TC_MAX_BATCH;
     for (uint32_t k = 0; k < nchunks; ++k) {
       const uint32_t b = ids[k];
       if (b >= nbanks) return fail(TC_EINVAL, "bank id out of range");
@@ -623,17 +642,17 @@ struct Engine {
       d.prow_off = z.prow;
       d.pbits = part_log2_for(r[b], tune.part_q);
       d.ptile_off = (uint32_t)pl.ptiles;
-      d.ptile_log2 = ptile_log2_for(r[b], w[k]);
+      d.ptile_log2 = ptile_log2_for(r[b], w[k], nseg);
       d.netile = ptiles_for(w[k], d.ptile_log2);
       d.nqtile = ptiles_for(r[b], d.ptile_log2);
       pl.ptiles += d.netile + d.nqtile;
       d.part_off = (uint32_t)(z.parts);
       d.pscan_off = (uint32_t)pl.pscans;
       pl.pscans += 2ull * (((1ull << d.pbits) + 63) / 64);
-      d.jslices = jslices_for(w[k], d.pbits, tune.join_edges);
+      d.jslices = jslices_for(w[k], d.pbits, tune.join_edges, nseg);
       d.jblk_off = (uint32_t)pl.jblks;
       pl.jblks += (uint64_t)d.jslices << d.pbits;
-      add_chunk(z, r[b], w[k], tune.part_q);
+      add_chunk(z, r[b], w[k], tune.part_q, nseg);
       pl.segs.push_back(d);
       pl.bank.push_back(b);
     }
@@ -723,34 +742,64 @@ struct Engine {
            const uint32_t* w, hipStream_t st, bool reserve = false,
            bool overlap = false) {
     if (sticky != TC_OK) return fail(sticky, "an earlier batch failed on the device");
-    Plan pl;
-    int rc = plan(nchunks, ids, edges, w, reserve, pl);
-    if (rc || pl.segs.empty()) return rc;
-    if (reserve) return ensure_scratch(pl.z, st);
+    Plan all;  // every chunk, validated
+    int rc = plan(nchunks, ids, edges, w, reserve, all);
+    if (rc || all.segs.empty()) return rc;
+    if (reserve) return ensure_scratch(all.z, st);
     // the capture status decides before anything may synchronize, allocate
     // or free: growing the scratch under capture would do all three
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess)
       return fail(TC_EHIP, "hipStreamIsCapturing failed");
     const bool capturing = cs == hipStreamCaptureStatusActive;
-    if (capturing && !cap.fits(pl.z))
-      return fail(TC_EINVAL, "a step being captured needs more scratch than reserved "
-                             "(call tc_reserve / tc_multi_reserve before capturing)");
     if (capturing && timing) return fail(TC_EINVAL, "kernel timing is on while capturing");
-    rc = ensure_scratch(pl.z, st);
-    if (rc) return rc;
-    if (++steps % 0xFFFF0000ull == 0 && !capturing) {
-      // directory tags are about to wrap: forget every entry (fill, not memset)
-      if (join(st) || launch_fill32(reinterpret_cast<uint32_t*>(S.dir), cap.dir * 4, 0, st))
-        return fail(TC_EHIP, "table reset failed");
+    // a step whose chunks all have at most fused_edges edges takes the
+    // fused step (one launch, no scratch); any other step the chain of
+    // kernels, for all its chunks (a fused launch after the chain would
+    // only add to the step's time).  Under capture every step takes the
+    // chain, whose descriptors have per-capture buffers.
+    bool fuse = !capturing;
+    for (const SegDesc& d : all.segs) fuse = fuse && d.w <= tune.fused_edges;
+    std::vector<SmallDesc> small;
+    std::vector<uint32_t> sbank, lid, lw;
+    std::vector<const uint32_t*> led;
+    uint32_t sblk = 0;
+    for (size_t k = 0; k < all.segs.size(); ++k) {
+      const SegDesc& d = all.segs[k];
+      if (fuse) {
+        small.push_back(SmallDesc{d.edges, d.m, d.batch, d.key0, d.est_off, d.w, d.r, sblk, 0});
+        sbank.push_back(all.bank[k]);
+        sblk += (d.r + kSmallR - 1) / kSmallR;
+      } else {
+        lid.push_back(all.bank[k]), led.push_back(d.edges), lw.push_back(d.w);
+      }
     }
-    const ParityScratch& P = S.par[steps & 1];
-    StepArgs a = make_args(pl, S, P);
-    if (a.nseg > 1) {
-      rc = stage_descs(pl.segs, P.segs, st, capturing);
+    Plan pl;
+    if (!lid.empty()) {
+      rc = plan((uint32_t)lid.size(), lid.data(), led.data(), lw.data(), false, pl);
       if (rc) return rc;
     }
-    if (capturing) captured = true;
+    const bool chain = !pl.segs.empty();
+    if (capturing && chain && !cap.fits(pl.z))
+      return fail(TC_EINVAL, "a step being captured needs more scratch than reserved "
+                             "(call tc_reserve / tc_multi_reserve before capturing)");
+    StepArgs a{};
+    if (chain) {
+      rc = ensure_scratch(pl.z, st);
+      if (rc) return rc;
+      if (++steps % 0xFFFF0000ull == 0 && !capturing) {
+        // directory tags are about to wrap: forget every entry (fill, not memset)
+        if (join(st) || launch_fill32(reinterpret_cast<uint32_t*>(S.dir), cap.dir * 4, 0, st))
+          return fail(TC_EHIP, "table reset failed");
+      }
+      const ParityScratch& P = S.par[steps & 1];
+      a = make_args(pl, S, P);
+      if (a.nseg > 1) {
+        rc = stage_descs(pl.segs, P.segs, st, capturing);
+        if (rc) return rc;
+      }
+      if (capturing) captured = true;
+    }
     hipEvent_t* ev = nullptr;
     if (timing) {
       if (!ev_free.empty()) {
@@ -764,9 +813,43 @@ struct Engine {
               return fail(TC_EHIP, "hipEventCreate failed");
       }
       ev_pending.push_back(ev);
-      ev_launched.push_back(launched_kernels(npass, a.single_chunk != 0));
+      ev_launched.push_back((chain ? launched_kernels(npass, a.single_chunk != 0) : 0u) |
+                            (small.empty() ? 0u : 1u << kSmallKernel));
     }
-    return launch(pl, a, st, ev, overlap);
+    if (chain) {
+      rc = launch(pl, a, st, ev, overlap);
+      if (rc) return rc;
+    }
+    if (!small.empty()) return launch_fused(small, sbank, sblk, st, ev, !chain);
+    return TC_OK;
+  }
+
+  // The fused step of the small chunks: after the previous step's Step 3
+  // (join_first: when no chain of this step has already waited for it),
+  // one launch of k_small.
+  int launch_fused(const std::vector<SmallDesc>& small, const std::vector<uint32_t>& sbank,
+                   uint32_t nblk, hipStream_t st, hipEvent_t* ev, bool join_first) {
+    if (join_first) {
+      int rc = join(st);
+      if (rc) return rc;
+    }
+    SmallArgs a{};
+    a.nseg = (uint32_t)small.size();
+    a.d0 = small[0];
+    a.nblk = nblk;
+    a.descs = sdesc;
+    if (a.nseg > 1) {
+      int rc = stage_bytes(small.data(), a.nseg, sizeof(SmallDesc), sdesc, st, false);
+      if (rc) return rc;
+    }
+    a.r1 = R1, a.r2 = R2, a.cc = CC, a.err = err, a.id_limit = id_limit;
+    if (launch_small(a, st, ev) != hipSuccess) return fail(TC_EHIP, "kernel launch failed");
+    for (size_t k = 0; k < small.size(); ++k) {
+      m[sbank[k]] += small[k].w;
+      batch[sbank[k]] += 1;
+    }
+    last = st;
+    return TC_OK;
   }
 
   // One batch for bank 0 with every per-step buffer carved from the
@@ -960,7 +1043,7 @@ struct Engine {
     auto pow2 = [](uint32_t x) { return x && !(x & (x - 1)); };
     if (t.digits8 > 1 || t.chunk_log2 < kMinChunkLog2 || (1u << t.chunk_log2) > kChunk ||
         !pow2(t.part_q) || t.part_q < kMinPartQ || t.part_q > 8192 || !pow2(t.join_edges) ||
-        t.join_edges < 1024 || t.join_edges > 65536)
+        t.join_edges < 1024 || t.join_edges > 65536 || t.fused_edges > kSmallW)
       return fail(TC_EINVAL, "tuning out of range");
     tune = t;
     digits();
@@ -1203,10 +1286,13 @@ uint64_t tc_bank_bytes(uint32_t r) {
 uint64_t tc_step_bytes(uint32_t nchunks, const uint32_t* r, const uint32_t* w) {
   if (nchunks && (!r || !w)) return 0;
   Sizes z;
+  uint32_t nseg = 0;
   for (uint32_t k = 0; k < nchunks; ++k) {
     if (w[k] > TC_MAX_BATCH || r[k] == 0) return 0;
-    if (w[k]) add_chunk(z, r[k], w[k]);
+    nseg += w[k] != 0;
   }
+  for (uint32_t k = 0; k < nchunks; ++k)
+    if (w[k]) add_chunk(z, r[k], w[k], kPartQ, nseg);
   return z.segs ? carve(nullptr, z, 2, false, nullptr) : 0;
 }
 
@@ -1232,6 +1318,7 @@ static int set_tuning_from(Engine& e, const tc_tuning* t) {
     return fail(TC_EINVAL, "chunk_tiles must be 8, 16 or 32");
   u.part_q = t->part_estimators;
   u.join_edges = t->join_edges;
+  u.fused_edges = t->fused_edges;
   return e.set_tuning(u);
 }
 
@@ -1240,6 +1327,7 @@ static void get_tuning_from(const Engine& e, tc_tuning* t) {
   t->chunk_tiles = 1u << e.tune.chunk_log2;
   t->part_estimators = e.tune.part_q;
   t->join_edges = e.tune.join_edges;
+  t->fused_edges = e.tune.fused_edges;
 }
 
 int tc_set_tuning(tc_state* s, const tc_tuning* t) {
@@ -1326,7 +1414,7 @@ static const char* const kKernelNames[kNumKernels] = {
     "k_cnt<1>", "k_csum<1>", "k_cscan<1>", "k_scat<1>",
     "k_cnt<2>", "k_csum<2>", "k_cscan<2>", "k_scat<2>",
     "k_cnt<3>", "k_csum<3>", "k_cscan<3>", "k_scat<3>",
-    "k_dir", "k_est", "k_pcnt", "k_pscan", "k_pscat", "k_pjoin"};
+    "k_dir", "k_est", "k_pcnt", "k_pscan", "k_pscat", "k_pjoin", "k_small"};
 
 static int set_timing(Engine& e, uint32_t mask) {
   int rc = e.collect_times();

@@ -28,7 +28,8 @@ constexpr int kWidePasses = 2;           // passes of wide digits
 // passes: pass P's counts start at word P << D
 constexpr int kRowWords = kWidePasses << kWideBits;
 static_assert(kRowWords >= kPasses << 8, "a row holds every 8-bit pass");
-constexpr int kNumKernels = 22;  // launches per step (k_hist .. k_pjoin)
+constexpr int kNumKernels = 23;  // kernels of a step (k_hist .. k_pjoin, k_small)
+constexpr int kSmallKernel = 22; // k_small's index (the fused step of small chunks)
 constexpr int kHistTiles = 1;   // tiles per k_hist block (one: its counts are
                                 // the per-tile counts of the first radix pass)
 constexpr uint32_t kChunk = 32;  // most tiles per chunk of the radix scans (and
@@ -207,6 +208,39 @@ struct NaiveArgs {
   uint64_t* r2;
   uint32_t* cc;
   uint32_t* err;
+};
+
+// The fused step of small chunks (k_small): every chunk of at most
+// kSmallW edges runs Steps 1-3 in one launch, in LDS, with no scratch; a
+// block takes one bank's slice of kSmallR estimators and rebuilds the
+// chunk's sorted arcs and edge table itself.
+constexpr uint32_t kSmallW = 2048;     // edges of a fused chunk at most
+constexpr uint32_t kSmallR = 1024;     // estimators per block (one per
+                                       // thread: small banks spread over CUs)
+constexpr int kSmallThreads = 1024;
+
+struct SmallDesc {
+  const uint32_t* edges;  // W: uint32[2w], device
+  uint64_t m;             // bank's |E| before this batch
+  uint64_t batch;         // bank's batch index
+  uint64_t key0;          // mix64(seed ^ golden)
+  uint64_t est_off;       // bank's first estimator
+  uint32_t w;             // edges (1..kSmallW)
+  uint32_t r;             // estimators in the bank
+  uint32_t blk_off;       // first k_small block of the chunk
+  uint32_t pad;
+};
+
+struct SmallArgs {
+  const SmallDesc* descs;  // device copy of the descriptors
+  SmallDesc d0;            // inline copy when nseg == 1
+  uint32_t nseg;
+  uint32_t nblk;           // blocks over all chunks
+  uint64_t* r1;
+  uint64_t* r2;
+  uint32_t* cc;
+  uint32_t* err;
+  uint32_t id_limit;       // largest vertex id allowed
 };
 
 }  // namespace tc

@@ -2,7 +2,8 @@
 
 The shapes -- radix digit width where the vertex bound allows a choice,
 radix tiles per chunk of the reduce-then-scan, waiting estimators per Step-3
-join partition, batch edges per join block -- change no result, only the
+join partition, batch edges per join block, the largest chunk that takes the
+fused single-launch step -- change no result, only the
 time a step takes, and the best ones depend on the step's batch sizes and
 bank sizes and on the width of the vertex ids.  `tune` times candidate shapes
 on the caller's own steps by coordinate descent (one field at a time, every
@@ -30,6 +31,7 @@ CANDIDATES = {
     "chunk_tiles": (8, 16, 32),
     "part_estimators": (1024, 2048, 4096),
     "join_edges": (4096, 8192, 16384),
+    "fused_edges": (0, 2048),
 }
 
 

@@ -93,7 +93,7 @@ def test_kernel_names_in_launch_order():
     want = ["k_hist", "k_fold_step1", "k_cscan<0>", "k_scat<0>"]
     for p in (1, 2, 3):
         want += [f"k_cnt<{p}>", f"k_csum<{p}>", f"k_cscan<{p}>", f"k_scat<{p}>"]
-    want += ["k_dir", "k_est", "k_pcnt", "k_pscan", "k_pscat", "k_pjoin"]
+    want += ["k_dir", "k_est", "k_pcnt", "k_pscan", "k_pscat", "k_pjoin", "k_small"]
     assert [tc.tc_kernel_name(k) for k in range(tc.tc_num_kernels())] == want
     bench = __import__("bench")
     assert [n for n in bench.STEP_ORDER] == want

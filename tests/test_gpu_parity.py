@@ -791,16 +791,19 @@ def test_multi_vertex_bound(tc):
 
 def test_kernel_timing_with_bound(tc):
     # passes above the bound are not launched: their times stay zero; a
-    # batch of one radix chunk (8-bit digits) launches no chunk scan
+    # batch of one radix chunk (8-bit digits) launches no chunk scan (the
+    # fused step is switched off, so these small batches take the chain)
     E = to_dev(np_edges(inputs.gnm(200, 3000, seed=9)))
     g = tc.Bank(1000, 2)
     tc.tc_set_vertex_bound(g.h, 200)
+    tc.tc_set_tuning(g.h, {"fused_edges": 0})
     tc.tc_set_kernel_timing(g.h, True)
     g.process(E[:1500])
     g.process(E[1500:])
     times, steps = tc.tc_kernel_times(g.h)
     assert steps == 2
     assert times["k_scat<0>"] > 0 and times["k_est"] > 0 and times["k_cscan<0>"] == 0.0
+    assert times["k_small"] == 0.0
     for p in (1, 2, 3):
         for k in ("k_cnt", "k_csum", "k_cscan", "k_scat"):
             assert times[f"{k}<{p}>"] == 0.0
@@ -986,6 +989,81 @@ def test_join_slices_and_partition_counts(tc):
         run_both(tc, E[:min(len(E), 2 * w + 17)], r, seed=r, w=w, every=False)
 
 
+# -- the fused step of small chunks (k_small) against the chain and the oracle ------
+
+@pytest.mark.parametrize("n,m,r,w", [(30, 120, 7, 2), (60, 500, 100, 7), (200, 3000, 1000, 2048),
+                                     (1000, 9000, 257, 2047), (80, 2000, 5000, 333),
+                                     (3000, 30000, 9000, 1500)])
+def test_fused_step_equals_chain_and_oracle(tc, n, m, r, w):
+    E = np_edges(inputs.gnm(n, m, seed=n + 7 * m))
+    dev = to_dev(E)
+    o = O.run_stream(E, r, 55, w)
+    for fused in (0, 2048):
+        g = tc.Bank(r, 55)
+        tc.tc_set_tuning(g.h, {"fused_edges": fused})
+        for j in range(0, len(E), w):
+            g.process(dev[j:j + w])
+        assert_same(g.state(), o.state(), f"fused_edges={fused}")
+        assert tc.tc_estimate_ex(g.h)[0] == o.sum()
+
+
+def test_fused_step_edge_cases(tc):
+    # a star (one vertex in every arc), ids at the top of uint32, repeated
+    # edges, a bank larger than one block's slice, and fused and chained
+    # chunks in one batched step
+    hub = 0xFFFFFFFE
+    leaves = np.arange(5, 2005, dtype=np.uint32)
+    star = np.stack([np.full_like(leaves, hub), leaves], 1)
+    star = star[np.random.default_rng(2).permutation(len(star))]
+    g, o = run_both(tc, star, r=9000, seed=3, w=2000)
+    rep = np_edges(inputs.gnm(40, 300, seed=4))
+    rep = np.concatenate([rep, rep[::-1], rep])
+    run_both(tc, rep, r=5000, seed=5, w=611)
+    top = (np.uint64(2**32 - 1) - np_edges(inputs.gnm(300, 4000, seed=6)).astype(np.uint64))
+    run_both(tc, top.astype(np.uint32), r=20000, seed=7, w=1999)
+    rs, seeds = [3000, 70000, 5000], [1, 2, 3]
+    Es = [np_edges(inputs.gnm(900 + 400 * b, 20000, seed=80 + b)) for b in range(3)]
+    # steps of three fused chunks (one launch, descriptors uploaded), then
+    # steps mixing small chunks with one that needs the chain (all take it)
+    for ws in ([2048, 1024, 700], [2048, 1024, 6000]):
+        mb = tc.MultiBank(rs, seeds)
+        for t in range(max(-(-len(E) // w) for E, w in zip(Es, ws))):
+            ids = [b for b in range(3) if t * ws[b] < len(Es[b])]
+            mb.process(ids, [to_dev(Es[b][t * ws[b]:(t + 1) * ws[b]]) for b in ids])
+        for b in range(3):
+            assert_same(mb.state(b), O.run_stream(Es[b], rs[b], seeds[b], ws[b]).state(),
+                        f"bank {b}, chunks {ws}")
+        mb.close()
+
+
+def test_fused_step_errors(tc):
+    # a self-loop or an id above the bound in a fused chunk is reported
+    g = tc.Bank(100, 1)
+    E = np_edges(inputs.gnm(50, 200, seed=1)).copy()
+    E[7] = [3, 3]
+    g.process(to_dev(E))
+    with pytest.raises(tc.TcError) as ei:
+        g.sync()
+    assert ei.value.code == tc.TC_EBADEDGE
+    g = tc.Bank(100, 1)
+    tc.tc_set_vertex_bound(g.h, 40)
+    g.process(to_dev(np_edges(inputs.gnm(50, 200, seed=1))))
+    with pytest.raises(tc.TcError) as ei:
+        g.sync()
+    assert ei.value.code == tc.TC_EINVAL
+
+
+def test_fused_kernel_timing(tc):
+    E = to_dev(np_edges(inputs.gnm(300, 3000, seed=2)))
+    g = tc.Bank(1000, 1)
+    tc.tc_set_kernel_timing(g.h, True)
+    g.process(E[:1500])
+    g.process(E[1500:])
+    times, steps = tc.tc_kernel_times(g.h)
+    assert steps == 2 and times["k_small"] > 0
+    assert all(v == 0.0 for k, v in times.items() if k != "k_small")
+
+
 # -- launch shapes (tc_tuning): no choice changes a result --------------------------
 
 def _tuning_workload():
@@ -1010,9 +1088,9 @@ def test_every_tuning_choice_leaves_identical_state(tc):
                 c[field] = v
                 configs.append(c)
     configs.append({"digit_bits": 8, "chunk_tiles": 8, "part_estimators": 512,
-                    "join_edges": 1024})
+                    "join_edges": 1024, "fused_edges": 0})
     configs.append({"digit_bits": 0, "chunk_tiles": 16, "part_estimators": 8192,
-                    "join_edges": 65536})
+                    "join_edges": 65536, "fused_edges": 1024})
     devs = [to_dev(E) for E in Es]
     for cfg in configs:
         say(f"  tuning {cfg}")
