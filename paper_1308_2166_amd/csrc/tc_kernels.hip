@@ -893,14 +893,42 @@ __device__ __forceinline__ uint2 dir_find_hashed(const DirSlot* dir, uint32_t ma
   return make_uint2(0, 0);
 }
 
-// The block's tile of sorted arcs (plus one arc on each side) is loaded up
-// front into LDS; each arc then finds its neighbours there.  Dense
-// directory: the tile writes the CSR offsets of the vertex ids from one past
-// the arc before the tile to its last arc's (to max id + 1 for the last
-// tile), each by a binary search of the tile, so every id up to max id + 1
-// is written by exactly one tile and the writes are consecutive words.
+// Vertex ids per window of the dense offsets that k_dir fills at a time.
+constexpr uint32_t kDirWin = 16u * kBlock;
+static_assert(kTile < 0xFFFFu, "tile indices and the empty mark fit 16 bits");
+
+// suffix minimum over a kBlock block of one value per thread: the minimum
+// of the values of the threads above this one (0xFFFF when there is none)
+__device__ __forceinline__ uint32_t block_excl_suffix_min(uint32_t v, uint32_t* s_tmp) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_down(x, d);
+    if (lane + d < 64) x = min(x, y);
+  }
+  if (lane == 0) s_tmp[wave] = x;
+  uint32_t above = __shfl_down(x, 1);
+  if (lane == 63) above = 0xFFFFu;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k)
+    if (k > wave) above = min(above, s_tmp[k]);
+  return above;
+}
+
+// The block's tile of sorted arcs keeps its arcs in registers and their
+// vertices (plus the arc on each side) in LDS.  Dense directory: the tile
+// writes the CSR offsets of the vertex ids from one past the arc before the
+// tile to its last arc's (to max id + 1 for the last tile), so every id up
+// to max id + 1 is written by exactly one tile.  Offset y is the tile's
+// first arc of a vertex >= y: a suffix minimum, over the window of ids, of
+// the marks that each vertex's first arc in the tile leaves at its id; the
+// windows go from the top down, each written out in consecutive words.
 __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
-  __shared__ uint64_t s_arc[kTile + 2];  // s_arc[1 + t] = arc base + t
+  __shared__ uint32_t s_vtx[kTile + 2];  // s_vtx[1 + t] = vertex of arc base + t
+  __shared__ __align__(16) uint16_t s_win[kDirWin];
+  __shared__ uint32_t s_tmp[kWaves];
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
   const uint32_t gtile = blockIdx.x;
@@ -915,50 +943,79 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
   const uint32_t n = 2u * S.w;
   const uint32_t base = (gtile - S.tile_off) * kTile;
   const uint32_t nv = min((uint32_t)kTile, n - base);
-  {
-    // clamped loads past the ragged end are never used as arcs
-    uint64_t v[kItems];
+  // clamped loads past the ragged end are never used as arcs
+  uint64_t v[kItems];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) v[k] = arc[min(base + k * kBlock + tid, n - 1)];
-    if (tid == 0) s_arc[0] = arc[base > 0 ? base - 1 : 0];
-    if (tid == 1) s_arc[kTile + 1] = arc[min(base + kTile, n - 1)];
+  for (int k = 0; k < kItems; ++k) v[k] = arc[min(base + k * kBlock + tid, n - 1)];
+  if (tid == 0) s_vtx[0] = (uint32_t)(arc[base > 0 ? base - 1 : 0] >> 32);
+  if (tid == 1) s_vtx[kTile + 1] = (uint32_t)(arc[min(base + kTile, n - 1)] >> 32);
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) s_arc[1 + k * kBlock + tid] = v[k];
-  }
+  for (int k = 0; k < kItems; ++k) s_vtx[1 + k * kBlock + tid] = (uint32_t)(v[k] >> 32);
   __syncthreads();
   const bool dense = wk->dense != 0;
   uint32_t* inv = a.inv + S.arc_off;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const uint32_t t = k * kBlock + tid;
+    const uint32_t id = (uint32_t)v[k];
+    if (t < nv && (id & kNeedFlag)) inv[id & kIdMask] = base + t;
+  }
   if (dense) {
-    for (uint32_t t = tid; t < nv; t += kBlock) {
-      const uint32_t id = (uint32_t)s_arc[1 + t];
-      if (id & kNeedFlag) inv[id & kIdMask] = base + t;
-    }
     uint32_t* off = a.doff + S.doff_off;
-    const uint32_t lo = base == 0 ? 0u : (uint32_t)(s_arc[0] >> 32) + 1u;
-    const uint32_t hi = base + nv == n ? uniform(wk->maxid) + 1u
-                                       : (uint32_t)(s_arc[nv] >> 32);
-    for (uint64_t y = (uint64_t)lo + tid; y <= hi; y += kBlock) {
-      // the tile's first arc of a vertex >= y (nv when there is none)
-      uint32_t l = 0, h = nv;
-      while (l < h) {
-        const uint32_t mid = (l + h) >> 1;
-        if ((uint64_t)(s_arc[1 + mid] >> 32) < y) l = mid + 1; else h = mid;
+    const uint64_t lo = base == 0 ? 0u : (uint64_t)s_vtx[0] + 1u;
+    const uint64_t hi = base + nv == n ? (uint64_t)uniform(wk->maxid) + 1u
+                                       : (uint64_t)s_vtx[nv];
+    if (lo > hi) return;  // the whole tile continues the vertex before it
+    uint32_t carry = nv;  // first arc at or above the current window's end
+    for (uint64_t win = (hi - lo) / kDirWin + 1; win-- > 0;) {
+      const uint64_t y0 = lo + win * kDirWin;
+      const uint32_t len = hi - y0 + 1 < kDirWin ? (uint32_t)(hi - y0 + 1) : kDirWin;
+      uint4* w4 = reinterpret_cast<uint4*>(s_win);
+      w4[2 * tid] = make_uint4(~0u, ~0u, ~0u, ~0u);
+      w4[2 * tid + 1] = make_uint4(~0u, ~0u, ~0u, ~0u);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) {
+        const uint32_t t = k * kBlock + tid;
+        const uint32_t x = s_vtx[1 + t];
+        const bool head = t == 0 || s_vtx[t] != x;
+        if (t < nv && head && x >= y0 && x - y0 < len) s_win[x - y0] = (uint16_t)t;
       }
-      off[y] = base + l;
+      __syncthreads();
+      // the thread's 16 consecutive marks, their suffix minima in place
+      const uint4 q0 = w4[2 * tid], q1 = w4[2 * tid + 1];
+      uint32_t m[16] = {q0.x & 0xFFFFu, q0.x >> 16, q0.y & 0xFFFFu, q0.y >> 16,
+                        q0.z & 0xFFFFu, q0.z >> 16, q0.w & 0xFFFFu, q0.w >> 16,
+                        q1.x & 0xFFFFu, q1.x >> 16, q1.y & 0xFFFFu, q1.y >> 16,
+                        q1.z & 0xFFFFu, q1.z >> 16, q1.w & 0xFFFFu, q1.w >> 16};
+#pragma unroll
+      for (int j = 14; j >= 0; --j) m[j] = min(m[j], m[j + 1]);
+      const uint32_t above = min(block_excl_suffix_min(m[0], s_tmp), carry);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) m[j] = min(m[j], above);
+      __syncthreads();  // every thread has read its marks
+      w4[2 * tid] = make_uint4(m[0] | m[1] << 16, m[2] | m[3] << 16, m[4] | m[5] << 16,
+                               m[6] | m[7] << 16);
+      w4[2 * tid + 1] = make_uint4(m[8] | m[9] << 16, m[10] | m[11] << 16,
+                                   m[12] | m[13] << 16, m[14] | m[15] << 16);
+      __syncthreads();
+      for (uint32_t k = tid; k < len; k += kBlock) off[y0 + k] = base + s_win[k];
+      carry = s_win[0];
+      __syncthreads();  // before the next window overwrites the marks
     }
     return;
   }
   DirSlot* dir = a.dir + S.dir_off;
   const uint32_t mask = (1u << S.dir_log2) - 1u;
   const uint32_t tag = uniform(*a.tagp);
-  for (uint32_t t = tid; t < nv; t += kBlock) {
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const uint32_t t = k * kBlock + tid;
+    if (t >= nv) continue;
     const uint32_t i = base + t;
-    const uint64_t e = s_arc[1 + t];
-    const uint32_t id = (uint32_t)e;
-    if (id & kNeedFlag) inv[id & kIdMask] = i;
-    const uint32_t x = (uint32_t)(e >> 32);
-    const bool head = i == 0 || (uint32_t)(s_arc[t] >> 32) != x;
-    const bool tail = i + 1 == n || (uint32_t)(s_arc[t + 2] >> 32) != x;
+    const uint32_t x = s_vtx[1 + t];
+    const bool head = i == 0 || s_vtx[t] != x;
+    const bool tail = i + 1 == n || s_vtx[t + 2] != x;
     if (!head && !tail) continue;
     const uint32_t slot = dir_claim(dir, mask, x, tag, a.err);
     if (slot == kNone) continue;
