@@ -469,13 +469,14 @@ STEP_ORDER = (["k_hist", "k_fold_step1", "k_cscan<0>", "k_scat<0>"]
 
 
 def _short(name: str) -> str:
-    """Kernel name as tc_kernel_name gives it: the digit width is dropped
-    (k_scat<1, 10> is the launch k_scat<1>, k_hist<8> is k_hist), and the
-    four-wave build of a radix pass, k_scat4<P>, is the launch k_scat<P>."""
+    """Kernel name as tc_kernel_name gives it: the digit width and the
+    single-segment flag are dropped (k_scat<1, 10> is the launch k_scat<1>,
+    k_hist<8> is k_hist, k_est<true> is k_est), and the four-wave build of a
+    radix pass, k_scat4<P>, is the launch k_scat<P>."""
     import re
     n = re.sub(r"\(.*", "", name).replace("void ", "").replace("tc::", "").strip()
     n = re.sub(r"<(\d+), \d+>$", r"<\1>", n)
-    n = re.sub(r"^(k_hist|k_fold_step1)<\d+>$", r"\1", n)
+    n = re.sub(r"^(k_hist|k_fold_step1|k_est)<.*>$", r"\1", n)
     return n.replace("k_scat4<", "k_scat<")
 
 
@@ -601,31 +602,21 @@ def summarize_l2(ctr_dir, out_dir, command, workload="rmat20"):
         fo.write("\n".join(lines) + "\n")
 
 
-def random_gather_ceiling(table_bytes, n_idx=1 << 26, reps=5):
-    """Random 8-byte gathers per second on this GPU (torch.index_select over
-    a table of `table_bytes` with uniformly random indices): the ceiling for
-    a kernel bound by random line accesses.  Each gather is one L2 request
-    and, for tables far above the L2s, almost always one miss."""
+def line_rate_ceiling(tc, table_bytes=1 << 30, n=1 << 24):
+    """Random 128-byte line reads per second that this GPU serves from a
+    table far above its caches (hand-written probe kernel, tc_probe_line_rate):
+    one, two and four independent lines per thread and a chain of four
+    dependent ones.  The largest is the ceiling of a kernel bound by random
+    line reads."""
     import torch
-    n = table_bytes // 8
-    table = torch.arange(n, dtype=torch.int64, device="cuda")
-    g = torch.Generator(device="cuda")
-    g.manual_seed(7)
-    idx = torch.randint(0, n, (n_idx,), device="cuda", generator=g)
-    out = torch.empty(n_idx, dtype=torch.int64, device="cuda")
-    torch.index_select(table, 0, idx, out=out)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        torch.index_select(table, 0, idx, out=out)
-    e1.record()
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3 / reps
-    ok = bool(torch.equal(out, idx))
-    del table, idx, out
-    return {"table_bytes": table_bytes, "gathers": n_idx, "ms": round(sec * 1e3, 3),
-            "G_per_s": round(n_idx / sec / 1e9, 2), "checked": ok}
+    table = torch.zeros(table_bytes // 4, dtype=torch.int32, device="cuda")
+    shapes = [(1, False), (2, False), (4, False), (4, True)]
+    rates = {f"{p}{'_dependent' if d else ''}": round(
+        tc.tc_probe_line_rate(table, n, p, d, reps=10) / 1e9, 2) for p, d in shapes}
+    del table
+    torch.cuda.empty_cache()
+    return {"table_bytes": table_bytes, "threads": n, "G_lines_per_s": rates,
+            "ceiling_G_lines_per_s": max(rates.values())}
 
 
 def served_comparison(tc, inputs, nstreams=1024, ngraphs=64, r=1 << 16,
@@ -667,7 +658,8 @@ def served_comparison(tc, inputs, nstreams=1024, ngraphs=64, r=1 << 16,
         lat = np.array(lat) * 1e3
         return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "value": rw / el, "elapsed_s": el, "slots": srv.slots,
-                "device_bytes": srv.device_bytes()}, res
+                "device_bytes": srv.device_bytes(), "steps": srv.steps,
+                "fused_steps": srv.fused_steps}, res
 
     log("[bench]   capacity run")
     run(0.0, budget, 1)
@@ -685,12 +677,26 @@ def served_comparison(tc, inputs, nstreams=1024, ngraphs=64, r=1 << 16,
         d, res = run(rate, budget, 2)
         d["load"] = f
         out["loads"].append(d)
+    # the same capacity and first-load runs with the fused small-chunk step
+    # switched off (every step then takes the chain of kernels)
+    log("[bench]   without the fused step")
+    h = server(budget, max_step_edges).bank.h
+    tun = tc.tc_multi_get_tuning(h)
+    tc.tc_multi_set_tuning(h, dict(tun, fused_edges=0))
+    run(0.0, budget, 1)
+    cap0, res0 = run(0.0, budget, 1)
+    d0, _ = run(loads[0] * capacity / (r * mean_chunk), budget, 2)
+    tc.tc_multi_set_tuning(h, tun)
+    out["without_fused_step"] = {"capacity": cap0["value"], "load": loads[0],
+                                 "p50_ms": d0["p50_ms"], "p99_ms": d0["p99_ms"],
+                                 "steps": d0["steps"]}
     log(f"[bench]   tight budget: {tight_budget} bytes")
     run(0.0, tight_budget, 1, tight_step_edges)  # warm-up of this server
     d, res_t = run(0.5 * capacity / (r * mean_chunk), tight_budget, 3, tight_step_edges)
     d["load"], d["budget_bytes"], d["max_step_edges"] = 0.5, tight_budget, tight_step_edges
     out["tight_budget"] = d
-    same = all((res_cap[s].S, res_cap[s].m) == (res_t[s].S, res_t[s].m) for s in range(nstreams))
+    same = all((res_cap[s].S, res_cap[s].m) == (res_t[s].S, res_t[s].m) == (res0[s].S, res0[s].m)
+               for s in range(nstreams))
     for srv in servers.values():
         srv.close()
     servers.clear()
@@ -980,22 +986,21 @@ def main():
                     step_bytes / (dt / steps) / 1e9 / HBM_PEAK_GBS, 4)
         except (OSError, KeyError, ValueError):
             pass
-        # random-access view of the dominant kernel: its measured L2 misses
-        # per second against the random-gather ceiling of this GPU (a table
-        # the size of the memory-side cache, and one far above it)
+        # random-line view of the dominant kernel: the lines it reads per
+        # second (rocprofv3 FETCH_SIZE counts 64 bytes per line request)
+        # against the random-line ceiling of this GPU
         try:
-            with open(os.path.join(ROOT, "profiles", f"l2_hits_{args.workload}.json")) as f:
-                l2 = json.load(f)
-            if (l2["kernel_source_sha256_16"] == kernel_source_hash()
-                    and dom in l2["per_kernel"]):
-                miss = l2["per_kernel"][dom]["misses"]
-                rate = miss / (avg_ms * 1e-3) / 1e9
-                ceil_mall = random_gather_ceiling(128 << 20)
-                ceil_hbm = random_gather_ceiling(1 << 30)
-                roofline["random_access"] = {
-                    "l2_misses_per_launch": miss, "G_misses_per_s": round(rate, 2),
-                    "gather_ceiling_128MB": ceil_mall, "gather_ceiling_1GB": ceil_hbm,
-                    "ratio_to_torch_gather_128MB": round(rate / ceil_mall["G_per_s"], 3)}
+            with open(traffic_json(args.workload)) as f:
+                rec = json.load(f)
+            if rec["kernel_source_sha256_16"] == kernel_source_hash():
+                lines = rec["per_kernel"][dom]["fetch_kib"] * 1024 / 64
+                rate = lines / (avg_ms * 1e-3) / 1e9
+                ceil = line_rate_ceiling(tc)
+                roofline["random_lines"] = {
+                    "kernel": dom, "lines_per_launch": round(lines),
+                    "lines_per_estimator": round(lines / r, 3),
+                    "G_lines_per_s": round(rate, 2), "probe": ceil,
+                    "frac_of_ceiling": round(rate / ceil["ceiling_G_lines_per_s"], 3)}
         except (OSError, KeyError, ValueError):
             pass
         step_alg = sum(alg_bytes(k_, w, r, nontrivial) for k_ in per_kernel)

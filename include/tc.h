@@ -360,6 +360,24 @@ int tc_multi_kernel_times(tc_multi *s, double *ms, uint64_t *steps);
 int tc_num_kernels(void);
 const char *tc_kernel_name(int k);
 
+/* ---- diagnostics: random cache-line read rate ---------------------------
+ * Not part of the method: measures how many random cache-line reads per
+ * second the device serves, the ceiling of a kernel whose time goes to
+ * independent random line reads (Step 2's directory, inverse-index, arc and
+ * edge lookups, Sec. 4.3).  table: DEVICE buffer of table_bytes (a multiple
+ * of 128; only read, contents arbitrary); sink: DEVICE uint32_t[n], written
+ * (caller-owned).  n threads each read per_thread (1..8) words, each the
+ * first word of a 128-byte line of the table chosen by a counter-based
+ * hash; dependent = 1 makes each address depend on the word read before.
+ * The kernel runs once untimed, then reps times between two events on
+ * `stream`; *lines_per_s (HOST) gets n * per_thread * reps / elapsed.
+ * Blocking.  TC_EINVAL for NULL pointers, table_bytes 0 or not a multiple
+ * of 128, n == 0, per_thread outside 1..8 or reps == 0; TC_EHIP if a HIP
+ * call fails. */
+int tc_probe_line_rate(const void *table, uint64_t table_bytes, uint32_t n,
+                       uint32_t per_thread, uint32_t dependent, uint32_t reps,
+                       uint32_t *sink, double *lines_per_s, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

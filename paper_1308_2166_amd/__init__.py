@@ -84,6 +84,8 @@ def lib():
         "tc_process_batch_naive": ([vp, vp, u32, vp], i32),
         "tc_process_batch_noalloc": ([vp, vp, u32, vp], i32),
         "tc_parse_edges": ([vp, u64, vp, u64, P64, vp], i32),
+        "tc_probe_line_rate": ([vp, u64, u32, u32, u32, u32, vp,
+                                ctypes.POINTER(ctypes.c_double), vp], i32),
         "tc_set_vertex_bound": ([vp, u64], i32),
         "tc_estimate_mom": ([vp, u32, ctypes.POINTER(ctypes.c_double), P64], i32),
         "tc_multi_estimate_mom": ([vp, u32, u32, ctypes.POINTER(ctypes.c_double), P64], i32),
@@ -137,6 +139,7 @@ EXPORTS = ("tc_create", "tc_process_batch", "tc_process_stream", "tc_estimate", 
            "tc_multi_graph_reserve", "tc_multi_assign", "tc_set_vertex_bound",
            "tc_multi_set_vertex_bound", "tc_estimate_mom", "tc_multi_estimate_mom",
            "tc_estimators_needed", "tc_process_batch_naive", "tc_parse_edges",
+           "tc_probe_line_rate",
            "tc_process_batch_noalloc", "tc_process_host_stream", "tc_bank_bytes",
            "tc_step_bytes", "tc_device_bytes", "tc_multi_device_bytes",
            "tc_step_bytes_max", "tc_multi_reserve_max", "tc_set_tuning", "tc_get_tuning",
@@ -215,6 +218,22 @@ def tc_parse_edges(text: torch.Tensor, max_edges: int | None = None, stream=None
     _check(lib().tc_parse_edges(text.data_ptr() if n else None, n, out.data_ptr(), max_edges,
                                 ctypes.byref(cnt), _stream_handle(stream)))
     return out[:cnt.value]
+
+
+def tc_probe_line_rate(table: torch.Tensor, n: int, per_thread: int = 1,
+                       dependent: bool = False, reps: int = 10, stream=None) -> float:
+    """Random 128-byte line reads per second from `table` (a CUDA tensor
+    whose byte size is a multiple of 128): a diagnostic of the device, not
+    part of the method."""
+    if not isinstance(table, torch.Tensor) or not table.is_cuda or not table.is_contiguous():
+        raise TypeError("table must be a contiguous CUDA tensor")
+    nbytes = table.numel() * table.element_size()
+    sink = torch.empty(max(n, 1), dtype=torch.int32, device=table.device)
+    rate = ctypes.c_double()
+    _check(lib().tc_probe_line_rate(table.data_ptr(), nbytes, n, per_thread, int(dependent),
+                                    reps, sink.data_ptr(), ctypes.byref(rate),
+                                    _stream_handle(stream)))
+    return rate.value
 
 
 def tc_process_stream(state: int, edges, w: int, stream=None) -> None:

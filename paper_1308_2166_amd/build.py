@@ -8,7 +8,7 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _CSRC = os.path.join(_HERE, "csrc")
 LIB = os.path.join(_HERE, "libtc.so")
-SOURCES = ["tc_kernels.hip", "tc_api.hip", "tc_parse.hip"]
+SOURCES = ["tc_kernels.hip", "tc_api.hip", "tc_parse.hip", "tc_probe.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

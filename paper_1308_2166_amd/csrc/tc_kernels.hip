@@ -132,6 +132,16 @@ __device__ __forceinline__ SegDesc seg_desc(const StepArgs& a, uint32_t s) {
   return a.nseg == 1 ? a.seg0 : a.segs[s];
 }
 
+// Kernels with one thread per estimator index the descriptor per thread,
+// which the compiler turns into vector loads through a pointer for both
+// cases; their single-segment builds (kOne) take the descriptor straight
+// from the kernel arguments instead (scalar loads issued at the start).
+template <bool kOne>
+__device__ __forceinline__ SegDesc est_seg_desc(const StepArgs& a, uint32_t s) {
+  if constexpr (kOne) return a.seg0;
+  return a.segs[s];
+}
+
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
@@ -259,23 +269,30 @@ __global__ __launch_bounds__(kBlock) void k_hist(StepArgs a) {
   // issued before the first is used
   constexpr int kRounds = kHistTiles * kTile / (4 * kBlock);
   uint4 xs[kRounds];
+  if (vec && abase + kHistTiles * kTile <= aend) {
+    // a whole aligned tile: no conditions, so all loads are in flight at once
+    const uint4* e4 = reinterpret_cast<const uint4*>(S.edges + abase);
 #pragma unroll
-  for (int it = 0; it < kRounds; ++it) {
-    const uint32_t i = abase + 4 * tid + it * 4 * kBlock;
-    uint4 x = make_uint4(0, 0, 0, 0);
-    const bool full = i + 4 <= aend;
-    if (full && vec) {
-      x = *reinterpret_cast<const uint4*>(S.edges + i);
-    } else if (full) {
-      const uint2 e0 = *reinterpret_cast<const uint2*>(S.edges + i);
-      const uint2 e1 = *reinterpret_cast<const uint2*>(S.edges + i + 2);
-      x = make_uint4(e0.x, e0.y, e1.x, e1.y);
-    } else if (i < aend) {  // ragged tail: i is even, so i + 1 < aend
-      const uint2 e0 = *reinterpret_cast<const uint2*>(S.edges + i);
-      x.x = e0.x;
-      x.y = e0.y;
+    for (int it = 0; it < kRounds; ++it) xs[it] = e4[tid + it * kBlock];
+  } else {
+#pragma unroll
+    for (int it = 0; it < kRounds; ++it) {
+      const uint32_t i = abase + 4 * tid + it * 4 * kBlock;
+      uint4 x = make_uint4(0, 0, 0, 0);
+      const bool full = i + 4 <= aend;
+      if (full && vec) {
+        x = *reinterpret_cast<const uint4*>(S.edges + i);
+      } else if (full) {
+        const uint2 e0 = *reinterpret_cast<const uint2*>(S.edges + i);
+        const uint2 e1 = *reinterpret_cast<const uint2*>(S.edges + i + 2);
+        x = make_uint4(e0.x, e0.y, e1.x, e1.y);
+      } else if (i < aend) {  // ragged tail: i is even, so i + 1 < aend
+        const uint2 e0 = *reinterpret_cast<const uint2*>(S.edges + i);
+        x.x = e0.x;
+        x.y = e0.y;
+      }
+      xs[it] = x;
     }
-    xs[it] = x;
   }
   // clear the need bytes (Step 1 marks them next) while the loads above
   // are in flight
@@ -814,11 +831,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 // k_step1: Step 1 (Sec. 4.2) draws for every estimator; the replacement
 // index goes to j1[] and its batch position is marked as needed
 // ---------------------------------------------------------------------------
+template <bool kOne>
 __device__ void step1_block(const StepArgs& a, uint32_t blk) {
   const uint64_t gid = (uint64_t)blk * kBlock + threadIdx.x;
   if (gid >= a.nest) return;
-  const uint32_t sidx = seg_of_est(a, gid);
-  const SegDesc S = seg_desc(a, sidx);
+  const uint32_t sidx = kOne ? 0u : seg_of_est(a, gid);
+  const SegDesc S = est_seg_desc<kOne>(a, sidx);
   const uint32_t i = (uint32_t)(gid - S.gest_off);
   const uint64_t kb = mix64(mix64(S.key0 ^ (uint64_t)i) ^ S.batch);
   // replace f1 with probability w / (m + w): x uniform on [0, m + w)
@@ -836,11 +854,11 @@ __device__ void step1_block(const StepArgs& a, uint32_t blk) {
 
 // one launch for two independent jobs: blocks [0, nchunk) fold the k_hist
 // counts, the rest run Step 1
-template <int D>
+template <int D, bool kOne>
 __global__ __launch_bounds__(kBlock) void k_fold_step1(StepArgs a) {
   const uint32_t nfold = a.nchunk * (uint32_t)Rdx<D>::kPer;
   if (blockIdx.x < nfold) fold_chunk<D>(a, blockIdx.x);
-  else step1_block(a, blockIdx.x - nfold);
+  else step1_block<kOne>(a, blockIdx.x - nfold);
 }
 
 // ---------------------------------------------------------------------------
@@ -1027,12 +1045,13 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
 // ---------------------------------------------------------------------------
 // k_est: Steps 1 and 2 per estimator, Step-3 query posted
 // ---------------------------------------------------------------------------
+template <bool kOne>
 __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (gid >= a.nest) return;
   if (*a.err & kErrFatal) return;
-  const uint32_t sidx = seg_of_est(a, gid);
-  const SegDesc S = seg_desc(a, sidx);
+  const uint32_t sidx = kOne ? 0u : seg_of_est(a, gid);
+  const SegDesc S = est_seg_desc<kOne>(a, sidx);
   const SegWork* wk = a.work + sidx;
   const uint32_t i = (uint32_t)(gid - S.gest_off);  // index within the bank
   const uint64_t e = S.est_off + i;
@@ -1188,45 +1207,64 @@ __device__ __forceinline__ uint32_t pblock_excl_scan(uint32_t v, uint32_t* s_tmp
   return off + x - v;
 }
 
+// Global (not generic) view of a pointer: its loads are global loads, so
+// waiting for them never waits for LDS traffic, nor LDS waits for them.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 // Up to 2^ptile_log2 elements of one side of a partition tile: edges of W
-// (side 0) or estimators (side 1, waiting ones only).  f(h, id, valid) is
-// called by every thread for each of its elements, in rounds of kPRound
-// loads issued together; h = mix64 of the (closing) edge, id its batch
-// position or state index.  Every lane of a wave makes the same calls.
+// (side 0) or estimators (side 1, waiting ones only), in rounds of kPRound
+// elements per thread whose loads are issued together.  f(h, id, valid) is
+// called by every thread for each of its elements; h = mix64 of the
+// (closing) edge, id its batch position or state index.  Every lane of a
+// wave makes the same calls.
 constexpr uint32_t kPRound = 8;
 
-template <class F>
-__device__ __forceinline__ void for_tile(const StepArgs& a, const SegDesc& S, uint32_t t,
-                                         F&& f) {
+struct TileSpan {
+  uint32_t lo, hi;  // element range of the side
+  bool edge;        // side 0
+};
+struct TileRound {
+  uint64_t v[kPRound];  // an edge (x | y << 32) or a closing-edge code
+};
+
+__device__ __forceinline__ TileSpan tile_span(const SegDesc& S, uint32_t t) {
+  const bool edge = t < S.netile;
+  const uint32_t lo = (edge ? t : t - S.netile) << S.ptile_log2;
+  return {lo, min(lo + (1u << S.ptile_log2), edge ? S.w : S.r), edge};
+}
+
+// the round at element b (clamped loads past the end are never used)
+__device__ __forceinline__ void tile_load(const StepArgs& a, const SegDesc& S,
+                                          const TileSpan& sp, uint32_t b, TileRound& r) {
   const int tid = threadIdx.x;
-  if (t < S.netile) {
-    const uint2* W = reinterpret_cast<const uint2*>(S.edges);
-    const uint32_t j0 = t << S.ptile_log2, j1 = min(j0 + (1u << S.ptile_log2), S.w);
-    for (uint32_t b = j0; b < j1; b += kPRound * kPThreads) {
-      uint2 ed[kPRound];
+  const auto* src = sp.edge ? as_global(reinterpret_cast<const uint64_t*>(S.edges))
+                            : as_global(a.qq + S.est_off);
 #pragma unroll
-      for (uint32_t k = 0; k < kPRound; ++k)
-        ed[k] = W[min(b + k * kPThreads + tid, j1 - 1)];
+  for (uint32_t k = 0; k < kPRound; ++k) r.v[k] = src[min(b + k * kPThreads + tid, sp.hi - 1)];
+}
+
+// the whole side: `cur` holds its first round (the caller issues those loads
+// early, before its own set-up); each later round's loads are issued before
+// the round before it is processed
+template <class F>
+__device__ __forceinline__ void for_tile(const StepArgs& a, const SegDesc& S, const TileSpan& sp,
+                                         TileRound& cur, F&& f) {
+  const int tid = threadIdx.x;
+  for (uint32_t b = sp.lo; b < sp.hi; b += kPRound * kPThreads) {
+    const uint32_t bn = b + kPRound * kPThreads;
+    TileRound nxt;
+    if (bn < sp.hi) tile_load(a, S, sp, bn, nxt);
 #pragma unroll
-      for (uint32_t k = 0; k < kPRound; ++k) {
-        const uint32_t j = b + k * kPThreads + tid;
-        f(mix64(canon(ed[k].x, ed[k].y)), j, j < j1);
-      }
+    for (uint32_t k = 0; k < kPRound; ++k) {
+      const uint32_t j = b + k * kPThreads + tid;
+      const uint64_t v = cur.v[k];
+      if (sp.edge) f(mix64(canon((uint32_t)v, (uint32_t)(v >> 32))), j, j < sp.hi);
+      else f(mix64(v), (uint32_t)S.est_off + j, j < sp.hi && v != kEmpty);
     }
-  } else {
-    const uint32_t i0 = (t - S.netile) << S.ptile_log2;
-    const uint32_t i1 = min(i0 + (1u << S.ptile_log2), S.r);
-    const uint64_t* qq = a.qq + S.est_off;
-    for (uint32_t b = i0; b < i1; b += kPRound * kPThreads) {
-      uint64_t q[kPRound];
-#pragma unroll
-      for (uint32_t k = 0; k < kPRound; ++k) q[k] = qq[min(b + k * kPThreads + tid, i1 - 1)];
-#pragma unroll
-      for (uint32_t k = 0; k < kPRound; ++k) {
-        const uint32_t i = b + k * kPThreads + tid;
-        f(mix64(q[k]), (uint32_t)S.est_off + i, i < i1 && q[k] != kEmpty);
-      }
-    }
+    if (bn < sp.hi) cur = nxt;
   }
 }
 
@@ -1268,8 +1306,11 @@ __global__ __launch_bounds__(kPThreads) void k_pcnt(StepArgs a) {
   if (*a.err & kErrFatal) return;
   const SegDesc S = seg_desc(a, uniform(s_seg));
   const uint32_t P = 1u << S.pbits, t = blk - S.ptile_off;
+  const TileSpan sp = tile_span(S, t);
+  TileRound cur;
+  tile_load(a, S, sp, sp.lo, cur);
   const bool agg = S.pbits <= kAggBits;
-  for_tile(a, S, t, [&](uint64_t h, uint32_t, bool valid) {
+  for_tile(a, S, sp, cur, [&](uint64_t h, uint32_t, bool valid) {
     const uint32_t p = part_of(h, S.pbits);
     if (agg) {
       const uint64_t mm = match_lanes(p, valid, S.pbits);
@@ -1364,6 +1405,10 @@ __global__ __launch_bounds__(kPThreads) void k_pscat(StepArgs a) {
   if (*a.err & kErrFatal) return;
   const SegDesc S = seg_desc(a, uniform(s_seg));
   const uint32_t P = 1u << S.pbits, t = blk - S.ptile_off;
+  // the tile's first round of elements is in flight during the set-up
+  const TileSpan sp = tile_span(S, t);
+  TileRound cur;
+  tile_load(a, S, sp, sp.lo, cur);
   const uint32_t side = t < S.netile ? 0u : 1u;
   const bool first = t == 0 || t == S.netile;
   const bool last = t + 1 == S.netile || t + 1 == S.netile + S.nqtile;
@@ -1405,7 +1450,7 @@ __global__ __launch_bounds__(kPThreads) void k_pscat(StepArgs a) {
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) lo[k] = kPer * tid + k < P ? s_loc[kPer * tid + k] : 0u;
   const bool agg = S.pbits <= kAggBits;
-  for_tile(a, S, t, [&](uint64_t h, uint32_t id, bool valid) {
+  for_tile(a, S, sp, cur, [&](uint64_t h, uint32_t id, bool valid) {
     const uint32_t p = part_of(h, S.pbits);
     uint32_t slot;
     if (agg) {
@@ -1438,14 +1483,25 @@ __global__ __launch_bounds__(kPThreads) void k_pscat(StepArgs a) {
 // indexed by the low bits of the record's high word, and the slice's edges
 // probed against it, kJoinRound loads in flight per thread.  A record whose
 // high word equals the edge's closes its estimator iff the edge is the
-// estimator's closing edge and comes at or after its limit.  Also resets
-// the per-segment work area (the step's last kernel).
+// estimator's closing edge and comes at or after its limit.  Most edges
+// match no record: a bitmap of the records' keys (one LDS read) turns them
+// away before the table, whose probe chains (the wave runs as long as its
+// longest) are the join's critical path.  Also resets the per-segment work
+// area (the step's last kernel).
 constexpr int kJoinThreads = 512;
 constexpr uint32_t kJoinRound = 8;
+constexpr uint32_t kQPer = kJoinQ / kJoinThreads;  // records per thread and round
+static_assert(kQPer * kJoinThreads == kJoinQ, "a round's records are whole loads");
 constexpr uint64_t kFreeRec = ~0ull;  // no record: ids stay below 2^31
+constexpr uint32_t kJoinBitsLog2 = 16;  // key bitmap bits (8 KB)
+
+__device__ __forceinline__ uint32_t join_bit(uint32_t f) {
+  return f & ((1u << kJoinBitsLog2) - 1u);
+}
 
 __global__ __launch_bounds__(kJoinThreads) void k_pjoin(StepArgs a) {
   __shared__ uint64_t s_tab[kJoinSlots];
+  __shared__ uint32_t s_bits[(1u << kJoinBitsLog2) / 32];
   __shared__ uint32_t s_seg;
   const int tid = threadIdx.x;
   if (tid == 0) s_seg = seg_of_block<&SegDesc::jblk_off>(a, blockIdx.x);
@@ -1458,52 +1514,75 @@ __global__ __launch_bounds__(kJoinThreads) void k_pjoin(StepArgs a) {
     const uint32_t es = a.pstart[g2], ec = a.ptot[g2];
     const uint32_t e_lo = es + (uint32_t)((uint64_t)ec * sl / S.jslices);
     const uint32_t e_hi = es + (uint32_t)((uint64_t)ec * (sl + 1) / S.jslices);
-    const uint64_t* qrec = a.qrec + S.gest_off;
-    const uint64_t* erec = a.erec + S.arc_off / 2;
-    const uint2* W = reinterpret_cast<const uint2*>(S.edges);
+    const auto* qrec = as_global(a.qrec + S.gest_off);
+    const auto* erec = as_global(a.erec + S.arc_off / 2);
+    const auto* W = as_global(reinterpret_cast<const uint64_t*>(S.edges));
+    constexpr uint32_t kStride = kJoinRound * kJoinThreads;
     for (uint32_t r0 = 0; e_hi > e_lo && r0 < qc; r0 += kJoinQ) {
       const uint32_t nq = min(kJoinQ, qc - r0);
+      // the round's records and the slice's first edges are loaded before
+      // the table is cleared, so their latency overlaps the clear
+      uint64_t rec[kQPer], er[kJoinRound];
+#pragma unroll
+      for (uint32_t k = 0; k < kQPer; ++k)
+        rec[k] = qrec[qs + r0 + min(k * kJoinThreads + tid, nq - 1)];
+#pragma unroll
+      for (uint32_t k = 0; k < kJoinRound; ++k)
+        er[k] = erec[min(e_lo + k * kJoinThreads + tid, e_hi - 1)];
       // a table of four times the round's records (load <= 1/4; at most
-      // kJoinSlots, so a full round of kJoinQ loads it to 1/2): the probes'
-      // chains of LDS reads are the join's critical path
+      // kJoinSlots, so a full round of kJoinQ loads it to 1/2)
       const uint32_t cl = nq > 1 ? 32u - (uint32_t)__clz(nq - 1) : 0u;
       const uint32_t mask = min(kJoinSlots, max(512u, 4u << cl)) - 1u;
       for (uint32_t i = tid; i <= mask; i += kJoinThreads) s_tab[i] = kFreeRec;
+      for (uint32_t i = tid; i < (1u << kJoinBitsLog2) / 32; i += kJoinThreads) s_bits[i] = 0;
       __syncthreads();
-      for (uint32_t i0 = 0; i0 < nq; i0 += kJoinRound * kJoinThreads) {
-        uint64_t rec[kJoinRound];
 #pragma unroll
-        for (uint32_t k = 0; k < kJoinRound; ++k)
-          rec[k] = qrec[qs + r0 + min(i0 + k * kJoinThreads + tid, nq - 1)];
-#pragma unroll
-        for (uint32_t k = 0; k < kJoinRound; ++k) {
-          if (i0 + k * kJoinThreads + tid >= nq) continue;
-          uint32_t slot = (uint32_t)(rec[k] >> 32) & mask;
-          while (atomicCAS(reinterpret_cast<unsigned long long*>(&s_tab[slot]),
-                           (unsigned long long)kFreeRec,
-                           (unsigned long long)rec[k]) != kFreeRec)
-            slot = (slot + 1) & mask;
-        }
+      for (uint32_t k = 0; k < kQPer; ++k) {
+        if (k * kJoinThreads + tid >= nq) continue;
+        const uint32_t f = (uint32_t)(rec[k] >> 32);
+        atomicOr(&s_bits[join_bit(f) >> 5], 1u << (join_bit(f) & 31u));
+        uint32_t slot = f & mask;
+        while (atomicCAS(reinterpret_cast<unsigned long long*>(&s_tab[slot]),
+                         (unsigned long long)kFreeRec,
+                         (unsigned long long)rec[k]) != kFreeRec)
+          slot = (slot + 1) & mask;
       }
       __syncthreads();
-      for (uint32_t j0 = e_lo; j0 < e_hi; j0 += kJoinRound * kJoinThreads) {
-        uint64_t er[kJoinRound];
+      for (uint32_t j0 = e_lo; j0 < e_hi; j0 += kStride) {
+        // the next edges are in flight while these probe the table
+        const uint32_t j1 = j0 + kStride;
+        uint64_t nx[kJoinRound];
+        if (j1 < e_hi) {
 #pragma unroll
-        for (uint32_t k = 0; k < kJoinRound; ++k)
-          er[k] = erec[min(j0 + k * kJoinThreads + tid, e_hi - 1)];
+          for (uint32_t k = 0; k < kJoinRound; ++k)
+            nx[k] = erec[min(j1 + k * kJoinThreads + tid, e_hi - 1)];
+        }
+        // the filter for all of the thread's edges at once, then the table
+        // for those that pass
+        uint32_t pass = 0;
 #pragma unroll
         for (uint32_t k = 0; k < kJoinRound; ++k) {
-          if (j0 + k * kJoinThreads + tid >= e_hi) continue;
+          const uint32_t f = (uint32_t)(er[k] >> 32);
+          const bool in = j0 + k * kJoinThreads + tid < e_hi;
+          pass |= (in && (s_bits[join_bit(f) >> 5] >> (join_bit(f) & 31u)) & 1u) ? 1u << k : 0u;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kJoinRound; ++k) {
+          if (!(pass >> k & 1u)) continue;
           const uint32_t f = (uint32_t)(er[k] >> 32), pos = (uint32_t)er[k];
           for (uint32_t slot = f & mask;; slot = (slot + 1) & mask) {
             const uint64_t qr = s_tab[slot];
             if (qr == kFreeRec) break;
             if ((uint32_t)(qr >> 32) != f) continue;
             const uint32_t e = (uint32_t)qr;
-            const uint2 ed = W[pos];
-            if (canon(ed.x, ed.y) == a.qq[e] && pos >= a.qthr[e])
+            const uint64_t ed = W[pos];
+            if (canon((uint32_t)ed, (uint32_t)(ed >> 32)) == a.qq[e] && pos >= a.qthr[e])
               atomicOr(&a.cc[e], kClosed);
           }
+        }
+        if (j1 < e_hi) {
+#pragma unroll
+          for (uint32_t k = 0; k < kJoinRound; ++k) er[k] = nx[k];
         }
       }
       __syncthreads();
@@ -1995,7 +2074,9 @@ void launch_sort(const StepArgs& a, hipStream_t st, Run& run) {
   const dim3 chunks(a.nchunk * kPer), segs(a.nseg * (Rdx<D>::kBins / 64));
   run(0, [&] { hipLaunchKernelGGL(k_hist<D>, dim3(a.nhblk), blk, 0, st, a); });
   run(1, [&] {
-    hipLaunchKernelGGL(k_fold_step1<D>, dim3(a.nchunk * kPer + a.nstep1), blk, 0, st, a);
+    const dim3 g(a.nchunk * kPer + a.nstep1);
+    if (a.nseg == 1) hipLaunchKernelGGL((k_fold_step1<D, true>), g, blk, 0, st, a);
+    else hipLaunchKernelGGL((k_fold_step1<D, false>), g, blk, 0, st, a);
   });
   if (!a.single_chunk)
     run(2, [&] { hipLaunchKernelGGL((k_cscan<0, D>), segs, blk, 0, st, a); });
@@ -2036,7 +2117,10 @@ hipError_t launch_phase(int phase, const StepArgs& a, hipStream_t st,
     }
     run(kSmallKernel - 6, [&] { hipLaunchKernelGGL(k_dir, tiles, blk, 0, st, a); });
   } else if (phase == 1) {
-    run(kSmallKernel - 5, [&] { hipLaunchKernelGGL(k_est, ests, blk, 0, st, a); });
+    run(kSmallKernel - 5, [&] {
+      if (a.nseg == 1) hipLaunchKernelGGL(k_est<true>, ests, blk, 0, st, a);
+      else hipLaunchKernelGGL(k_est<false>, ests, blk, 0, st, a);
+    });
   } else {
     const dim3 pblk(kPThreads), jblk(kJoinThreads);
     run(kSmallKernel - 4, [&] { hipLaunchKernelGGL(k_pcnt, dim3(a.nptile), pblk, 0, st, a); });

@@ -32,8 +32,8 @@ import time
 import torch
 
 from . import (MultiBank, tc_bank_bytes, tc_multi_assign, tc_multi_device_bytes,
-               tc_multi_estimate, tc_multi_reserve_max, tc_multi_set_vertex_bound,
-               tc_step_bytes_max)
+               tc_multi_estimate, tc_multi_get_tuning, tc_multi_reserve_max,
+               tc_multi_set_vertex_bound, tc_step_bytes_max)
 
 
 @dataclasses.dataclass
@@ -134,8 +134,13 @@ class Server:
 
     def run(self, arrivals, seeds, spin_s: float = 2e-5):
         """arrivals: list of Chunk sorted by time.  Returns (latencies in
-        seconds per chunk, results per stream, elapsed seconds, r*w done)."""
+        seconds per chunk, results per stream, elapsed seconds, r*w done).
+        Afterwards self.steps is the number of steps launched and
+        self.fused_steps those whose chunks all took the fused single-launch
+        step (every chunk at most the tuning's fused_edges)."""
         st = self.stream
+        fused_edges = tc_multi_get_tuning(self.bank.h)["fused_edges"]
+        self.steps = self.fused_steps = 0
         pending = collections.deque(arrivals)
         ready = collections.defaultdict(collections.deque)
         slot_of, waitlist, free = {}, collections.deque(), list(range(self.slots))[::-1]
@@ -193,6 +198,8 @@ class Server:
                     rw += self.r * w
                 if ids:
                     self.bank.process(ids, chunks, st)
+                    self.steps += 1
+                    self.fused_steps += all(int(c.shape[0]) <= fused_edges for c in chunks)
                     ev = torch.cuda.Event(enable_timing=True)
                     ev.record(st)
                     inflight.append((ev, items))

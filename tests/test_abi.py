@@ -141,3 +141,18 @@ def test_slots_for_budget_is_the_largest_fit():
         s = serve.slots_for_budget(budget, r, cap)
         assert s == 0 or serve.server_bytes(s, r, cap) <= budget
         assert serve.server_bytes(s + 1, r, cap) > budget
+
+
+def test_probe_line_rate_refuses_bad_arguments():
+    # argument checks happen before any HIP call (no GPU needed)
+    import ctypes
+    import paper_1308_2166_amd as tc
+    L = tc.lib()
+    d = ctypes.c_double()
+    dummy = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below is refused
+    for args in ((None, 128, 1, 1, 0, 1, dummy), (dummy, 100, 1, 1, 0, 1, dummy),
+                 (dummy, 0, 1, 1, 0, 1, dummy), (dummy, 128, 0, 1, 0, 1, dummy),
+                 (dummy, 128, 1, 0, 0, 1, dummy), (dummy, 128, 1, 9, 0, 1, dummy),
+                 (dummy, 128, 1, 1, 0, 0, dummy), (dummy, 128, 1, 1, 0, 1, None)):
+        assert L.tc_probe_line_rate(*args, ctypes.byref(d), None) == tc.TC_EINVAL, args
+    assert L.tc_probe_line_rate(dummy, 128, 1, 1, 0, 1, dummy, None, None) == tc.TC_EINVAL

@@ -96,6 +96,8 @@ def test_profile_names_map_to_launch_names():
     assert short("void tc::k_cscan<2, 8>(tc::StepArgs)") == "k_cscan<2>"
     assert short("tc::k_pjoin(tc::StepArgs)") == "k_pjoin"
     assert short("tc::k_est(tc::StepArgs)") == "k_est"
+    assert short("void tc::k_est<true>(tc::StepArgs)") == "k_est"
+    assert short("void tc::k_fold_step1<8, false>(tc::StepArgs)") == "k_fold_step1"
 
 
 def test_tuning_cache_round_trip(tmp_path):

@@ -1362,3 +1362,16 @@ def test_parse_errors(tc):
         assert ei.value.code == tc.TC_EINVAL
     with pytest.raises(tc.TcError):
         tc.tc_parse_edges(_dev_bytes(b"1 2\n3 4\n5 6\n"), max_edges=2)
+
+
+def test_probe_line_rate(tc):
+    # the diagnostic behind the random-line roofline: a positive, finite
+    # rate for every shape, reads only (the table is left as it was)
+    table = torch.arange(1 << 22, dtype=torch.int32, device="cuda")  # 16 MB
+    before = table.clone()
+    for per, dep in ((1, False), (2, False), (4, True), (8, False)):
+        rate = tc.tc_probe_line_rate(table, 1 << 16, per, dep, reps=2)
+        assert 1e6 < rate < 1e13, (per, dep, rate)
+    assert torch.equal(table, before)
+    with pytest.raises(tc.TcError):
+        tc.tc_probe_line_rate(table[:10], 1 << 10)  # 40 bytes: not whole lines
