@@ -1215,56 +1215,44 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(
 }
 
 // Up to 2^ptile_log2 elements of one side of a partition tile: edges of W
-// (side 0) or estimators (side 1, waiting ones only), in rounds of kPRound
-// elements per thread whose loads are issued together.  f(h, id, valid) is
-// called by every thread for each of its elements; h = mix64 of the
-// (closing) edge, id its batch position or state index.  Every lane of a
-// wave makes the same calls.
+// (side 0) or estimators (side 1, waiting ones only).  f(h, id, valid) is
+// called by every thread for each of its elements, in rounds of kPRound
+// loads issued together; h = mix64 of the (closing) edge, id its batch
+// position or state index.  Every lane of a wave makes the same calls.
 constexpr uint32_t kPRound = 8;
 
-struct TileSpan {
-  uint32_t lo, hi;  // element range of the side
-  bool edge;        // side 0
-};
-struct TileRound {
-  uint64_t v[kPRound];  // an edge (x | y << 32) or a closing-edge code
-};
-
-__device__ __forceinline__ TileSpan tile_span(const SegDesc& S, uint32_t t) {
-  const bool edge = t < S.netile;
-  const uint32_t lo = (edge ? t : t - S.netile) << S.ptile_log2;
-  return {lo, min(lo + (1u << S.ptile_log2), edge ? S.w : S.r), edge};
-}
-
-// the round at element b (clamped loads past the end are never used)
-__device__ __forceinline__ void tile_load(const StepArgs& a, const SegDesc& S,
-                                          const TileSpan& sp, uint32_t b, TileRound& r) {
-  const int tid = threadIdx.x;
-  const auto* src = sp.edge ? as_global(reinterpret_cast<const uint64_t*>(S.edges))
-                            : as_global(a.qq + S.est_off);
-#pragma unroll
-  for (uint32_t k = 0; k < kPRound; ++k) r.v[k] = src[min(b + k * kPThreads + tid, sp.hi - 1)];
-}
-
-// the whole side: `cur` holds its first round (the caller issues those loads
-// early, before its own set-up); each later round's loads are issued before
-// the round before it is processed
 template <class F>
-__device__ __forceinline__ void for_tile(const StepArgs& a, const SegDesc& S, const TileSpan& sp,
-                                         TileRound& cur, F&& f) {
+__device__ __forceinline__ void for_tile(const StepArgs& a, const SegDesc& S, uint32_t t,
+                                         F&& f) {
   const int tid = threadIdx.x;
-  for (uint32_t b = sp.lo; b < sp.hi; b += kPRound * kPThreads) {
-    const uint32_t bn = b + kPRound * kPThreads;
-    TileRound nxt;
-    if (bn < sp.hi) tile_load(a, S, sp, bn, nxt);
+  if (t < S.netile) {
+    const uint2* W = reinterpret_cast<const uint2*>(S.edges);
+    const uint32_t j0 = t << S.ptile_log2, j1 = min(j0 + (1u << S.ptile_log2), S.w);
+    for (uint32_t b = j0; b < j1; b += kPRound * kPThreads) {
+      uint2 ed[kPRound];
 #pragma unroll
-    for (uint32_t k = 0; k < kPRound; ++k) {
-      const uint32_t j = b + k * kPThreads + tid;
-      const uint64_t v = cur.v[k];
-      if (sp.edge) f(mix64(canon((uint32_t)v, (uint32_t)(v >> 32))), j, j < sp.hi);
-      else f(mix64(v), (uint32_t)S.est_off + j, j < sp.hi && v != kEmpty);
+      for (uint32_t k = 0; k < kPRound; ++k)
+        ed[k] = W[min(b + k * kPThreads + tid, j1 - 1)];
+#pragma unroll
+      for (uint32_t k = 0; k < kPRound; ++k) {
+        const uint32_t j = b + k * kPThreads + tid;
+        f(mix64(canon(ed[k].x, ed[k].y)), j, j < j1);
+      }
     }
-    if (bn < sp.hi) cur = nxt;
+  } else {
+    const uint32_t i0 = (t - S.netile) << S.ptile_log2;
+    const uint32_t i1 = min(i0 + (1u << S.ptile_log2), S.r);
+    const uint64_t* qq = a.qq + S.est_off;
+    for (uint32_t b = i0; b < i1; b += kPRound * kPThreads) {
+      uint64_t q[kPRound];
+#pragma unroll
+      for (uint32_t k = 0; k < kPRound; ++k) q[k] = qq[min(b + k * kPThreads + tid, i1 - 1)];
+#pragma unroll
+      for (uint32_t k = 0; k < kPRound; ++k) {
+        const uint32_t i = b + k * kPThreads + tid;
+        f(mix64(q[k]), (uint32_t)S.est_off + i, i < i1 && q[k] != kEmpty);
+      }
+    }
   }
 }
 
@@ -1306,11 +1294,8 @@ __global__ __launch_bounds__(kPThreads) void k_pcnt(StepArgs a) {
   if (*a.err & kErrFatal) return;
   const SegDesc S = seg_desc(a, uniform(s_seg));
   const uint32_t P = 1u << S.pbits, t = blk - S.ptile_off;
-  const TileSpan sp = tile_span(S, t);
-  TileRound cur;
-  tile_load(a, S, sp, sp.lo, cur);
   const bool agg = S.pbits <= kAggBits;
-  for_tile(a, S, sp, cur, [&](uint64_t h, uint32_t, bool valid) {
+  for_tile(a, S, t, [&](uint64_t h, uint32_t, bool valid) {
     const uint32_t p = part_of(h, S.pbits);
     if (agg) {
       const uint64_t mm = match_lanes(p, valid, S.pbits);
@@ -1405,10 +1390,6 @@ __global__ __launch_bounds__(kPThreads) void k_pscat(StepArgs a) {
   if (*a.err & kErrFatal) return;
   const SegDesc S = seg_desc(a, uniform(s_seg));
   const uint32_t P = 1u << S.pbits, t = blk - S.ptile_off;
-  // the tile's first round of elements is in flight during the set-up
-  const TileSpan sp = tile_span(S, t);
-  TileRound cur;
-  tile_load(a, S, sp, sp.lo, cur);
   const uint32_t side = t < S.netile ? 0u : 1u;
   const bool first = t == 0 || t == S.netile;
   const bool last = t + 1 == S.netile || t + 1 == S.netile + S.nqtile;
@@ -1450,7 +1431,7 @@ __global__ __launch_bounds__(kPThreads) void k_pscat(StepArgs a) {
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) lo[k] = kPer * tid + k < P ? s_loc[kPer * tid + k] : 0u;
   const bool agg = S.pbits <= kAggBits;
-  for_tile(a, S, sp, cur, [&](uint64_t h, uint32_t id, bool valid) {
+  for_tile(a, S, t, [&](uint64_t h, uint32_t id, bool valid) {
     const uint32_t p = part_of(h, S.pbits);
     uint32_t slot;
     if (agg) {
