@@ -105,11 +105,11 @@ int tc_process_batch_naive(tc_state *s, const uint32_t *edges, uint32_t w,
  * (uint32_t[2*m], 8-byte aligned) cut into ceil(m/w) consecutive batches of
  * w edges (the last one ragged), each one bulkUpdateAll in stream order.
  * The result is bit-identical to that many tc_process_batch calls on the
- * same cuts.  Inside the call, for w <= 2^20, the closing-edge check
- * (Step 3) of batch k runs on an internal stream while batch k+1 is grouped
- * on `stream` (larger batches run one after the other); the call joins that
- * stream back before it returns, so work enqueued on `stream` afterwards
- * sees every batch complete, and the call may be captured into a HIP graph.  TC_EINVAL for a NULL state, NULL edges with
+ * same cuts.  Inside the call, the closing-edge check (Step 3) of batch k
+ * runs on an internal stream while batch k+1 is grouped on `stream`; the
+ * call joins that stream back before it returns, so work enqueued on
+ * `stream` afterwards sees every batch complete, and the call may be
+ * captured into a HIP graph.  TC_EINVAL for a NULL state, NULL edges with
  * m > 0, w == 0 or w > TC_MAX_BATCH; on any error the batches before the
  * failing one stay enqueued. */
 int tc_process_stream(tc_state *s, const uint32_t *edges, uint64_t m,

@@ -954,7 +954,7 @@ struct Engine {
       }
       // Step 3 of a batch may overlap the next batch's grouping (as in
       // tc_process_stream); its last reader of the buffer is then on st2
-      const bool more = j + w < mm && w <= (1u << 20);
+      const bool more = j + w < mm;
       const uint32_t* ek = hbuf[b];
       int rc = step(1, &id, &ek, &wk, st, false, more);
       if (rc) {
@@ -1243,10 +1243,9 @@ int tc_process_stream(tc_state* s, const uint32_t* edges, uint64_t m,
   for (uint64_t j = 0; j < m; j += w) {
     const uint32_t wk = (uint32_t)std::min<uint64_t>(w, m - j);
     const uint32_t* ek = edges + 2 * j;
-    // Step 3 of a batch overlaps the grouping of the next only for batches
-    // of up to 2^20 edges: larger ones fill the device on their own, and
-    // the two phases then slow each other down more than they overlap
-    const bool more = j + w < m && w <= (1u << 20);
+    // Step 3 of a batch overlaps the grouping of the next (the join's
+    // probes are bound by LDS latency, the grouping by HBM bandwidth)
+    const bool more = j + w < m;
     int rc = s->e.step(1, &id, &ek, &wk, st, false, more);
     if (rc) {
       (void)s->e.join(st);
