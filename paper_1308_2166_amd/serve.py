@@ -148,9 +148,14 @@ class Server:
         inflight = collections.deque()
         rw = 0
         torch.cuda.synchronize()
+        # the GPU clock's origin: an event that has completed before the
+        # host clock starts, so a GPU time after it never reads as earlier
+        # than the host time of the same instant (latencies err high by the
+        # few microseconds the synchronisation takes to return, never low)
         ref = torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
         ref.record(st)
+        ref.synchronize()
+        t0 = time.perf_counter()
         while pending or inflight or waitlist or any(ready.values()):
             now = time.perf_counter() - t0
             while pending and pending[0].t <= now:

@@ -526,7 +526,14 @@ def test_served_streams_equal_their_alone_runs(tc):
     arrivals = serve.poisson_arrivals(chunks, rate_per_s=20000.0, seed=4)
     srv = serve.Server(r=r, max_step_edges=20000, slots=7)  # streams wait for slots
     lat, results, elapsed, rw = srv.run(arrivals, seeds)
+    assert 0 < srv.fused_steps < srv.steps  # chunks of 200-5000 edges: both kinds of step
+    # the same arrivals with every step on the chain of kernels
+    tun = tc.tc_multi_get_tuning(srv.bank.h)
+    tc.tc_multi_set_tuning(srv.bank.h, dict(tun, fused_edges=0))
+    _, results0, _, _ = srv.run(arrivals, seeds)
+    assert srv.fused_steps == 0
     srv.close()
+    assert {s: (x.S, x.m) for s, x in results.items()} == {s: (x.S, x.m) for s, x in results0.items()}
     assert len(lat) == sum(len(c) for c in chunks) and len(results) == nstreams
     assert min(lat) > 0
     for s in range(nstreams):
