@@ -95,6 +95,29 @@ def test_multi_tile_ragged(tc):
     run_both(tc, E, r=20000, seed=9, w=9001)
 
 
+@pytest.mark.parametrize("n,m,w", [(12000, 20000, 3000), (16000, 9000, 4000), (8190, 6000, 2049)])
+def test_dense_directory_id_windows(tc, n, m, w):
+    # ids spread over up to 4w (still the dense directory) make a tile's id
+    # range span several 4096-id windows of the offsets, with gaps of empty
+    # ids between the arcs
+    E = np_edges(inputs.gnm(n, m, seed=n + w))
+    run_both(tc, E, r=5000, seed=n, w=w)
+
+
+def test_dense_directory_far_apart_ids(tc):
+    # a few vertices at both ends of the dense id range: long runs of
+    # absent ids inside one tile, and the last tile's run up to the top
+    w = 3000
+    lo = np.arange(0, 40, dtype=np.uint32)
+    hi = np.arange(4 * w - 41, 4 * w - 1, dtype=np.uint32)
+    ids = np.concatenate([lo, hi])
+    rng = np.random.default_rng(5)
+    pairs = {(int(min(a, b)), int(max(a, b))) for a, b in rng.choice(ids, (6000, 2)) if a != b}
+    E = np.array(sorted(pairs), dtype=np.uint32)
+    E = E[rng.permutation(len(E))]
+    run_both(tc, E, r=3000, seed=11, w=w)
+
+
 def test_star_giant_segment(tc):
     hub = 7
     leaves = np.arange(8, 20008, dtype=np.uint32)
