@@ -86,8 +86,9 @@ uint64_t orc_sum(const orc_state *s);
 /* Lemma 1 averaged over the bank: (m / r) * S. */
 double orc_estimate(const orc_state *s);
 
-/* Median-of-means (Sec. 3.1, the aggregate named before Theorem 2; group
- * layout is this build's reading): the r estimators are cut into g
+/* Median-of-means (Sec. 3.1, the aggregate named before Theorem 2; the
+ * paper does not fix the group layout, this one is a reading): the r
+ * estimators are cut into g
  * contiguous groups, group k = [floor(k r / g), floor((k+1) r / g)); each
  * group's mean of Lemma 1's X is (m / size_k) * S_k with S_k the exact sum
  * of c_i * closed_i over the group; the result is the median of the g
