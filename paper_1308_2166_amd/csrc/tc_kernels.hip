@@ -1876,18 +1876,108 @@ __device__ __forceinline__ uint32_t lds_lower_bound(const uint64_t* s, uint32_t 
   return lo;
 }
 
+// Stable LSD radix sort of the n <= kSmallArcs arcs in s by their vertex
+// (the high word), 8 bits a pass over the bits of vmax, through the buffer
+// t; the result ends in s.  Wave w ranks elements [w kSmallPerWave, (w+1)
+// kSmallPerWave) in order, four rounds of 64: lanes with equal digits find
+// each other by ballots, and the lowest adds their number to the wave's
+// count of that digit with a returning LDS atomic (a wave's atomics land in
+// program order, so each returns the count of earlier equal digits).
+constexpr uint32_t kSmallArcs = 2 * kSmallW;
+constexpr int kSmallWaves = kSmallThreads / 64;
+constexpr uint32_t kSmallPerWave = kSmallArcs / kSmallWaves;
+static_assert(kSmallPerWave % 64 == 0, "whole rounds of 64 arcs per wave");
+
+__device__ void small_sort(uint64_t* s, uint64_t* t, uint32_t n, uint32_t vmax,
+                           uint32_t (*s_wh)[256], uint32_t* s_start, uint32_t* s_part) {
+  constexpr int kRounds = (int)(kSmallPerWave / 64);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const int nbits = 32 - __clz(vmax | 1u);
+  for (int sh = 0; sh < nbits; sh += 8) {
+    for (uint32_t i = tid; i < kSmallWaves * 256u; i += kSmallThreads) (&s_wh[0][0])[i] = 0;
+    __syncthreads();
+    uint64_t el[kRounds];
+    uint32_t dg[kRounds], rk[kRounds];
+#pragma unroll
+    for (int it = 0; it < kRounds; ++it) {
+      const uint32_t i = (uint32_t)wave * kSmallPerWave + it * 64 + lane;
+      const bool valid = i < n;
+      el[it] = valid ? s[i] : 0ull;
+      dg[it] = (uint32_t)(el[it] >> (32 + sh)) & 255u;
+      uint64_t mm = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t bb = __ballot((dg[it] >> b) & 1u);
+        mm &= ((dg[it] >> b) & 1u) ? bb : ~bb;
+      }
+      const uint32_t below = (uint32_t)__popcll(mm & lt);
+      uint32_t base = 0;
+      if (valid && below == 0) base = atomicAdd(&s_wh[wave][dg[it]], (uint32_t)__popcll(mm));
+      const int leader = (int)(((uint32_t)__ffsll((long long)mm) - 1u) & 63u);
+      rk[it] = valid ? __shfl(base, leader) + below : 0u;
+    }
+    __syncthreads();
+    // per digit: the waves' counts become offsets, the digits' totals an
+    // exclusive scan (threads 0..255, one digit each)
+    uint32_t tot = 0;
+    if (tid < 256) {
+#pragma unroll
+      for (int w = 0; w < kSmallWaves; ++w) {
+        const uint32_t c = s_wh[w][tid];
+        s_wh[w][tid] = tot;
+        tot += c;
+      }
+    }
+    uint32_t x = tot;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (tid < 256 && lane == 63) s_part[wave] = x;
+    __syncthreads();
+    if (tid < 256) {
+      uint32_t off = 0;
+      for (int w = 0; w < wave; ++w) off += s_part[w];
+      s_start[tid] = off + x - tot;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kRounds; ++it) {
+      const uint32_t i = (uint32_t)wave * kSmallPerWave + it * 64 + lane;
+      if (i < n) t[s_start[dg[it]] + s_wh[wave][dg[it]] + rk[it]] = el[it];
+    }
+    __syncthreads();
+    uint64_t* u = s;
+    s = t;
+    t = u;
+  }
+  // an odd number of passes left the result in the other buffer
+  if (((nbits + 7) / 8) & 1) {
+    for (uint32_t i = threadIdx.x; i < n; i += kSmallThreads) t[i] = s[i];
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
-  constexpr uint32_t kArcs = 2 * kSmallW;
+  constexpr uint32_t kArcs = kSmallArcs;
   constexpr uint32_t kTab = 2 * kSmallW;  // edge table slots (load <= 1/2)
   __shared__ uint2 s_w[kSmallW];
   __shared__ uint64_t s_arc[kArcs];
-  __shared__ uint64_t s_ek[kTab];  // canonical edge, kEmpty = free
+  __shared__ uint64_t s_ek[kTab];  // canonical edge, kEmpty = free (the sort's
+                                   // second buffer before that)
   __shared__ uint32_t s_ep[kTab];  // 1 + its latest position
-  __shared__ uint32_t s_seg, s_bad;
+  __shared__ uint32_t s_wh[kSmallWaves][256];
+  __shared__ uint32_t s_start[256];
+  __shared__ uint32_t s_part[4];
+  __shared__ uint32_t s_seg, s_bad, s_vmax;
+  static_assert(kTab == kArcs, "the edge table's keys double as the sort buffer");
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_seg = small_seg(a, blockIdx.x);
     s_bad = 0;
+    s_vmax = 0;
   }
   __syncthreads();
   if (*a.err & kErrFatal) return;
@@ -1904,11 +1994,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     s_arc[2 * j] = ((uint64_t)ed.x << 32) | (2u * j);
     s_arc[2 * j + 1] = ((uint64_t)ed.y << 32) | (2u * j + 1u);
   }
-  for (uint32_t i = n + tid; i < kArcs; i += kSmallThreads) s_arc[i] = ~0ull;
-  for (uint32_t i = tid; i < kTab; i += kSmallThreads) {
-    s_ek[i] = kEmpty;
-    s_ep[i] = 0;
-  }
+  atomicMax(&s_vmax, vmax);
   if (loop) {
     atomicOr(a.err, kErrSelfLoop);
     s_bad = 1;
@@ -1919,27 +2005,13 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
   }
   __syncthreads();
   if (s_bad) return;
-  // bitonic sort of the first np slots of s_arc (np: the arc count rounded
-  // up to a power of two; the ~0 padding after them is in order already).
-  // Strides are powers of two: shifts, not divisions.  (A variant holding
-  // four slots per thread, with shuffles for strides below 256, was no
-  // faster: 53 against 57 us for 2048 edges, 35 against 26 for 512.)
-  uint32_t np = 2;
-  while (np < n) np <<= 1;
-  for (uint32_t k = 2; k <= np; k <<= 1) {
-    for (uint32_t jj = k >> 1, lj = 31u - (uint32_t)__clz(jj); jj > 0; jj >>= 1, --lj) {
-      for (uint32_t i = tid; i < np / 2; i += kSmallThreads) {
-        const uint32_t lo = ((i >> lj) << (lj + 1)) + (i & (jj - 1)), hi = lo + jj;
-        const bool up = (lo & k) == 0;
-        const uint64_t x = s_arc[lo], y = s_arc[hi];
-        if ((x > y) == up) {
-          s_arc[lo] = y;
-          s_arc[hi] = x;
-        }
-      }
-      __syncthreads();
-    }
+  // the arcs by vertex, stably (arc ids ascend within a vertex, as built)
+  small_sort(s_arc, s_ek, n, s_vmax, s_wh, s_start, s_part);
+  for (uint32_t i = tid; i < kTab; i += kSmallThreads) {
+    s_ek[i] = kEmpty;
+    s_ep[i] = 0;
   }
+  __syncthreads();
   // the chunk's edges and their latest positions (1 + position, 0 = none)
   constexpr uint32_t kTabMask = kTab - 1;
   for (uint32_t j = tid; j < w; j += kSmallThreads) {
