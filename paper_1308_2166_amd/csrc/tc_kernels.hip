@@ -142,6 +142,23 @@ __device__ __forceinline__ SegDesc est_seg_desc(const StepArgs& a, uint32_t s) {
   return a.segs[s];
 }
 
+// Segment of estimator thread gid in a block of consecutive estimator
+// threads starting at gid0 (every thread of the block calls it): thread 0
+// searches gid0's segment and the start of the one after it, and only a
+// thread at or past that start (a block that crosses a segment's end)
+// searches for itself.
+__device__ __forceinline__ uint32_t block_seg_of_est(const StepArgs& a, uint64_t gid0,
+                                                     uint64_t gid, uint32_t* s_seg,
+                                                     uint64_t* s_next) {
+  if (threadIdx.x == 0) {
+    const uint32_t s = seg_of_est(a, gid0);
+    *s_seg = s;
+    *s_next = s + 1 < a.nseg ? a.segs[s + 1].gest_off : ~0ull;
+  }
+  __syncthreads();
+  return gid < *s_next ? *s_seg : seg_of_est(a, gid);
+}
+
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
@@ -834,8 +851,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 template <bool kOne>
 __device__ void step1_block(const StepArgs& a, uint32_t blk) {
   const uint64_t gid = (uint64_t)blk * kBlock + threadIdx.x;
+  uint32_t sidx = 0;
+  if constexpr (!kOne) {
+    __shared__ uint32_t s_seg;
+    __shared__ uint64_t s_next;
+    sidx = block_seg_of_est(a, (uint64_t)blk * kBlock, gid, &s_seg, &s_next);
+  }
   if (gid >= a.nest) return;
-  const uint32_t sidx = kOne ? 0u : seg_of_est(a, gid);
   const SegDesc S = est_seg_desc<kOne>(a, sidx);
   const uint32_t i = (uint32_t)(gid - S.gest_off);
   const uint64_t kb = mix64(mix64(S.key0 ^ (uint64_t)i) ^ S.batch);
@@ -1048,9 +1070,14 @@ __global__ __launch_bounds__(kBlock) void k_dir(StepArgs a) {
 template <bool kOne>
 __global__ __launch_bounds__(kBlock) void k_est(StepArgs a) {
   const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t sidx = 0;
+  if constexpr (!kOne) {
+    __shared__ uint32_t s_seg;
+    __shared__ uint64_t s_next;
+    sidx = block_seg_of_est(a, (uint64_t)blockIdx.x * kBlock, gid, &s_seg, &s_next);
+  }
   if (gid >= a.nest) return;
   if (*a.err & kErrFatal) return;
-  const uint32_t sidx = kOne ? 0u : seg_of_est(a, gid);
   const SegDesc S = est_seg_desc<kOne>(a, sidx);
   const SegWork* wk = a.work + sidx;
   const uint32_t i = (uint32_t)(gid - S.gest_off);  // index within the bank
